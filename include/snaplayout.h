@@ -1,0 +1,262 @@
+/*
+ * snaplayout.h -- C ABI of the MI355X (gfx950) SNAP-tFDP layout library.
+ *
+ * The library lays out an undirected graph in 2D with the edge-centric
+ * negative-sampling method of SNAP-tFDP: per epoch, every directed edge
+ * (i, j) applies a bounded t-distribution attraction to the pair, then draws k
+ * negative nodes uniformly from V \ {i} and applies the bounded t-distribution
+ * repulsion to each (i, s), with immediate lock-free updates and a step size
+ * that decays linearly over the epochs.
+ *   - method and pair updates: Algorithm 1 and Sec. 3.3 of the paper;
+ *   - forces: Table 1, t-FDP row (alpha = 0.1, beta = 8, gamma = 2, Sec. 3.1);
+ *   - the implicit weight k (d_i + d_j) / (|V| - 1) of the sampled repulsion:
+ *     Sec. 3.3 (expected force), Eq. (5) (linear normalised degree weight);
+ *   - lock-free bundles (all out-edges of a source in one worker): Sec. 3.4.
+ *
+ * Conventions shared by every entry point
+ *   - Graph input is CSR with int32 indices: row_ptr[n+1], col_idx[nnz].  Each
+ *     undirected edge must appear in both directions (Sec. 3.3), rows sorted
+ *     strictly increasing, no self-loops, no duplicates; nnz = row_ptr[n] <
+ *     2^31.  Isolated nodes are allowed (they are drawn as negatives only).
+ *   - Positions are float32, row-major n x 2 (x0, y0, x1, y1, ...).
+ *   - Unless stated otherwise, pointers are host pointers owned by the caller
+ *     and only read during the call; the library copies what it keeps.
+ *   - Every function returns LAYOUT_OK (0) or a negative LAYOUT_E_* code and,
+ *     on error, sets a thread-local message readable with layout_last_error().
+ *     No C++ exception crosses the ABI.
+ *   - A layout handle is not thread-safe: one thread at a time per handle.
+ *   - Device faults are sticky for the process (HIP context); the library
+ *     reports them as LAYOUT_E_DEVICE and cannot recover them in-process.
+ */
+#ifndef SNAPLAYOUT_H
+#define SNAPLAYOUT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LAYOUT_OK = 0,
+    LAYOUT_E_INVALID_ARG = -1, /* a scalar argument or pointer is out of range */
+    LAYOUT_E_BAD_GRAPH = -2,   /* the CSR violates the conventions above */
+    LAYOUT_E_OOM = -3,         /* device memory allocation failed */
+    LAYOUT_E_DEVICE = -4,      /* a HIP runtime call failed */
+    LAYOUT_E_DONE = -5,        /* all epochs of the schedule have run */
+    LAYOUT_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+};
+
+/* How concurrent position updates are committed (Sec. 3.4 lock-free scheme). */
+enum {
+    LAYOUT_HOGWILD_STORE = 0, /* device-scope plain stores; racing updates may be lost */
+    LAYOUT_ATOMIC = 1,        /* device-scope float atomic adds; no update lost */
+    LAYOUT_JACOBI = 2,        /* test mode: all pair forces from epoch-start positions */
+    LAYOUT_UPDATE_AUTO = 3    /* ATOMIC on the LDS engine, HOGWILD_STORE on the global one */
+};
+
+/* How the global engine reaches positions in device memory. */
+enum {
+    LAYOUT_ACCESS_COHERENT = 0, /* device-scope loads/stores: every lane sees the value last
+                                   written anywhere on the device */
+    LAYOUT_ACCESS_CACHED = 1    /* plain loads/stores through the per-XCD L2 (HOGWILD_STORE
+                                   only); writes of other XCDs show up after eviction */
+};
+
+/* Distribution of the negatives. */
+enum {
+    LAYOUT_NEG_UNIFORM = 0, /* uniform over V \ {i}: the paper's method (Algorithm 1) */
+    LAYOUT_NEG_DEGREE = 1   /* proportional to degree via an alias table (control) */
+};
+
+/* Which kernel family runs the epochs. */
+enum {
+    LAYOUT_ENGINE_AUTO = 0,   /* LDS for small graphs, global otherwise */
+    LAYOUT_ENGINE_GLOBAL = 1, /* positions in device memory, all CUs */
+    LAYOUT_ENGINE_LDS = 2     /* positions in one workgroup's LDS (n * 8 B must fit) */
+};
+
+typedef struct layout layout_t;
+
+typedef struct layout_opts {
+    float alpha, beta, gamma; /* t-force parameters, defaults 0.1, 8, 2 (Table 1) */
+    float eta0;               /* initial step; eta_t = eta0 * (1 - t / epochs); default 1 */
+    int32_t update_mode;      /* LAYOUT_UPDATE_AUTO (default) / LAYOUT_HOGWILD_STORE /
+                                 LAYOUT_ATOMIC / LAYOUT_JACOBI */
+    int32_t neg_weights;      /* LAYOUT_NEG_UNIFORM (default) / LAYOUT_NEG_DEGREE */
+    int32_t engine;           /* LAYOUT_ENGINE_* (default AUTO) */
+    int32_t start_epoch;      /* resume point in [0, epochs]; default 0 */
+    int32_t bundle_edges;     /* target directed edges per lane chunk (whole rows); 0 = default */
+    int32_t block_threads;    /* threads per workgroup; 0 = default */
+    int32_t grid_blocks;      /* workgroups of the epoch kernel; 0 = fill the device */
+    int32_t access;           /* LAYOUT_ACCESS_COHERENT (default) / LAYOUT_ACCESS_CACHED */
+    int32_t hub_split_edges;  /* rows with more edges are split into segments of this many
+                                 edges, one lane each; 0 = default (4 * bundle_edges on the
+                                 global engine, never on the LDS engine) */
+    int32_t reserved1;
+    const float *init_pos;    /* n*2 initial positions (host, or device when the
+                                 inputs are on the device); NULL = seeded uniform
+                                 init in [-sqrt(n), sqrt(n)]^2 */
+    void *stream;             /* hipStream_t for all work of the handle; NULL = a
+                                 stream owned by the library */
+} layout_opts;
+
+/* Fills *opts with the defaults listed above. */
+void layout_opts_init(layout_opts *opts);
+
+/* Creates a layout job with default options.  Validates the CSR on the device,
+ * builds the chunk table, initialises positions.  Returns when the job is
+ * ready.  row_ptr/col_idx: host arrays (copied).  dim must be 2.  k in [0, 8].
+ * epochs >= 1.  seed keys every random draw (init and negatives). */
+int layout_create(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t dim,
+                  int32_t k, int32_t epochs, uint64_t seed, layout_t **out);
+
+/* As layout_create, with options.  inputs_on_device = 1: row_ptr, col_idx and
+ * opts->init_pos are device pointers (the caller keeps them alive until this
+ * call returns; they are copied). */
+int layout_create_ex(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t dim,
+                     int32_t k, int32_t epochs, uint64_t seed, const layout_opts *opts,
+                     int32_t inputs_on_device, layout_t **out);
+
+/* Enqueues min(count, remaining) epochs on the handle's stream and returns
+ * without waiting.  Returns LAYOUT_E_DONE when no epoch remains. */
+int layout_epoch(layout_t *L, int32_t count);
+
+/* As layout_epoch, then waits and reports the device time of the enqueued
+ * epoch kernels (HIP events on the handle's stream) in *ms. */
+int layout_epoch_timed(layout_t *L, int32_t count, float *ms);
+
+/* Copies the n*2 positions to host memory; waits for the handle's stream. */
+int layout_get_positions(const layout_t *L, float *host_out);
+
+/* Copies the n*2 positions to a device buffer, ordered after the handle's
+ * work; stream = NULL uses the handle's stream.  Does not wait. */
+int layout_get_positions_device(const layout_t *L, float *dev_out, void *stream);
+
+/* Overwrites the positions from host memory (n*2 floats); waits. */
+int layout_set_positions(layout_t *L, const float *host_in);
+
+/* Epochs run so far and device bytes held by the handle (either may be NULL). */
+int layout_status(const layout_t *L, int32_t *epochs_done, int64_t *device_bytes);
+
+/* Waits for all work enqueued on the handle. */
+int layout_sync(layout_t *L);
+
+/* Frees the handle and its device memory (waits first).  NULL is ignored. */
+void layout_destroy(layout_t *L);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *layout_last_error(void);
+
+/* ---- test and measurement support ------------------------------------- */
+
+typedef struct layout_info {
+    int32_t engine;        /* engine chosen for the epochs */
+    int32_t bundle_edges;  /* B */
+    int32_t block_threads;
+    int32_t grid_blocks;
+    int64_t n_chunks;      /* chunks of the row-aligned chunk table */
+    int64_t nnz;
+    int32_t n, k;
+    int32_t epochs, update_mode; /* the resolved policy (never AUTO) */
+    int32_t access, hub_split_edges;
+} layout_info;
+
+int layout_get_info(const layout_t *L, layout_info *info);
+
+/* Writes the k negatives the epoch kernels draw for every directed edge in
+ * epoch t (host array nnz*k, int32, edge-major).  Does not change positions. */
+int layout_debug_draws(layout_t *L, int32_t epoch, int32_t *host_out);
+
+/* Copies the chunk table: begin[n_chunks + 1] (first directed edge of each
+ * lane chunk, begin[n_chunks] = nnz) and src[n_chunks] (row holding that
+ * edge).  n_chunks comes from layout_get_info. */
+int layout_debug_chunks(const layout_t *L, int32_t *begin_out, int32_t *src_out);
+
+/* Copies the alias table (n entries each) used by LAYOUT_NEG_DEGREE. */
+int layout_debug_alias(const layout_t *L, uint32_t *thr_out, uint32_t *alias_out);
+
+/* Random-gather roofline of the handle's graph: the memory pattern of one
+ * epoch (stream col, one read-modify-write at col[e] and k at hashed uniform
+ * nodes per directed edge) without force arithmetic or generator.  mode:
+ * LAYOUT_HOGWILD_STORE or LAYOUT_ATOMIC; access: LAYOUT_ACCESS_* (CACHED only
+ * with HOGWILD_STORE).  Runs reps launches, reports the mean launch time in
+ * *ms.  Perturbs the positions slightly (use on a scratch job). */
+int layout_bench_gather(layout_t *L, int32_t mode, int32_t access, int32_t reps, float *ms);
+
+/* Streaming copy of bytes bytes between two device buffers allocated by the
+ * library; mean time of reps launches in *ms (HBM roofline and counter
+ * calibration). */
+int layout_bench_copy(int64_t bytes, int32_t reps, float *ms);
+
+/* ---- batched layout: many graphs in one launch --------------------------
+ *
+ * Lays out many independent graphs together (the same method per graph, each
+ * with its own seed, so each graph draws exactly the samples it would draw
+ * alone).  The CSRs are packed into one allocation.  Graphs whose positions fit
+ * one workgroup's LDS run whole, all epochs, one workgroup each (the LDS
+ * engine, ATOMIC under LAYOUT_UPDATE_AUTO).  The others share one launch per
+ * epoch of the global engine (HOGWILD_STORE under LAYOUT_UPDATE_AUTO).  All
+ * epochs of both groups are captured in one HIP graph and replayed by
+ * layout_batch_run.  k and the epoch count are common to the batch. */
+
+typedef struct layout_graph {
+    const int32_t *row_ptr; /* n+1, host (or device when inputs_on_device) */
+    const int32_t *col_idx; /* row_ptr[n] entries */
+    int32_t n;
+    int32_t reserved;
+    uint64_t seed;          /* keys this graph's draws */
+    const float *init_pos;  /* n*2 or NULL (seeded uniform init) */
+} layout_graph;
+
+typedef struct layout_batch layout_batch_t;
+
+typedef struct layout_batch_info {
+    int32_t graphs, lds_graphs, global_graphs, epochs;
+    int64_t nodes, nnz, global_chunks, device_bytes;
+    int32_t bundle_edges, hub_split_edges; /* of the global group */
+    int32_t grid_blocks, block_threads;    /* of the global group */
+    int32_t lds_block_threads, update_mode_global, update_mode_lds, epochs_done;
+} layout_batch_info;
+
+/* Creates a batch of count graphs (validated like layout_create).  opts as for
+ * layout_create_ex; init_pos and start_epoch are ignored (per-graph init_pos
+ * lives in layout_graph).  Returns when the batch is ready to run. */
+int layout_batch_create(const layout_graph *graphs, int32_t count, int32_t k, int32_t epochs,
+                        const layout_opts *opts, int32_t inputs_on_device,
+                        layout_batch_t **out);
+
+/* Replays the captured epochs (all of them) on the batch's stream; returns
+ * without waiting.  LAYOUT_E_DONE if the batch already ran. */
+int layout_batch_run(layout_batch_t *B);
+
+/* As layout_batch_run, then waits; *ms = device time of the replay. */
+int layout_batch_run_timed(layout_batch_t *B, float *ms);
+
+/* Copies graph g's n_g*2 positions to host memory (waits). */
+int layout_batch_get_positions(const layout_batch_t *B, int32_t g, float *host_out);
+
+/* Negatives graph g draws in epoch t (host int32[nnz_g * k]). */
+int layout_batch_debug_draws(const layout_batch_t *B, int32_t g, int32_t epoch, int32_t *host_out);
+
+int layout_batch_get_info(const layout_batch_t *B, layout_batch_info *info);
+
+/* Launch-shape autotuner of the global group.  Times trial_epochs epochs for
+ * every candidate (directed edges per chunk in {8, 16, 32} x workgroups per CU
+ * in {2, 4, 8, occupancy limit}) on a scratch copy of the positions, keeps the
+ * fastest, rebuilds the chunk tables and re-captures the epochs.  With
+ * cache_path (a text file, created if absent) a result for the same device
+ * architecture, k, policy and size class is reused without timing.  Results
+ * in *bundle_out, *blocks_per_cu_out, *ms_out (any may be NULL).  Call before
+ * layout_batch_run. */
+int layout_batch_autotune(layout_batch_t *B, int32_t trial_epochs, const char *cache_path,
+                          int32_t *bundle_out, int32_t *blocks_per_cu_out, float *ms_out);
+
+/* Frees the batch (waits first).  NULL is ignored. */
+void layout_batch_destroy(layout_batch_t *B);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNAPLAYOUT_H */

@@ -1,0 +1,105 @@
+// Host helpers shared by the plain, batched and served entry points.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "desc.hpp"
+#include "rng.hpp"
+
+namespace snap {
+
+// Defaults of the launch shape (overridable per handle, tuned by the batch
+// autotuner).
+constexpr int kDefaultBundle = 16;           // target directed edges per lane chunk (global engine)
+constexpr int kHubFactor = 4;                // global engine: rows above 4 * B edges are split
+constexpr int kLdsDefaultThreads = 256;      // workgroup of the LDS engine
+constexpr long long kLdsAutoMaxEdges = 400000;  // AUTO picks LDS below this many directed edges
+
+extern thread_local std::string g_last_error;
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int hip_fail(hipError_t e, const char* what);
+
+struct DeviceProps {
+  bool valid = false;
+  int cus = 0;
+  int lds_per_block = 0;
+};
+const DeviceProps& device_props();
+
+SamplerConsts sampler_consts(int32_t n);
+
+inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Upper bound of the chunk count, for allocation before the exact count is
+// known: one chunk per B-bucket, one per hub segment, one after each hub.
+inline int64_t chunk_bound(int64_t nnz, int32_t bundle, int32_t hub) {
+  return (nnz + bundle - 1) / bundle + 2 * ((nnz + hub - 1) / hub) + 2;
+}
+
+// Preprocessing shared by every entry point (snaplayout.hip).
+int build_chunk_table(hipStream_t stream, const int32_t* d_row, int32_t n, int64_t nnz,
+                      int32_t bundle, int32_t hub, int32_t* d_chunk_begin, int32_t* d_chunk_src,
+                      int64_t* n_chunks);
+int build_alias_table(hipStream_t stream, const int32_t* d_row, int32_t n, int64_t W,
+                      uint32_t* d_thr, uint32_t* d_alias);
+// Device validation of one CSR (LAYOUT_E_BAD_GRAPH with a message on failure);
+// err is a device word of scratch.
+int validate_csr(hipStream_t stream, const int32_t* d_row, const int32_t* d_col, int32_t n,
+                 int64_t nnz, uint32_t* d_err);
+void launch_init_positions(hipStream_t stream, float2* d_Y, int32_t n, uint64_t seed);
+void launch_fill_zero(hipStream_t stream, float2* d_p, int64_t n);
+
+// Graphs whose epochs run on the global engine, one launch per epoch for all
+// of them (table entries carry chunk_base prefixes over the group).
+struct GlobalGroup {
+  const GraphDesc* d_table = nullptr;
+  int G = 0;
+  int64_t total_chunks = 0;
+  int k = 5, mode = kStore;
+  bool degree = false;
+  int access = 0;  // LAYOUT_ACCESS_*
+  int block = 256;
+  int grid = 0;    // 0 = fill the device
+  float2* jacobi_Y = nullptr;  // JACOBI: Y and D of every graph, contiguous
+  float2* jacobi_D = nullptr;
+  int64_t jacobi_nodes = 0;
+};
+// Graphs run whole by one workgroup each, positions in LDS.
+struct LdsGroup {
+  const GraphDesc* d_table = nullptr;
+  const int32_t* d_ids = nullptr;  // table index of each workgroup's graph
+  int blocks = 0;
+  int lds_bytes = 0;
+  int k = 5, mode = kAtomic;
+  bool degree = false;
+  int block = 256;
+};
+int lds_bytes_for(int32_t n);
+int global_grid(const GlobalGroup& g);  // resolved grid size
+int launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t dt, int32_t count);
+int launch_lds_epochs(hipStream_t stream, const LdsGroup& g, int32_t dt, int32_t count);
+int allow_lds(int k, int bytes);  // raise the dynamic LDS limit of the LDS kernels
+// negatives of every edge of one graph in epoch t (device out[nnz*k])
+int launch_dump_draws(hipStream_t stream, int k, bool degree, const GraphDesc& g, int32_t t,
+                      int32_t* d_out);
+
+// Device allocations owned by one object, freed together.
+struct DeviceBuffers {
+  std::vector<void*> ptrs;
+  size_t total = 0;
+  void add(void* p, size_t bytes) {
+    ptrs.push_back(p);
+    total += bytes;
+  }
+  size_t bytes() const { return total; }
+  void free_all() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    total = 0;
+  }
+};
+
+}  // namespace snap

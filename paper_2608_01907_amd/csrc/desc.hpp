@@ -1,0 +1,36 @@
+// Per-graph descriptor read by the epoch kernels (one entry per graph of a
+// launch: a single layout job, a packed batch, or the active jobs of a server
+// round).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rng.hpp"
+
+namespace snap {
+
+// Update policies (Sec. 3.4 lock-free scheme; see kernels.hpp).
+enum : int { kStore = 0, kAtomic = 1, kJacobi = 2 };
+
+struct GraphDesc {
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const int32_t* chunk_begin;  // first edge of each chunk; [n_chunks] = nnz
+  const int32_t* chunk_src;    // row holding the first edge of each chunk
+  float2* Y;
+  float2* D;  // Jacobi accumulator (JACOBI only)
+  const uint32_t* thr;    // alias table (degree-weighted negatives only)
+  const uint32_t* alias;
+  int64_t chunk_base;  // first global chunk index of this graph
+  int64_t n_chunks;
+  int64_t nnz;
+  int32_t n;
+  int32_t hub;     // rows longer than this are split into segments of hub edges
+  int32_t t0;      // epoch index at launch offset 0
+  int32_t T;       // epochs in the step-size schedule
+  uint64_t seed;
+  float eta0, alpha, beta, gamma;
+  SamplerConsts sc;
+};
+
+}  // namespace snap

@@ -1,0 +1,500 @@
+// HIP kernels of the edge-centric SNAP-tFDP epoch (gfx950, wave64).
+//
+// What one epoch computes (Algorithm 1; forces of Table 1, t-FDP row): for
+// every directed edge (i, j) -- each undirected edge is stored in both
+// directions (Sec. 3.3) -- an attraction step on the pair (i, j), then k
+// negatives s drawn uniformly from V \ {i}, each with a repulsion step on
+// (i, s).  With d = y_i - y_o and q = |d|^2:
+//     attraction: y_i -= eta*alpha*(1 + beta/(1+q)) d,   y_j += the same
+//     repulsion:  y_i += eta*d/(1+q)^gamma,              y_s -= the same
+// (signs read physically: edges pull, all pairs push, Sec. 3.1).  Positions are
+// updated immediately after each pair (Sec. 3.3), lock-free (Sec. 3.4).
+//
+// Work decomposition.  One lane owns one chunk of the row-aligned chunk table
+// (chunks.hpp): a run of whole rows of about B directed edges -- the paper's
+// bundles (Sec. 3.4: all out-edges of a source handled by one worker) -- or one
+// segment of a hub row longer than H.  The lane keeps the source position in
+// a register for the run of its row (the source is updated k+1 times per edge)
+// and commits it once at the row end.  Neighbour and negative positions are
+// gathered, updated and committed per edge.
+//
+// Commit policies:
+//   STORE  -- Hogwild with plain device-scope stores: every touched position
+//             (neighbours, negatives, and the source at the end of its run) is
+//             written with the lane's new value; a concurrent update inside
+//             the load-to-store window is lost (last writer wins).  A lost
+//             update never accumulates, so no node can receive a burst of
+//             stale contributions (hubs stay stable under massive
+//             concurrency).
+//   ATOMIC -- every change is committed with device-scope float atomic adds
+//             (no update is lost; reads may still be stale).  Stale
+//             contributions accumulate, so the number of concurrent updates
+//             of one node must stay small: the mode suits bounded concurrency
+//             (the LDS engine) and bounded degrees.
+//   JACOBI -- synchronous test mode: every pair force uses the epoch-start
+//             positions, contributions are atomically summed into D, and a
+//             second kernel applies Y += D.
+// Inside one lane the pair updates are exactly sequential: when a negative
+// repeats the neighbour or an earlier negative, the lane forwards its own
+// updated value instead of the stale gathered one.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "desc.hpp"
+#include "rng.hpp"
+
+namespace snap {
+
+// --------------------------------------------------------------- memory ops
+// Global positions: device-scope relaxed accesses, so that every lane reads
+// the value last committed at device level (no stale per-CU L1 copy), 64-bit
+// for a position pair.
+struct GlobalMem {
+  static __device__ __forceinline__ float2 load(const float2* p) {
+    const uint64_t b = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(float2, b);
+  }
+  static __device__ __forceinline__ void store(float2* p, float2 v) {
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), __builtin_bit_cast(uint64_t, v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  static __device__ __forceinline__ void add(float2* p, float2 v) {
+    __hip_atomic_fetch_add(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+
+// Global positions through the caches with plain accesses: an XCD's L2 may
+// serve a line that another XCD has since written (STORE policy only).
+struct GlobalCachedMem {
+  static __device__ __forceinline__ float2 load(const float2* p) { return *p; }
+  static __device__ __forceinline__ void store(float2* p, float2 v) { *p = v; }
+};
+
+// LDS-resident positions (one workgroup owns the whole graph).
+struct LdsMem {
+  static __device__ __forceinline__ float2 load(const float2* p) {
+    const uint64_t b = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+    return __builtin_bit_cast(float2, b);
+  }
+  static __device__ __forceinline__ void store(float2* p, float2 v) {
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), __builtin_bit_cast(uint64_t, v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  static __device__ __forceinline__ void add(float2* p, float2 v) {
+    __hip_atomic_fetch_add(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
+
+// ------------------------------------------------------------------- forces
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// attraction coefficient: A(d) = coef * d
+__device__ __forceinline__ float attr_coef(float q, float alpha, float beta) {
+  return alpha * (1.0f + beta * fast_rcp(1.0f + q));
+}
+
+// repulsion coefficient: R(d) = coef * d = d / (1+q)^gamma
+__device__ __forceinline__ float rep_coef(float q, float gamma) {
+  const float r = fast_rcp(1.0f + q);
+  if (gamma == 2.0f) return r * r;
+  return __builtin_amdgcn_exp2f(gamma * __builtin_amdgcn_logf(r));
+}
+
+__device__ __forceinline__ float eta_of(const GraphDesc& g, int32_t t) {
+  return g.eta0 * (1.0f - static_cast<float>(t) / static_cast<float>(g.T));
+}
+
+// --------------------------------------------------------------- one chunk
+template <int K, bool DEGREE>
+__device__ __forceinline__ void draw_k(const GraphDesc& g, int64_t e, uint32_t t, uint32_t i,
+                                       uint32_t (&s)[K > 0 ? K : 1]) {
+  if constexpr (K > 0) {
+    WordStream ws;
+    ws.open(g.seed, static_cast<uint64_t>(e), t, kTagNeg);
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      if constexpr (DEGREE)
+        s[m] = draw_alias(ws, g.sc, i, g.thr, g.alias);
+      else
+        s[m] = draw_uniform(ws, g.sc, i);
+    }
+  }
+}
+
+// Commit of the source at the end of its run inside a chunk.  A whole row
+// (the lane owns every out-edge of i) commits the change since the run
+// started, so that updates other lanes made to y_i meanwhile (i as a
+// neighbour or a negative) survive:
+//   STORE : y_i <- (current y_i) + change  (load + store, short race window)
+//   ATOMIC: y_i += change                  (float atomics)
+// A hub segment (the row is split over `segments` lanes that start from the
+// same stale y_i) must not add up `segments` deltas computed from one start:
+//   STORE : y_i <- the lane's own value (last segment to finish wins)
+//   ATOMIC: y_i += change / segments      (the mean of the segments' moves)
+// JACOBI sums contributions into D, which is exact in every case.
+template <int MODE, class Mem>
+__device__ __forceinline__ void commit_source(float2* __restrict__ Y, float2* __restrict__ D,
+                                              int32_t i, float2 yi, float2 yi_start, float2 acc,
+                                              int32_t segments) {
+  if constexpr (MODE == kJacobi) {
+    Mem::add(D + i, acc);
+  } else if constexpr (MODE == kAtomic) {
+    const float w = segments > 1 ? 1.0f / static_cast<float>(segments) : 1.0f;
+    Mem::add(Y + i, make_float2(w * (yi.x - yi_start.x), w * (yi.y - yi_start.y)));
+  } else {
+    if (segments > 1) {
+      Mem::store(Y + i, yi);
+    } else {
+      const float2 cur = Mem::load(Y + i);
+      Mem::store(Y + i, make_float2(cur.x + (yi.x - yi_start.x), cur.y + (yi.y - yi_start.y)));
+    }
+  }
+}
+
+__device__ __forceinline__ int32_t row_segments(int64_t row_begin, int64_t row_end, int32_t hub) {
+  const int64_t d = row_end - row_begin;
+  return d > hub ? static_cast<int32_t>((d + hub - 1) / hub) : 1;
+}
+
+template <int K, int MODE, bool DEGREE, class Mem>
+__device__ __forceinline__ void process_chunk(const GraphDesc& g, float2* __restrict__ Y,
+                                              float2* __restrict__ D, int64_t lc, int32_t t,
+                                              float eta) {
+  constexpr int KS = K > 0 ? K : 1;
+  const int64_t e0 = g.chunk_begin[lc];
+  const int64_t e_end = g.chunk_begin[lc + 1];
+  int32_t i = g.chunk_src[lc];
+  int64_t row_end = g.row_ptr[i + 1];
+  int32_t segs = row_segments(g.row_ptr[i], row_end, g.hub);
+  float2 yi = Mem::load(Y + i);
+  float2 yi_start = yi;                // value at the start of the run
+  float2 acc = make_float2(0.f, 0.f);  // JACOBI: source contributions
+  const float ca = eta * g.alpha;
+
+  for (int64_t e = e0; e < e_end; ++e) {
+    if (e >= row_end) {
+      // the row is finished: commit the source, move to the next non-empty row
+      commit_source<MODE, Mem>(Y, D, i, yi, yi_start, acc, segs);
+      int64_t row_begin;
+      do {
+        ++i;
+        row_begin = row_end;
+        row_end = g.row_ptr[i + 1];
+      } while (e >= row_end);
+      segs = row_segments(row_begin, row_end, g.hub);
+      yi = Mem::load(Y + i);
+      yi_start = yi;
+      acc = make_float2(0.f, 0.f);
+    }
+    const int32_t j = __builtin_nontemporal_load(g.col + e);
+    uint32_t s[KS];
+    draw_k<K, DEGREE>(g, e, static_cast<uint32_t>(t), static_cast<uint32_t>(i), s);
+
+    // issue every gather of the edge before any arithmetic
+    float2 yj = Mem::load(Y + j);
+    float2 ys[KS];
+#pragma unroll
+    for (int m = 0; m < K; ++m) ys[m] = Mem::load(Y + s[m]);
+
+    if constexpr (MODE == kJacobi) {
+      {
+        const float dx = yi.x - yj.x, dy = yi.y - yj.y;
+        const float c = ca * (1.0f + g.beta * fast_rcp(1.0f + dx * dx + dy * dy));
+        acc.x -= c * dx;
+        acc.y -= c * dy;
+        Mem::add(D + j, make_float2(c * dx, c * dy));
+      }
+#pragma unroll
+      for (int m = 0; m < K; ++m) {
+        const float dx = yi.x - ys[m].x, dy = yi.y - ys[m].y;
+        const float h = eta * rep_coef(dx * dx + dy * dy, g.gamma);
+        acc.x += h * dx;
+        acc.y += h * dy;
+        Mem::add(D + s[m], make_float2(-h * dx, -h * dy));
+      }
+    } else {
+      // ATOMIC commits differences, so it keeps the gathered values
+      float2 yj_old = yj;
+      float2 ys_old[KS];
+      if constexpr (MODE == kAtomic) {
+#pragma unroll
+        for (int m = 0; m < K; ++m) ys_old[m] = ys[m];
+      }
+      {
+        const float dx = yi.x - yj.x, dy = yi.y - yj.y;
+        const float c = ca * (1.0f + g.beta * fast_rcp(1.0f + dx * dx + dy * dy));
+        yi.x -= c * dx;
+        yi.y -= c * dy;
+        yj.x += c * dx;
+        yj.y += c * dy;
+      }
+      bool dup[KS];
+#pragma unroll
+      for (int m = 0; m < K; ++m) {
+        // forward this lane's own newer value when the negative repeats
+        float2 cur = ys[m];
+        dup[m] = false;
+        if (s[m] == static_cast<uint32_t>(j)) {
+          cur = yj;
+          dup[m] = true;
+        }
+#pragma unroll
+        for (int m2 = 0; m2 < m; ++m2)
+          if (s[m2] == s[m]) {
+            cur = ys[m2];
+            dup[m] = true;
+          }
+        const float dx = yi.x - cur.x, dy = yi.y - cur.y;
+        const float h = eta * rep_coef(dx * dx + dy * dy, g.gamma);
+        yi.x += h * dx;
+        yi.y += h * dy;
+        cur.x -= h * dx;
+        cur.y -= h * dy;
+        ys[m] = cur;
+        if (s[m] == static_cast<uint32_t>(j)) yj = cur;
+#pragma unroll
+        for (int m2 = 0; m2 < m; ++m2)
+          if (s[m2] == s[m]) ys[m2] = cur;
+      }
+      if constexpr (MODE == kAtomic) {
+        Mem::add(Y + j, make_float2(yj.x - yj_old.x, yj.y - yj_old.y));
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+          if (!dup[m]) Mem::add(Y + s[m], make_float2(ys[m].x - ys_old[m].x, ys[m].y - ys_old[m].y));
+      } else {
+        (void)yj_old;
+        Mem::store(Y + j, yj);
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+          if (!dup[m]) Mem::store(Y + s[m], ys[m]);
+      }
+    }
+  }
+  // commit the last source of the chunk
+  commit_source<MODE, Mem>(Y, D, i, yi, yi_start, acc, segs);
+}
+
+// Graph of a global chunk index (tables are short; binary search).
+__device__ __forceinline__ int find_graph(const GraphDesc* __restrict__ table, int G, int64_t c) {
+  int lo = 0, hi = G - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (table[mid].chunk_base <= c)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------- epoch kernels
+// One epoch of every graph in the table; lanes stride over all chunks.
+template <int K, int MODE, bool DEGREE, class Mem = GlobalMem>
+static __global__ void __launch_bounds__(256) epoch_global_kernel(const GraphDesc* __restrict__ table,
+                                                           int G, int64_t total_chunks,
+                                                           int32_t dt) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < total_chunks;
+       c += stride) {
+    const int gi = G == 1 ? 0 : find_graph(table, G, c);
+    const GraphDesc& g = table[gi];
+    const int32_t t = g.t0 + dt;
+    process_chunk<K, MODE, DEGREE, Mem>(g, g.Y, g.D, c - g.chunk_base, t, eta_of(g, t));
+  }
+}
+
+// Whole epochs [dt, dt + count) of one small graph per workgroup, positions in
+// LDS for the duration of the launch.
+template <int K, int MODE, bool DEGREE>
+static __global__ void __launch_bounds__(1024) epoch_lds_kernel(const GraphDesc* __restrict__ table,
+                                                         const int32_t* __restrict__ graph_ids,
+                                                         int32_t dt, int32_t count) {
+  extern __shared__ float2 sY[];
+  const GraphDesc& g = table[graph_ids[blockIdx.x]];
+  for (int32_t v = threadIdx.x; v < g.n; v += blockDim.x) sY[v] = g.Y[v];
+  __syncthreads();
+  for (int32_t ep = 0; ep < count; ++ep) {
+    const int32_t t = g.t0 + dt + ep;
+    const float eta = eta_of(g, t);
+    for (int64_t lc = threadIdx.x; lc < g.n_chunks; lc += blockDim.x)
+      process_chunk<K, MODE, DEGREE, LdsMem>(g, sY, nullptr, lc, t, eta);
+    __syncthreads();
+  }
+  for (int32_t v = threadIdx.x; v < g.n; v += blockDim.x) g.Y[v] = sY[v];
+}
+
+// Jacobi apply: Y += D, D = 0.
+static __global__ void jacobi_apply_kernel(float2* __restrict__ Y, float2* __restrict__ D, int32_t n) {
+  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const float2 d = D[v];
+  float2 y = Y[v];
+  y.x += d.x;
+  y.y += d.y;
+  Y[v] = y;
+  D[v] = make_float2(0.f, 0.f);
+}
+
+static __global__ void fill_zero_kernel(float2* __restrict__ p, int64_t n) {
+  const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v < n) p[v] = make_float2(0.f, 0.f);
+}
+
+// ------------------------------------------------------------- preprocessing
+// Largest r in [0, n] with row_ptr[r] <= e (the row holding edge e when the
+// row pointers are monotone and row_ptr[n] > e).
+__device__ __forceinline__ int32_t row_of(const int32_t* __restrict__ row_ptr, int32_t n,
+                                          int64_t e) {
+  int32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo + 1) >> 1);
+    if (row_ptr[mid] <= e)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+enum : uint32_t {
+  kErrRowStart = 1u,      // row_ptr[0] != 0
+  kErrRowOrder = 2u,      // row_ptr decreasing
+  kErrRowEnd = 4u,        // row_ptr[n] != nnz
+  kErrColRange = 8u,      // col outside [0, n)
+  kErrSelfLoop = 16u,     // (i, i)
+  kErrUnsorted = 32u,     // row not strictly increasing (unsorted or duplicate)
+  kErrAsymmetric = 64u,   // (i, j) present without (j, i)
+};
+
+static __global__ void validate_rows_kernel(const int32_t* __restrict__ row_ptr, int32_t n, int64_t nnz,
+                                     uint32_t* __restrict__ err) {
+  const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v > n) return;
+  uint32_t bad = 0;
+  if (v == 0 && row_ptr[0] != 0) bad |= kErrRowStart;
+  if (v < n && row_ptr[v + 1] < row_ptr[v]) bad |= kErrRowOrder;
+  if (v == n && row_ptr[n] != nnz) bad |= kErrRowEnd;
+  if (bad) atomicOr(err, bad);
+}
+
+static __global__ void validate_edges_kernel(const int32_t* __restrict__ row_ptr,
+                                      const int32_t* __restrict__ col, int32_t n, int64_t nnz,
+                                      uint32_t* __restrict__ err) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const int32_t i = row_of(row_ptr, n, e);
+  const int32_t j = col[e];
+  uint32_t bad = 0;
+  if (j < 0 || j >= n) {
+    bad |= kErrColRange;
+  } else {
+    if (j == i) bad |= kErrSelfLoop;
+    if (e > row_ptr[i] && col[e - 1] >= j) bad |= kErrUnsorted;
+    // the reverse edge (j, i) must exist: binary search row j
+    int32_t lo = row_ptr[j], hi = row_ptr[j + 1] - 1;
+    bool found = false;
+    while (lo <= hi) {
+      const int32_t mid = lo + ((hi - lo) >> 1);
+      const int32_t v = col[mid];
+      if (v == i) {
+        found = true;
+        break;
+      }
+      if (v < i)
+        lo = mid + 1;
+      else
+        hi = mid - 1;
+    }
+    if (!found) bad |= kErrAsymmetric;
+  }
+  if (bad) atomicOr(err, bad);
+}
+
+// Initial positions: uniform in [-s, s]^2, s = sqrtf(n) computed on the host.
+// Coordinate c of node v comes from the top 24 bits of word x_c of the block
+// (v, 0, 0, tag 1): a signed 24-bit integer times 2^-23 (exact) times s (one
+// rounding).
+static __global__ void init_positions_kernel(float2* __restrict__ Y, int32_t n, uint64_t seed,
+                                      float scale) {
+  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const U64x4 x = philox4x64_10(static_cast<uint64_t>(v), 0, 0, kTagInit, seed, kKeyDomain);
+  const int32_t a = static_cast<int32_t>(x.x0 >> 40) - (1 << 23);
+  const int32_t b = static_cast<int32_t>(x.x1 >> 40) - (1 << 23);
+  const float ua = __fmul_rn(static_cast<float>(a), 0x1p-23f);
+  const float ub = __fmul_rn(static_cast<float>(b), 0x1p-23f);
+  Y[v] = make_float2(__fmul_rn(ua, scale), __fmul_rn(ub, scale));
+}
+
+// Debug: the negatives the epoch kernels draw for every edge in epoch t.
+template <int K, bool DEGREE>
+static __global__ void dump_draws_kernel(GraphDesc g, int32_t t, int32_t* __restrict__ out) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= g.nnz) return;
+  const int32_t i = row_of(g.row_ptr, g.n, e);
+  uint32_t s[K > 0 ? K : 1];
+  draw_k<K, DEGREE>(g, e, static_cast<uint32_t>(t), static_cast<uint32_t>(i), s);
+#pragma unroll
+  for (int m = 0; m < K; ++m) out[e * K + m] = static_cast<int32_t>(s[m]);
+}
+
+// ----------------------------------------------------------- microbenchmarks
+// Plain streaming copy (HBM roofline and counter calibration).
+static __global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n4) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < n4;
+       v += stride)
+    dst[v] = src[v];
+}
+
+// The memory pattern of an epoch without the force arithmetic or the
+// generator: per directed edge one read-modify-write at col[e] and k at
+// hashed uniform nodes, plus the source per chunk (random-gather roofline).
+template <int K, int MODE, class Mem>
+static __global__ void __launch_bounds__(256) gather_rmw_kernel(const GraphDesc* __restrict__ table,
+                                                         int64_t total_chunks) {
+  const GraphDesc& g = table[0];
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < total_chunks;
+       c += stride) {
+    const int64_t e0 = g.chunk_begin[c];
+    const int64_t e_end = g.chunk_begin[c + 1];
+    int32_t i = g.chunk_src[c];
+    float2 yi = Mem::load(g.Y + i);
+    for (int64_t e = e0; e < e_end; ++e) {
+      const int32_t j = __builtin_nontemporal_load(g.col + e);
+      uint32_t s[K > 0 ? K : 1];
+#pragma unroll
+      for (int m = 0; m < K; ++m) {
+        uint32_t h = static_cast<uint32_t>(e) * 0x9E3779B1u + static_cast<uint32_t>(m) * 0x85EBCA77u;
+        h ^= h >> 15;
+        h *= 0x2C1B3C6Du;
+        h ^= h >> 12;
+        s[m] = static_cast<uint32_t>((static_cast<uint64_t>(h) * g.sc.n) >> 32);
+      }
+      float2 yj = Mem::load(g.Y + j);
+      float2 ys[K > 0 ? K : 1];
+#pragma unroll
+      for (int m = 0; m < K; ++m) ys[m] = Mem::load(g.Y + s[m]);
+      yi.x += 1e-7f * yj.x;
+      if constexpr (MODE == kAtomic) {
+        Mem::add(g.Y + j, make_float2(1e-7f * yj.y, 0.f));
+#pragma unroll
+        for (int m = 0; m < K; ++m) Mem::add(g.Y + s[m], make_float2(1e-7f * ys[m].y, 0.f));
+      } else {
+        Mem::store(g.Y + j, make_float2(yj.x + 1e-7f * yj.y, yj.y));
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+          Mem::store(g.Y + s[m], make_float2(ys[m].x + 1e-7f * ys[m].y, ys[m].y));
+      }
+    }
+    Mem::store(g.Y + i, yi);
+  }
+}
+
+}  // namespace snap

@@ -1,0 +1,905 @@
+// Host side of the C ABI declared in include/snaplayout.h.
+//
+// A handle owns its device copy of the CSR, the chunk table, the positions and
+// a one-entry graph table; every kernel of the handle runs on one HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <type_traits>
+#include <utility>
+
+#include "alias.hpp"
+#include "chunks.hpp"
+#include "common.hpp"
+#include "kernels.hpp"
+#include "snaplayout.h"
+
+using namespace snap;
+
+// ----------------------------------------------------------------- errors
+namespace snap {
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory)
+    return fail(LAYOUT_E_OOM, "%s: out of device memory", what);
+  return fail(LAYOUT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+const DeviceProps& device_props() {
+  static thread_local DeviceProps cache[64];
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  DeviceProps& p = cache[dev & 63];
+  if (!p.valid) {
+    (void)hipDeviceGetAttribute(&p.cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipDeviceGetAttribute(&p.lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (p.cus <= 0) p.cus = 256;
+    if (p.lds_per_block <= 0) p.lds_per_block = 65536;
+    p.valid = true;
+  }
+  return p;
+}
+
+SamplerConsts sampler_consts(int32_t n) {
+  SamplerConsts sc{};
+  sc.n = static_cast<uint32_t>(n);
+  sc.range = n >= 2 ? static_cast<uint32_t>(n - 1) : 1u;
+  sc.reject_range = n >= 2 ? static_cast<uint32_t>((1ull << 32) % static_cast<uint64_t>(n - 1)) : 0u;
+  sc.reject_n = n >= 1 ? static_cast<uint32_t>((1ull << 32) % static_cast<uint64_t>(n)) : 0u;
+  return sc;
+}
+}  // namespace snap
+
+// ------------------------------------------------------------- dispatching
+namespace {
+
+template <class F>
+int with_k(int k, F&& f) {
+  switch (k) {
+    case 0: return f(std::integral_constant<int, 0>{});
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 3: return f(std::integral_constant<int, 3>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 5: return f(std::integral_constant<int, 5>{});
+    case 6: return f(std::integral_constant<int, 6>{});
+    case 7: return f(std::integral_constant<int, 7>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    default: return fail(LAYOUT_E_UNSUPPORTED, "k = %d not supported (0..8)", k);
+  }
+}
+
+template <class F>
+int with_mode(int mode, F&& f) {
+  switch (mode) {
+    case kStore: return f(std::integral_constant<int, kStore>{});
+    case kAtomic: return f(std::integral_constant<int, kAtomic>{});
+    case kJacobi: return f(std::integral_constant<int, kJacobi>{});
+    default: return fail(LAYOUT_E_INVALID_ARG, "update_mode %d", mode);
+  }
+}
+
+template <class F>
+int with_degree(bool degree, F&& f) {
+  if (degree) return f(std::true_type{});
+  return f(std::false_type{});
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle
+struct layout {
+  int32_t n = 0, k = 0, epochs = 0, t = 0;
+  int64_t nnz = 0;
+  uint64_t seed = 0;
+  layout_opts opts{};
+  int32_t engine = LAYOUT_ENGINE_GLOBAL;
+  int32_t mode = LAYOUT_ATOMIC;  // resolved update policy
+  int32_t access = LAYOUT_ACCESS_COHERENT;
+  int32_t bundle = 16;
+  int32_t hub = 64;
+  int32_t block = 256;
+  int32_t grid = 0;
+  int64_t n_chunks = 0;
+  bool own_stream = false;
+  hipStream_t stream = nullptr;
+  int dev = 0;
+  DeviceBuffers buf;
+  GraphDesc host_desc{};
+  GraphDesc* d_table = nullptr;  // one entry
+  int32_t* d_graph_ids = nullptr;
+};
+
+namespace {
+
+int alloc(layout_t* L, void** p, size_t bytes, const char* what) {
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return hip_fail(e, what);
+  L->buf.add(*p, bytes);
+  return LAYOUT_OK;
+}
+
+GlobalGroup global_group_of(const layout_t* L) {
+  GlobalGroup g;
+  g.d_table = L->d_table;
+  g.G = 1;
+  g.total_chunks = L->n_chunks;
+  g.k = L->k;
+  g.mode = L->mode;
+  g.degree = L->opts.neg_weights == LAYOUT_NEG_DEGREE;
+  g.access = L->access;
+  g.block = L->block;
+  g.grid = L->opts.grid_blocks;
+  g.jacobi_Y = L->host_desc.Y;
+  g.jacobi_D = L->host_desc.D;
+  g.jacobi_nodes = L->n;
+  return g;
+}
+
+LdsGroup lds_group_of(const layout_t* L) {
+  LdsGroup g;
+  g.d_table = L->d_table;
+  g.d_ids = L->d_graph_ids;
+  g.blocks = 1;
+  g.lds_bytes = lds_bytes_for(L->n);
+  g.k = L->k;
+  g.mode = L->mode;
+  g.degree = L->opts.neg_weights == LAYOUT_NEG_DEGREE;
+  g.block = L->block;
+  return g;
+}
+
+int launch_epochs(layout_t* L, int32_t count) {
+  if (L->nnz == 0) return LAYOUT_OK;  // no edge, nothing moves
+  if (L->engine == LAYOUT_ENGINE_LDS) return launch_lds_epochs(L->stream, lds_group_of(L), L->t, count);
+  return launch_global_epochs(L->stream, global_group_of(L), L->t, count);
+}
+
+}  // namespace
+
+// Row-aligned chunk table (chunks.hpp), built on the device.  begin/src must
+// hold chunk_bound(nnz, bundle, hub) (+1 for begin) entries.
+int snap::build_chunk_table(hipStream_t stream, const int32_t* d_row, int32_t n, int64_t nnz,
+                            int32_t bundle, int32_t hub, int32_t* d_chunk_begin,
+                            int32_t* d_chunk_src, int64_t* n_chunks) {
+  const int64_t tiles = std::max<int64_t>(1, scan_tiles(n));
+  void* tmp = nullptr;
+  const size_t b_scan = sizeof(int32_t) * size_t(tiles + 1);
+  const size_t bytes = b_scan + size_t(n) + 64;
+  hipError_t e = hipMalloc(&tmp, bytes);
+  if (e != hipSuccess) return hip_fail(e, "chunk scratch");
+  auto* scan = static_cast<int32_t*>(tmp);
+  auto* flags = reinterpret_cast<uint8_t*>(scan + tiles + 1);
+  e = hipMemsetAsync(flags, 0, size_t(n), stream);
+  const int64_t buckets = div_up(nnz, bundle);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(chunk_flag_buckets_kernel, dim3(div_up(buckets, 256)), dim3(256), 0,
+                       stream, d_row, n, nnz, bundle, flags);
+    hipLaunchKernelGGL(chunk_flag_hubs_kernel, dim3(div_up(n, 256)), dim3(256), 0, stream, d_row,
+                       n, nnz, hub, flags);
+    device_exclusive_scan<int32_t>(stream, n, ChunkCountLoad{d_row, flags, n, hub},
+                                   ChunkWrite{d_row, hub, d_chunk_begin, d_chunk_src}, scan);
+    hipLaunchKernelGGL(chunk_sentinel_kernel, dim3(1), dim3(1), 0, stream, d_chunk_begin,
+                       scan + tiles, nnz);
+    int32_t count = 0;
+    e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&count, scan + tiles, sizeof count, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    *n_chunks = count;
+  }
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return hip_fail(e, "building the chunk table");
+  return LAYOUT_OK;
+}
+
+// Alias table for weights w_s = degree(s), W = sum w = nnz, built on the
+// device (temporary buffers freed before returning).
+int snap::build_alias_table(hipStream_t stream, const int32_t* d_row, int32_t n, int64_t W,
+                            uint32_t* d_thr, uint32_t* d_alias) {
+  const int64_t tiles = std::max<int64_t>(1, scan_tiles(n));
+  void* tmp = nullptr;
+  const size_t b_sums = sizeof(AliasScanItem) * size_t(tiles + 1);
+  const size_t b_items = sizeof(int32_t) * size_t(n);
+  const size_t b_inc = sizeof(int64_t) * size_t(n);
+  const size_t bytes = b_sums + 2 * b_items + 2 * b_inc + 64;
+  hipError_t e = hipMalloc(&tmp, bytes);
+  if (e != hipSuccess) return hip_fail(e, "alias scratch");
+  char* p = static_cast<char*>(tmp);
+  auto* sums = reinterpret_cast<AliasScanItem*>(p);
+  auto* grand = sums + tiles;
+  auto* heavy_inc = reinterpret_cast<int64_t*>(p + b_sums);
+  auto* light_inc = heavy_inc + n;
+  auto* heavy_item = reinterpret_cast<int32_t*>(light_inc + n);
+  auto* light_item = heavy_item + n;
+  device_exclusive_scan<AliasScanItem>(stream, n, AliasLoad{d_row, n, W},
+                                       AliasCompact{heavy_item, heavy_inc, light_item, light_inc},
+                                       sums);
+  hipLaunchKernelGGL(alias_fill_kernel, dim3(div_up(n, 256)), dim3(256), 0, stream, d_row,
+                     int64_t(n), W, grand, heavy_item, heavy_inc, light_item, light_inc, d_thr,
+                     d_alias);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return hip_fail(e, "building the alias table");
+  return LAYOUT_OK;
+}
+
+int snap::lds_bytes_for(int32_t n) { return std::max(8, n * 8); }
+
+int snap::global_grid(const GlobalGroup& g) {
+  if (g.grid > 0) return g.grid;
+  int per_cu = 0;
+  with_k(g.k, [&](auto kc) -> int {
+    constexpr int K = decltype(kc)::value;
+    return with_degree(g.degree, [&](auto dc) -> int {
+      constexpr bool DEG = decltype(dc)::value;
+      return with_mode(g.mode, [&](auto mc) -> int {
+        constexpr int MODE = decltype(mc)::value;
+        const void* fn = reinterpret_cast<const void*>(&epoch_global_kernel<K, MODE, DEG>);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, g.block, 0) != hipSuccess)
+          per_cu = 0;
+        return LAYOUT_OK;
+      });
+    });
+  });
+  if (per_cu <= 0) per_cu = 4;
+  const int64_t want = std::max<int64_t>(1, div_up(g.total_chunks, g.block));
+  return static_cast<int>(std::min<int64_t>(want, int64_t(per_cu) * device_props().cus));
+}
+
+int snap::launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t dt,
+                               int32_t count) {
+  if (g.total_chunks == 0 || count <= 0) return LAYOUT_OK;
+  const int grid = global_grid(g);
+  return with_k(g.k, [&](auto kc) -> int {
+    constexpr int K = decltype(kc)::value;
+    return with_degree(g.degree, [&](auto dc) -> int {
+      constexpr bool DEG = decltype(dc)::value;
+      return with_mode(g.mode, [&](auto mc) -> int {
+        constexpr int MODE = decltype(mc)::value;
+        for (int32_t ep = 0; ep < count; ++ep) {
+          if constexpr (MODE == kStore) {
+            if (g.access == LAYOUT_ACCESS_CACHED) {
+              hipLaunchKernelGGL((epoch_global_kernel<K, MODE, DEG, GlobalCachedMem>), dim3(grid),
+                                 dim3(g.block), 0, stream, g.d_table, g.G, g.total_chunks, dt + ep);
+              continue;
+            }
+          }
+          hipLaunchKernelGGL((epoch_global_kernel<K, MODE, DEG>), dim3(grid), dim3(g.block), 0,
+                             stream, g.d_table, g.G, g.total_chunks, dt + ep);
+          if constexpr (MODE == kJacobi) {
+            hipLaunchKernelGGL(jacobi_apply_kernel, dim3(div_up(g.jacobi_nodes, 256)), dim3(256),
+                               0, stream, g.jacobi_Y, g.jacobi_D, g.jacobi_nodes);
+          }
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "epoch_global_kernel launch");
+        return LAYOUT_OK;
+      });
+    });
+  });
+}
+
+int snap::launch_lds_epochs(hipStream_t stream, const LdsGroup& g, int32_t dt, int32_t count) {
+  if (g.blocks == 0 || count <= 0) return LAYOUT_OK;
+  return with_k(g.k, [&](auto kc) -> int {
+    constexpr int K = decltype(kc)::value;
+    return with_degree(g.degree, [&](auto dc) -> int {
+      constexpr bool DEG = decltype(dc)::value;
+      return with_mode(g.mode, [&](auto mc) -> int {
+        constexpr int MODE = decltype(mc)::value;
+        if constexpr (MODE == kJacobi) {
+          return fail(LAYOUT_E_UNSUPPORTED, "LDS engine has no Jacobi mode");
+        } else {
+          hipLaunchKernelGGL((epoch_lds_kernel<K, MODE, DEG>), dim3(g.blocks), dim3(g.block),
+                             g.lds_bytes, stream, g.d_table, g.d_ids, dt, count);
+          hipError_t e = hipGetLastError();
+          if (e != hipSuccess) return hip_fail(e, "epoch_lds_kernel launch");
+          return LAYOUT_OK;
+        }
+      });
+    });
+  });
+}
+
+int snap::allow_lds(int k, int bytes) {
+  if (bytes <= 65536) return LAYOUT_OK;
+  return with_k(k, [&](auto kc) -> int {
+    constexpr int K = decltype(kc)::value;
+    const void* fns[] = {reinterpret_cast<const void*>(&epoch_lds_kernel<K, kStore, false>),
+                         reinterpret_cast<const void*>(&epoch_lds_kernel<K, kAtomic, false>),
+                         reinterpret_cast<const void*>(&epoch_lds_kernel<K, kStore, true>),
+                         reinterpret_cast<const void*>(&epoch_lds_kernel<K, kAtomic, true>)};
+    for (const void* fn : fns) {
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+      if (e != hipSuccess) return hip_fail(e, "raising the LDS limit");
+    }
+    return LAYOUT_OK;
+  });
+}
+
+int snap::validate_csr(hipStream_t stream, const int32_t* d_row, const int32_t* d_col, int32_t n,
+                       int64_t nnz, uint32_t* d_err) {
+  hipError_t e = hipMemsetAsync(d_err, 0, sizeof(uint32_t), stream);
+  if (e != hipSuccess) return hip_fail(e, "clearing the validation flag");
+  hipLaunchKernelGGL(validate_rows_kernel, dim3(div_up(int64_t(n) + 1, 256)), dim3(256), 0,
+                     stream, d_row, n, nnz, d_err);
+  uint32_t err = 0;
+  e = hipMemcpyAsync(&err, d_err, sizeof err, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "validating row_ptr");
+  if (err)
+    return fail(LAYOUT_E_BAD_GRAPH, "row_ptr invalid (flags 0x%x: %s%s%s)", err,
+                (err & kErrRowStart) ? "row_ptr[0] != 0 " : "",
+                (err & kErrRowOrder) ? "decreasing " : "",
+                (err & kErrRowEnd) ? "row_ptr[n] != nnz" : "");
+  if (nnz == 0) return LAYOUT_OK;
+  hipLaunchKernelGGL(validate_edges_kernel, dim3(div_up(nnz, 256)), dim3(256), 0, stream, d_row,
+                     d_col, n, nnz, d_err);
+  e = hipMemcpyAsync(&err, d_err, sizeof err, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "validating col");
+  if (err)
+    return fail(LAYOUT_E_BAD_GRAPH, "CSR invalid (flags 0x%x: %s%s%s%s)", err,
+                (err & kErrColRange) ? "column out of range " : "",
+                (err & kErrSelfLoop) ? "self-loop " : "",
+                (err & kErrUnsorted) ? "unsorted or duplicate row entries " : "",
+                (err & kErrAsymmetric) ? "missing reverse edge" : "");
+  return LAYOUT_OK;
+}
+
+void snap::launch_init_positions(hipStream_t stream, float2* d_Y, int32_t n, uint64_t seed) {
+  if (n <= 0) return;
+  const float scale = std::sqrt(static_cast<float>(n));
+  hipLaunchKernelGGL(init_positions_kernel, dim3(div_up(n, 256)), dim3(256), 0, stream, d_Y, n,
+                     seed, scale);
+}
+
+int snap::launch_dump_draws(hipStream_t stream, int k, bool degree, const GraphDesc& g, int32_t t,
+                            int32_t* d_out) {
+  if (g.nnz == 0 || k == 0) return LAYOUT_OK;
+  return with_k(k, [&](auto kc) -> int {
+    constexpr int K = decltype(kc)::value;
+    return with_degree(degree, [&](auto dc) -> int {
+      constexpr bool DEG = decltype(dc)::value;
+      hipLaunchKernelGGL((dump_draws_kernel<K, DEG>), dim3(div_up(g.nnz, 256)), dim3(256), 0,
+                         stream, g, t, d_out);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "dump_draws_kernel launch");
+      return LAYOUT_OK;
+    });
+  });
+}
+
+void snap::launch_fill_zero(hipStream_t stream, float2* d_p, int64_t n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(div_up(n, 256)), dim3(256), 0, stream, d_p, n);
+}
+
+namespace {
+
+bool check_handle(const layout_t* L) {
+  if (!L) {
+    fail(LAYOUT_E_INVALID_ARG, "null layout handle");
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------- ABI
+extern "C" {
+
+const char* layout_last_error(void) { return g_last_error.c_str(); }
+
+void layout_opts_init(layout_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->alpha = 0.1f;
+  o->beta = 8.0f;
+  o->gamma = 2.0f;
+  o->eta0 = 1.0f;
+  o->update_mode = LAYOUT_UPDATE_AUTO;
+  o->access = LAYOUT_ACCESS_COHERENT;
+  o->neg_weights = LAYOUT_NEG_UNIFORM;
+  o->engine = LAYOUT_ENGINE_AUTO;
+}
+
+int layout_create(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, int32_t dim,
+                  int32_t k, int32_t epochs, uint64_t seed, layout_t** out) {
+  layout_opts o;
+  layout_opts_init(&o);
+  return layout_create_ex(row_ptr, col_idx, n, dim, k, epochs, seed, &o, 0, out);
+}
+
+int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, int32_t dim,
+                     int32_t k, int32_t epochs, uint64_t seed, const layout_opts* opts,
+                     int32_t inputs_on_device, layout_t** out) {
+  g_last_error.clear();
+  if (!out) return fail(LAYOUT_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (dim != 2) return fail(LAYOUT_E_UNSUPPORTED, "dim = %d (only 2 is supported)", dim);
+  if (n < 0) return fail(LAYOUT_E_INVALID_ARG, "n = %d", n);
+  if (k < 0 || k > 8) return fail(k < 0 ? LAYOUT_E_INVALID_ARG : LAYOUT_E_UNSUPPORTED,
+                                  "k = %d (0..8 supported)", k);
+  if (epochs < 1) return fail(LAYOUT_E_INVALID_ARG, "epochs = %d", epochs);
+  if (!row_ptr) return fail(LAYOUT_E_INVALID_ARG, "row_ptr is NULL");
+  layout_opts o;
+  if (opts)
+    o = *opts;
+  else
+    layout_opts_init(&o);
+  if (o.update_mode < 0 || o.update_mode > 3)
+    return fail(LAYOUT_E_INVALID_ARG, "update_mode = %d", o.update_mode);
+  if (o.neg_weights != LAYOUT_NEG_UNIFORM && o.neg_weights != LAYOUT_NEG_DEGREE)
+    return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
+  if (o.start_epoch < 0 || o.start_epoch > epochs)
+    return fail(LAYOUT_E_INVALID_ARG, "start_epoch = %d", o.start_epoch);
+  if (o.engine < 0 || o.engine > 2) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
+  if (o.access != LAYOUT_ACCESS_COHERENT && o.access != LAYOUT_ACCESS_CACHED)
+    return fail(LAYOUT_E_INVALID_ARG, "access = %d", o.access);
+  if (o.bundle_edges < 0 || o.block_threads < 0 || o.grid_blocks < 0 || o.hub_split_edges < 0)
+    return fail(LAYOUT_E_INVALID_ARG, "negative launch option");
+  if (o.block_threads > 1024 || (o.block_threads % 64) != 0)
+    return fail(LAYOUT_E_INVALID_ARG, "block_threads = %d (multiple of 64, <= 1024)",
+                o.block_threads);
+  if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g (must be > 1)", o.gamma);
+
+  layout_t* L = new (std::nothrow) layout_t();
+  if (!L) return fail(LAYOUT_E_OOM, "host allocation");
+  L->n = n;
+  L->k = k;
+  L->epochs = epochs;
+  L->t = o.start_epoch;
+  L->seed = seed;
+  L->opts = o;
+  (void)hipGetDevice(&L->dev);
+
+  auto bail = [&](int rc) {
+    layout_destroy(L);
+    return rc;
+  };
+
+  if (o.stream) {
+    L->stream = static_cast<hipStream_t>(o.stream);
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(hip_fail(e, "hipStreamCreate"));
+    L->own_stream = true;
+  }
+
+  // nnz from row_ptr[n]
+  int32_t nnz32 = 0;
+  if (inputs_on_device) {
+    hipError_t e = hipMemcpy(&nnz32, row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return bail(hip_fail(e, "reading row_ptr[n]"));
+  } else {
+    nnz32 = row_ptr[n];
+  }
+  if (nnz32 < 0) return bail(fail(LAYOUT_E_BAD_GRAPH, "row_ptr[n] = %d", nnz32));
+  if (nnz32 > 0 && !col_idx) return bail(fail(LAYOUT_E_INVALID_ARG, "col_idx is NULL"));
+  L->nnz = nnz32;
+
+  // engine and launch shape
+  const DeviceProps& dp = device_props();
+  const bool lds_fits = lds_bytes_for(n) <= dp.lds_per_block;
+  if (o.engine == LAYOUT_ENGINE_LDS) {
+    if (!lds_fits)
+      return bail(fail(LAYOUT_E_UNSUPPORTED, "LDS engine: %d nodes need %d B of LDS (> %d)", n,
+                       lds_bytes_for(n), dp.lds_per_block));
+    if (o.update_mode == LAYOUT_JACOBI)
+      return bail(fail(LAYOUT_E_UNSUPPORTED, "LDS engine has no Jacobi mode"));
+    L->engine = LAYOUT_ENGINE_LDS;
+  } else if (o.engine == LAYOUT_ENGINE_GLOBAL) {
+    L->engine = LAYOUT_ENGINE_GLOBAL;
+  } else {
+    L->engine = (lds_fits && L->nnz <= kLdsAutoMaxEdges && o.update_mode != LAYOUT_JACOBI)
+                    ? LAYOUT_ENGINE_LDS
+                    : LAYOUT_ENGINE_GLOBAL;
+  }
+  if (L->engine == LAYOUT_ENGINE_LDS) {
+    L->block = o.block_threads ? o.block_threads : kLdsDefaultThreads;
+    // enough chunks to keep every lane busy, each as long as possible
+    const int64_t per_lane = std::max<int64_t>(1, L->nnz / (4 * L->block));
+    L->bundle = o.bundle_edges ? o.bundle_edges : static_cast<int32_t>(std::min<int64_t>(16, per_lane));
+    // one workgroup: a lane may own a whole long row without stalling others
+    L->hub = o.hub_split_edges ? o.hub_split_edges
+                               : static_cast<int32_t>(std::max<int64_t>(1, L->nnz));
+  } else {
+    L->block = o.block_threads ? o.block_threads : 256;
+    L->bundle = o.bundle_edges ? o.bundle_edges : kDefaultBundle;
+    L->hub = o.hub_split_edges ? o.hub_split_edges : kHubFactor * L->bundle;
+  }
+  L->mode = o.update_mode != LAYOUT_UPDATE_AUTO
+                ? o.update_mode
+                : (L->engine == LAYOUT_ENGINE_LDS ? LAYOUT_ATOMIC : LAYOUT_HOGWILD_STORE);
+  L->access = o.access;
+  if (L->access == LAYOUT_ACCESS_CACHED &&
+      (L->mode != LAYOUT_HOGWILD_STORE || L->engine != LAYOUT_ENGINE_GLOBAL))
+    return bail(fail(LAYOUT_E_UNSUPPORTED,
+                     "cached access is only defined for HOGWILD_STORE on the global engine"));
+  if (L->engine == LAYOUT_ENGINE_GLOBAL && L->block > 256)
+    return bail(fail(LAYOUT_E_UNSUPPORTED, "global engine runs at most 256-thread workgroups"));
+  const int64_t chunk_cap = L->nnz > 0 ? chunk_bound(L->nnz, L->bundle, L->hub) : 0;
+
+  // device buffers
+  int rc;
+  int32_t* d_row = nullptr;
+  int32_t* d_col = nullptr;
+  int32_t* d_chunk = nullptr;
+  int32_t* d_chunk_begin = nullptr;
+  float2* d_Y = nullptr;
+  float2* d_D = nullptr;
+  uint32_t* d_err = nullptr;
+  if ((rc = alloc(L, reinterpret_cast<void**>(&d_row), sizeof(int32_t) * (size_t(n) + 1), "row_ptr")) ||
+      (rc = alloc(L, reinterpret_cast<void**>(&d_col), sizeof(int32_t) * size_t(L->nnz), "col")) ||
+      (rc = alloc(L, reinterpret_cast<void**>(&d_chunk), sizeof(int32_t) * size_t(chunk_cap), "chunk src")) ||
+      (rc = alloc(L, reinterpret_cast<void**>(&d_chunk_begin), sizeof(int32_t) * size_t(chunk_cap + 1), "chunk begin")) ||
+      (rc = alloc(L, reinterpret_cast<void**>(&d_Y), sizeof(float2) * size_t(n), "positions")) ||
+      (rc = alloc(L, reinterpret_cast<void**>(&d_err), sizeof(uint32_t), "flag")) ||
+      (rc = alloc(L, reinterpret_cast<void**>(&L->d_table), sizeof(GraphDesc), "table")) ||
+      (rc = alloc(L, reinterpret_cast<void**>(&L->d_graph_ids), sizeof(int32_t), "ids")))
+    return bail(rc);
+  if (L->mode == LAYOUT_JACOBI &&
+      (rc = alloc(L, reinterpret_cast<void**>(&d_D), sizeof(float2) * size_t(n), "jacobi delta")))
+    return bail(rc);
+
+  const hipMemcpyKind kind = inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  hipError_t e = hipMemcpyAsync(d_row, row_ptr, sizeof(int32_t) * (size_t(n) + 1), kind, L->stream);
+  if (e == hipSuccess && L->nnz > 0)
+    e = hipMemcpyAsync(d_col, col_idx, sizeof(int32_t) * size_t(L->nnz), kind, L->stream);
+  if (e != hipSuccess) return bail(hip_fail(e, "copying the graph"));
+
+  // validation on the device, then the chunk table
+  if ((rc = validate_csr(L->stream, d_row, d_col, n, L->nnz, d_err)) != LAYOUT_OK) return bail(rc);
+  if (L->nnz > 0) {
+    if ((rc = build_chunk_table(L->stream, d_row, n, L->nnz, L->bundle, L->hub, d_chunk_begin,
+                                d_chunk, &L->n_chunks)) != LAYOUT_OK)
+      return bail(rc);
+  }
+
+  // alias table of the degree-weighted negatives (weights = degrees, W = nnz)
+  uint32_t* d_thr = nullptr;
+  uint32_t* d_alias = nullptr;
+  if (o.neg_weights == LAYOUT_NEG_DEGREE && L->nnz > 0) {
+    if ((rc = alloc(L, reinterpret_cast<void**>(&d_thr), sizeof(uint32_t) * size_t(n), "alias thr")) ||
+        (rc = alloc(L, reinterpret_cast<void**>(&d_alias), sizeof(uint32_t) * size_t(n), "alias")))
+      return bail(rc);
+    if ((rc = build_alias_table(L->stream, d_row, n, L->nnz, d_thr, d_alias)) != LAYOUT_OK)
+      return bail(rc);
+  }
+
+  // initial positions
+  if (n > 0) {
+    if (o.init_pos) {
+      e = hipMemcpyAsync(d_Y, o.init_pos, sizeof(float2) * size_t(n), kind, L->stream);
+      if (e != hipSuccess) return bail(hip_fail(e, "copying init_pos"));
+    } else {
+      launch_init_positions(L->stream, d_Y, n, seed);
+    }
+  }
+  if (d_D) launch_fill_zero(L->stream, d_D, n);
+
+  GraphDesc& g = L->host_desc;
+  g.row_ptr = d_row;
+  g.col = d_col;
+  g.chunk_begin = d_chunk_begin;
+  g.chunk_src = d_chunk;
+  g.Y = d_Y;
+  g.D = d_D;
+  g.thr = d_thr;
+  g.alias = d_alias;
+  g.chunk_base = 0;
+  g.n_chunks = L->n_chunks;
+  g.nnz = L->nnz;
+  g.n = n;
+  g.hub = L->hub;
+  g.t0 = 0;
+  g.T = epochs;
+  g.seed = seed;
+  g.eta0 = o.eta0;
+  g.alpha = o.alpha;
+  g.beta = o.beta;
+  g.gamma = o.gamma;
+  g.sc = sampler_consts(n);
+  const int32_t zero = 0;
+  e = hipMemcpyAsync(L->d_table, &g, sizeof g, hipMemcpyHostToDevice, L->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(L->d_graph_ids, &zero, sizeof zero, hipMemcpyHostToDevice, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return bail(hip_fail(e, "finishing create"));
+  if (L->engine == LAYOUT_ENGINE_LDS && (rc = allow_lds(k, lds_bytes_for(n))) != LAYOUT_OK)
+    return bail(rc);
+  *out = L;
+  return LAYOUT_OK;
+}
+
+int layout_epoch(layout_t* L, int32_t count) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (count < 0) return fail(LAYOUT_E_INVALID_ARG, "count = %d", count);
+  if (L->t >= L->epochs) return fail(LAYOUT_E_DONE, "all %d epochs done", L->epochs);
+  const int32_t run = std::min(count, L->epochs - L->t);
+  if (run == 0) return LAYOUT_OK;
+  const int rc = launch_epochs(L, run);
+  if (rc != LAYOUT_OK) return rc;
+  L->t += run;
+  return LAYOUT_OK;
+}
+
+int layout_epoch_timed(layout_t* L, int32_t count, float* ms) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (!ms) return fail(LAYOUT_E_INVALID_ARG, "ms is NULL");
+  hipEvent_t a, b;
+  hipError_t e = hipEventCreate(&a);
+  if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  e = hipEventCreate(&b);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return hip_fail(e, "hipEventCreate");
+  }
+  int rc = LAYOUT_OK;
+  e = hipEventRecord(a, L->stream);
+  if (e == hipSuccess) {
+    rc = layout_epoch(L, count);
+    if (rc == LAYOUT_OK) {
+      e = hipEventRecord(b, L->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc != LAYOUT_OK) return rc;
+  if (e != hipSuccess) return hip_fail(e, "timing epochs");
+  return LAYOUT_OK;
+}
+
+int layout_get_positions(const layout_t* L, float* host_out) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (!host_out) return fail(LAYOUT_E_INVALID_ARG, "host_out is NULL");
+  if (L->n == 0) return LAYOUT_OK;
+  hipError_t e = hipMemcpyAsync(host_out, L->host_desc.Y, sizeof(float2) * size_t(L->n),
+                                hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_fail(e, "reading positions");
+  return LAYOUT_OK;
+}
+
+int layout_get_positions_device(const layout_t* L, float* dev_out, void* stream) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (!dev_out) return fail(LAYOUT_E_INVALID_ARG, "dev_out is NULL");
+  if (L->n == 0) return LAYOUT_OK;
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : L->stream;
+  hipError_t e = hipSuccess;
+  if (s != L->stream) {
+    // order the copy after the handle's work
+    hipEvent_t ev;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, L->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, ev, 0);
+    (void)hipEventDestroy(ev);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dev_out, L->host_desc.Y, sizeof(float2) * size_t(L->n),
+                       hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "copying positions");
+  return LAYOUT_OK;
+}
+
+int layout_set_positions(layout_t* L, const float* host_in) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (!host_in) return fail(LAYOUT_E_INVALID_ARG, "host_in is NULL");
+  if (L->n == 0) return LAYOUT_OK;
+  hipError_t e = hipMemcpyAsync(L->host_desc.Y, host_in, sizeof(float2) * size_t(L->n),
+                                hipMemcpyHostToDevice, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_fail(e, "writing positions");
+  return LAYOUT_OK;
+}
+
+int layout_status(const layout_t* L, int32_t* epochs_done, int64_t* device_bytes) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (epochs_done) *epochs_done = L->t;
+  if (device_bytes) *device_bytes = static_cast<int64_t>(L->buf.bytes());
+  return LAYOUT_OK;
+}
+
+int layout_sync(layout_t* L) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  hipError_t e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return LAYOUT_OK;
+}
+
+void layout_destroy(layout_t* L) {
+  if (!L) return;
+  if (L->stream) (void)hipStreamSynchronize(L->stream);
+  L->buf.free_all();
+  if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
+  delete L;
+}
+
+int layout_get_info(const layout_t* L, layout_info* info) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (!info) return fail(LAYOUT_E_INVALID_ARG, "info is NULL");
+  info->engine = L->engine;
+  info->bundle_edges = L->bundle;
+  info->block_threads = L->block;
+  info->grid_blocks = 0;
+  if (L->engine == LAYOUT_ENGINE_GLOBAL && L->nnz > 0) {
+    info->grid_blocks = global_grid(global_group_of(L));
+  } else if (L->engine == LAYOUT_ENGINE_LDS) {
+    info->grid_blocks = 1;
+  }
+  info->n_chunks = L->n_chunks;
+  info->nnz = L->nnz;
+  info->n = L->n;
+  info->k = L->k;
+  info->epochs = L->epochs;
+  info->update_mode = L->mode;
+  info->access = L->access;
+  info->hub_split_edges = L->hub;
+  return LAYOUT_OK;
+}
+
+int layout_debug_draws(layout_t* L, int32_t epoch, int32_t* host_out) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (!host_out) return fail(LAYOUT_E_INVALID_ARG, "host_out is NULL");
+  if (L->nnz == 0 || L->k == 0) return LAYOUT_OK;
+  const size_t bytes = sizeof(int32_t) * size_t(L->nnz) * size_t(L->k);
+  int32_t* d_out = nullptr;
+  hipError_t e = hipMalloc(&d_out, bytes);
+  if (e != hipSuccess) return hip_fail(e, "debug draws buffer");
+  int rc = launch_dump_draws(L->stream, L->k, L->opts.neg_weights == LAYOUT_NEG_DEGREE,
+                             L->host_desc, epoch, d_out);
+  if (rc == LAYOUT_OK) {
+    e = hipMemcpyAsync(host_out, d_out, bytes, hipMemcpyDeviceToHost, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "reading debug draws");
+  }
+  (void)hipFree(d_out);
+  return rc;
+}
+
+int layout_debug_chunks(const layout_t* L, int32_t* begin_out, int32_t* src_out) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (!begin_out || !src_out) return fail(LAYOUT_E_INVALID_ARG, "NULL output");
+  if (L->n_chunks == 0) return LAYOUT_OK;
+  hipError_t e = hipMemcpyAsync(begin_out, L->host_desc.chunk_begin,
+                                sizeof(int32_t) * size_t(L->n_chunks + 1), hipMemcpyDeviceToHost,
+                                L->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(src_out, L->host_desc.chunk_src, sizeof(int32_t) * size_t(L->n_chunks),
+                       hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_fail(e, "reading the chunk table");
+  return LAYOUT_OK;
+}
+
+int layout_debug_alias(const layout_t* L, uint32_t* thr_out, uint32_t* alias_out) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (!thr_out || !alias_out) return fail(LAYOUT_E_INVALID_ARG, "NULL output");
+  if (!L->host_desc.thr) return fail(LAYOUT_E_INVALID_ARG, "handle has no alias table");
+  hipError_t e = hipMemcpyAsync(thr_out, L->host_desc.thr, sizeof(uint32_t) * size_t(L->n),
+                                hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(alias_out, L->host_desc.alias, sizeof(uint32_t) * size_t(L->n),
+                       hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_fail(e, "reading alias table");
+  return LAYOUT_OK;
+}
+
+int layout_bench_gather(layout_t* L, int32_t mode, int32_t access, int32_t reps, float* ms) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (!ms || reps < 1) return fail(LAYOUT_E_INVALID_ARG, "ms NULL or reps < 1");
+  if (mode != kStore && mode != kAtomic) return fail(LAYOUT_E_INVALID_ARG, "mode %d", mode);
+  if (access != LAYOUT_ACCESS_COHERENT && access != LAYOUT_ACCESS_CACHED)
+    return fail(LAYOUT_E_INVALID_ARG, "access %d", access);
+  if (access == LAYOUT_ACCESS_CACHED && mode != kStore)
+    return fail(LAYOUT_E_UNSUPPORTED, "cached access only with the store policy");
+  if (L->nnz == 0) {
+    *ms = 0.f;
+    return LAYOUT_OK;
+  }
+  if (L->engine != LAYOUT_ENGINE_GLOBAL)
+    return fail(LAYOUT_E_UNSUPPORTED, "gather roofline runs on the global engine layout");
+  hipEvent_t a, b;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  int rc = with_k(L->k, [&](auto kc) -> int {
+    constexpr int K = decltype(kc)::value;
+    return with_mode(mode, [&](auto mc) -> int {
+      constexpr int MODE = decltype(mc)::value;
+      if constexpr (MODE == kJacobi) {
+        return LAYOUT_E_INVALID_ARG;
+      } else {
+        GlobalGroup gg = global_group_of(L);
+        gg.mode = MODE;
+        const int grid = global_grid(gg);
+        hipError_t ee = hipEventRecord(a, L->stream);
+        for (int r = 0; r < reps && ee == hipSuccess; ++r) {
+          if (access == LAYOUT_ACCESS_CACHED) {
+            if constexpr (MODE == kStore)
+              hipLaunchKernelGGL((gather_rmw_kernel<K, MODE, GlobalCachedMem>), dim3(grid),
+                                 dim3(256), 0, L->stream, L->d_table, L->n_chunks);
+          } else {
+            hipLaunchKernelGGL((gather_rmw_kernel<K, MODE, GlobalMem>), dim3(grid), dim3(256), 0,
+                               L->stream, L->d_table, L->n_chunks);
+          }
+        }
+        if (ee == hipSuccess) ee = hipEventRecord(b, L->stream);
+        if (ee == hipSuccess) ee = hipEventSynchronize(b);
+        float t = 0.f;
+        if (ee == hipSuccess) ee = hipEventElapsedTime(&t, a, b);
+        if (ee != hipSuccess) return hip_fail(ee, "gather benchmark");
+        *ms = t / reps;
+        return LAYOUT_OK;
+      }
+    });
+  });
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
+}
+
+int layout_bench_copy(int64_t bytes, int32_t reps, float* ms) {
+  if (!ms || reps < 1 || bytes < 16) return fail(LAYOUT_E_INVALID_ARG, "bad copy benchmark args");
+  const int64_t n4 = bytes / 16;
+  float4 *src = nullptr, *dst = nullptr;
+  hipError_t e = hipMalloc(&src, size_t(n4) * 16);
+  if (e != hipSuccess) return hip_fail(e, "copy src");
+  e = hipMalloc(&dst, size_t(n4) * 16);
+  if (e != hipSuccess) {
+    (void)hipFree(src);
+    return hip_fail(e, "copy dst");
+  }
+  hipStream_t s = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) e = hipMemsetAsync(src, 0, size_t(n4) * 16, s);
+  const int grid = device_props().cus * 8;
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, s, src, dst, n4);  // warm
+    e = hipEventRecord(a, s);
+  }
+  for (int r = 0; r < reps && e == hipSuccess; ++r)
+    hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, s, src, dst, n4);
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (s) (void)hipStreamDestroy(s);
+  (void)hipFree(src);
+  (void)hipFree(dst);
+  if (e != hipSuccess) return hip_fail(e, "copy benchmark");
+  *ms = t / reps;
+  return LAYOUT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,473 @@
+"""Python binding of libsnaplayout.so (the C ABI in include/snaplayout.h).
+
+Argument marshalling only: every step of the layout runs in the HIP library.
+The functions keep the C names; numpy arrays are passed as host pointers and
+torch CUDA tensors (device memory) as device pointers.  A missing library is
+an error, never a fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import _lib
+
+LAYOUT_OK = 0
+LAYOUT_E_INVALID_ARG = -1
+LAYOUT_E_BAD_GRAPH = -2
+LAYOUT_E_OOM = -3
+LAYOUT_E_DEVICE = -4
+LAYOUT_E_DONE = -5
+LAYOUT_E_UNSUPPORTED = -6
+
+LAYOUT_HOGWILD_STORE = 0
+LAYOUT_ATOMIC = 1
+LAYOUT_JACOBI = 2
+LAYOUT_UPDATE_AUTO = 3
+LAYOUT_ACCESS_COHERENT = 0
+LAYOUT_ACCESS_CACHED = 1
+LAYOUT_NEG_UNIFORM = 0
+LAYOUT_NEG_DEGREE = 1
+LAYOUT_ENGINE_AUTO = 0
+LAYOUT_ENGINE_GLOBAL = 1
+LAYOUT_ENGINE_LDS = 2
+
+_NAMES = {
+    LAYOUT_E_INVALID_ARG: "LAYOUT_E_INVALID_ARG", LAYOUT_E_BAD_GRAPH: "LAYOUT_E_BAD_GRAPH",
+    LAYOUT_E_OOM: "LAYOUT_E_OOM", LAYOUT_E_DEVICE: "LAYOUT_E_DEVICE",
+    LAYOUT_E_DONE: "LAYOUT_E_DONE", LAYOUT_E_UNSUPPORTED: "LAYOUT_E_UNSUPPORTED",
+}
+
+
+class LayoutError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"{_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+class layout_opts(ctypes.Structure):
+    _fields_ = [
+        ("alpha", ctypes.c_float), ("beta", ctypes.c_float), ("gamma", ctypes.c_float),
+        ("eta0", ctypes.c_float),
+        ("update_mode", ctypes.c_int32), ("neg_weights", ctypes.c_int32),
+        ("engine", ctypes.c_int32), ("start_epoch", ctypes.c_int32),
+        ("bundle_edges", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32), ("access", ctypes.c_int32),
+        ("hub_split_edges", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+        ("init_pos", ctypes.c_void_p), ("stream", ctypes.c_void_p),
+    ]
+
+
+class layout_info(ctypes.Structure):
+    _fields_ = [
+        ("engine", ctypes.c_int32), ("bundle_edges", ctypes.c_int32),
+        ("block_threads", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+        ("n_chunks", ctypes.c_int64), ("nnz", ctypes.c_int64),
+        ("n", ctypes.c_int32), ("k", ctypes.c_int32),
+        ("epochs", ctypes.c_int32), ("update_mode", ctypes.c_int32),
+        ("access", ctypes.c_int32), ("hub_split_edges", ctypes.c_int32),
+    ]
+
+
+class layout_graph(ctypes.Structure):
+    _fields_ = [
+        ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+        ("n", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("init_pos", ctypes.c_void_p),
+    ]
+
+
+class layout_batch_info(ctypes.Structure):
+    _fields_ = [
+        ("graphs", ctypes.c_int32), ("lds_graphs", ctypes.c_int32),
+        ("global_graphs", ctypes.c_int32), ("epochs", ctypes.c_int32),
+        ("nodes", ctypes.c_int64), ("nnz", ctypes.c_int64),
+        ("global_chunks", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+        ("bundle_edges", ctypes.c_int32), ("hub_split_edges", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+        ("lds_block_threads", ctypes.c_int32), ("update_mode_global", ctypes.c_int32),
+        ("update_mode_lds", ctypes.c_int32), ("epochs_done", ctypes.c_int32),
+    ]
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_f32p = ctypes.POINTER(ctypes.c_float)
+
+_SIGNATURES = {
+    "layout_opts_init": (None, [ctypes.POINTER(layout_opts)]),
+    "layout_create": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _i32, _u64, ctypes.POINTER(_vp)]),
+    "layout_create_ex": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _i32, _u64,
+                                        ctypes.POINTER(layout_opts), _i32, ctypes.POINTER(_vp)]),
+    "layout_epoch": (ctypes.c_int, [_vp, _i32]),
+    "layout_epoch_timed": (ctypes.c_int, [_vp, _i32, _f32p]),
+    "layout_get_positions": (ctypes.c_int, [_vp, _vp]),
+    "layout_get_positions_device": (ctypes.c_int, [_vp, _vp, _vp]),
+    "layout_set_positions": (ctypes.c_int, [_vp, _vp]),
+    "layout_status": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64)]),
+    "layout_sync": (ctypes.c_int, [_vp]),
+    "layout_destroy": (None, [_vp]),
+    "layout_last_error": (ctypes.c_char_p, []),
+    "layout_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(layout_info)]),
+    "layout_debug_draws": (ctypes.c_int, [_vp, _i32, _vp]),
+    "layout_debug_alias": (ctypes.c_int, [_vp, _vp, _vp]),
+    "layout_debug_chunks": (ctypes.c_int, [_vp, _vp, _vp]),
+    "layout_bench_gather": (ctypes.c_int, [_vp, _i32, _i32, _i32, _f32p]),
+    "layout_bench_copy": (ctypes.c_int, [_i64, _i32, _f32p]),
+    "layout_batch_create": (ctypes.c_int, [ctypes.POINTER(layout_graph), _i32, _i32, _i32,
+                                           ctypes.POINTER(layout_opts), _i32,
+                                           ctypes.POINTER(_vp)]),
+    "layout_batch_run": (ctypes.c_int, [_vp]),
+    "layout_batch_run_timed": (ctypes.c_int, [_vp, _f32p]),
+    "layout_batch_get_positions": (ctypes.c_int, [_vp, _i32, _vp]),
+    "layout_batch_debug_draws": (ctypes.c_int, [_vp, _i32, _i32, _vp]),
+    "layout_batch_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(layout_batch_info)]),
+    "layout_batch_autotune": (ctypes.c_int, [_vp, _i32, ctypes.c_char_p,
+                                             ctypes.POINTER(_i32), ctypes.POINTER(_i32), _f32p]),
+    "layout_batch_destroy": (None, [_vp]),
+}
+
+
+def lib():
+    return _lib.load(_SIGNATURES)
+
+
+def _check(rc):
+    if rc != LAYOUT_OK:
+        msg = lib().layout_last_error()
+        raise LayoutError(rc, msg.decode() if msg else "")
+
+
+def _ptr(a, dtype=None):
+    """(pointer, on_device) of a numpy array or a torch tensor."""
+    if a is None:
+        return None, False
+    if hasattr(a, "data_ptr"):  # torch tensor
+        if dtype is not None:
+            assert str(a.dtype).endswith(np.dtype(dtype).name), (a.dtype, dtype)
+        assert a.is_contiguous()
+        return a.data_ptr(), bool(a.is_cuda)
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr.ctypes.data, False
+
+
+# ----------------------------------------------------------- C-named calls
+def layout_opts_init() -> layout_opts:
+    o = layout_opts()
+    lib().layout_opts_init(ctypes.byref(o))
+    return o
+
+
+def layout_create(row_ptr, col_idx, n, dim, k, epochs, seed):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    h = _vp()
+    _check(lib().layout_create(rp.ctypes.data, ci.ctypes.data, n, dim, k, epochs, seed,
+                               ctypes.byref(h)))
+    return h
+
+
+def layout_create_ex(row_ptr, col_idx, n, dim, k, epochs, seed, opts=None, inputs_on_device=0):
+    keep = []
+    if inputs_on_device:
+        rp_p, _ = _ptr(row_ptr)
+        ci_p, _ = _ptr(col_idx)
+    else:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        keep += [rp, ci]
+        rp_p, ci_p = rp.ctypes.data, ci.ctypes.data
+    o = opts if opts is not None else layout_opts_init()
+    h = _vp()
+    _check(lib().layout_create_ex(rp_p, ci_p, n, dim, k, epochs, seed, ctypes.byref(o),
+                                  int(inputs_on_device), ctypes.byref(h)))
+    del keep
+    return h
+
+
+def layout_epoch(h, count):
+    _check(lib().layout_epoch(h, count))
+
+
+def layout_epoch_timed(h, count):
+    ms = ctypes.c_float()
+    _check(lib().layout_epoch_timed(h, count, ctypes.byref(ms)))
+    return ms.value
+
+
+def layout_get_positions(h, n):
+    out = np.zeros((n, 2), dtype=np.float32)
+    _check(lib().layout_get_positions(h, out.ctypes.data))
+    return out
+
+
+def layout_get_positions_device(h, dev_out, stream=None):
+    p, on_dev = _ptr(dev_out)
+    if not on_dev:
+        raise LayoutError(LAYOUT_E_INVALID_ARG, "dev_out must be a device tensor")
+    _check(lib().layout_get_positions_device(h, p, stream))
+
+
+def layout_set_positions(h, Y):
+    arr = np.ascontiguousarray(Y, dtype=np.float32)
+    _check(lib().layout_set_positions(h, arr.ctypes.data))
+
+
+def layout_status(h):
+    t = _i32()
+    b = _i64()
+    _check(lib().layout_status(h, ctypes.byref(t), ctypes.byref(b)))
+    return t.value, b.value
+
+
+def layout_sync(h):
+    _check(lib().layout_sync(h))
+
+
+def layout_destroy(h):
+    lib().layout_destroy(h)
+
+
+def layout_last_error():
+    m = lib().layout_last_error()
+    return m.decode() if m else ""
+
+
+def layout_get_info(h) -> dict:
+    info = layout_info()
+    _check(lib().layout_get_info(h, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in layout_info._fields_}
+
+
+def layout_debug_draws(h, epoch, nnz, k):
+    out = np.zeros((max(nnz, 1), max(k, 1)), dtype=np.int32)
+    _check(lib().layout_debug_draws(h, epoch, out.ctypes.data))
+    return out[:nnz, :k]
+
+
+def layout_debug_chunks(h):
+    n_chunks = layout_get_info(h)["n_chunks"]
+    begin = np.zeros(n_chunks + 1, dtype=np.int32)
+    src = np.zeros(max(n_chunks, 1), dtype=np.int32)
+    _check(lib().layout_debug_chunks(h, begin.ctypes.data, src.ctypes.data))
+    return begin, src[:n_chunks]
+
+
+def layout_debug_alias(h, n):
+    thr = np.zeros(max(n, 1), dtype=np.uint32)
+    alias = np.zeros(max(n, 1), dtype=np.uint32)
+    _check(lib().layout_debug_alias(h, thr.ctypes.data, alias.ctypes.data))
+    return thr[:n], alias[:n]
+
+
+def layout_bench_gather(h, mode, reps, access=LAYOUT_ACCESS_COHERENT):
+    ms = ctypes.c_float()
+    _check(lib().layout_bench_gather(h, mode, access, reps, ctypes.byref(ms)))
+    return ms.value
+
+
+def layout_bench_copy(nbytes, reps):
+    ms = ctypes.c_float()
+    _check(lib().layout_bench_copy(int(nbytes), reps, ctypes.byref(ms)))
+    return ms.value
+
+
+# ------------------------------------------------------------- batches
+def layout_batch_create(graphs, k, epochs, opts=None, inputs_on_device=0):
+    """graphs: list of dicts with row_ptr, col_idx, n, seed[, init_pos]."""
+    arr = (layout_graph * len(graphs))()
+    keep = []
+    for q, g in enumerate(graphs):
+        if inputs_on_device:
+            rp_p, ci_p = _ptr(g["row_ptr"])[0], _ptr(g["col_idx"])[0]
+            ip = _ptr(g.get("init_pos"))[0]
+        else:
+            rp = np.ascontiguousarray(g["row_ptr"], dtype=np.int32)
+            ci = np.ascontiguousarray(g["col_idx"], dtype=np.int32)
+            keep += [rp, ci]
+            rp_p, ci_p = rp.ctypes.data, ci.ctypes.data
+            ip = None
+            if g.get("init_pos") is not None:
+                a = np.ascontiguousarray(g["init_pos"], dtype=np.float32)
+                keep.append(a)
+                ip = a.ctypes.data
+        arr[q].row_ptr, arr[q].col_idx, arr[q].n = rp_p, ci_p, int(g["n"])
+        arr[q].seed, arr[q].init_pos = int(g.get("seed", 0)), ip
+    o = opts if opts is not None else layout_opts_init()
+    h = _vp()
+    _check(lib().layout_batch_create(arr, len(graphs), k, epochs, ctypes.byref(o),
+                                     int(inputs_on_device), ctypes.byref(h)))
+    del keep
+    return h
+
+
+def layout_batch_run(h):
+    _check(lib().layout_batch_run(h))
+
+
+def layout_batch_run_timed(h):
+    ms = ctypes.c_float()
+    _check(lib().layout_batch_run_timed(h, ctypes.byref(ms)))
+    return ms.value
+
+
+def layout_batch_get_positions(h, g, n):
+    out = np.zeros((n, 2), dtype=np.float32)
+    _check(lib().layout_batch_get_positions(h, g, out.ctypes.data))
+    return out
+
+
+def layout_batch_debug_draws(h, g, epoch, nnz, k):
+    out = np.zeros((max(nnz, 1), max(k, 1)), dtype=np.int32)
+    _check(lib().layout_batch_debug_draws(h, g, epoch, out.ctypes.data))
+    return out[:nnz, :k]
+
+
+def layout_batch_get_info(h) -> dict:
+    info = layout_batch_info()
+    _check(lib().layout_batch_get_info(h, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in layout_batch_info._fields_}
+
+
+def layout_batch_autotune(h, trial_epochs=2, cache_path=None):
+    b, p, ms = _i32(), _i32(), ctypes.c_float()
+    cp = cache_path.encode() if cache_path else None
+    _check(lib().layout_batch_autotune(h, trial_epochs, cp, ctypes.byref(b), ctypes.byref(p),
+                                       ctypes.byref(ms)))
+    return {"bundle_edges": b.value, "blocks_per_cu": p.value, "epoch_ms": ms.value}
+
+
+def layout_batch_destroy(h):
+    lib().layout_batch_destroy(h)
+
+
+# --------------------------------------------------------- convenience
+class Layout:
+    """One layout job: owns a handle; positions come back as numpy arrays."""
+
+    def __init__(self, row_ptr, col_idx, n, k=5, epochs=50, seed=0, *,
+                 update_mode=LAYOUT_UPDATE_AUTO, access=LAYOUT_ACCESS_COHERENT,
+                 neg_weights=LAYOUT_NEG_UNIFORM, engine=LAYOUT_ENGINE_AUTO, eta0=1.0,
+                 alpha=0.1, beta=8.0, gamma=2.0, init_pos=None, bundle_edges=0,
+                 block_threads=0, grid_blocks=0, start_epoch=0, stream=None,
+                 hub_split_edges=0):
+        o = layout_opts_init()
+        o.alpha, o.beta, o.gamma, o.eta0 = alpha, beta, gamma, eta0
+        o.update_mode, o.neg_weights, o.engine = update_mode, neg_weights, engine
+        o.access = access
+        o.bundle_edges, o.block_threads, o.grid_blocks = bundle_edges, block_threads, grid_blocks
+        o.start_epoch = start_epoch
+        o.hub_split_edges = hub_split_edges
+        on_device = hasattr(row_ptr, "data_ptr") and row_ptr.is_cuda
+        init_keep = None
+        if init_pos is not None:
+            if on_device:
+                o.init_pos = init_pos.data_ptr()
+            else:
+                init_keep = np.ascontiguousarray(init_pos, dtype=np.float32)
+                o.init_pos = init_keep.ctypes.data
+        if stream is not None:
+            o.stream = stream
+        self.n, self.k, self.epochs = int(n), int(k), int(epochs)
+        self.nnz = int(row_ptr[-1]) if not on_device else int(row_ptr[-1].item())
+        self.h = layout_create_ex(row_ptr, col_idx, self.n, 2, self.k, self.epochs, seed, o,
+                                  int(on_device))
+        del init_keep
+
+    def run(self, count=None):
+        layout_epoch(self.h, self.epochs if count is None else count)
+        return self
+
+    def run_timed(self, count=None):
+        return layout_epoch_timed(self.h, self.epochs if count is None else count)
+
+    def positions(self):
+        return layout_get_positions(self.h, self.n)
+
+    def set_positions(self, Y):
+        layout_set_positions(self.h, Y)
+
+    def draws(self, epoch):
+        return layout_debug_draws(self.h, epoch, self.nnz, self.k)
+
+    def info(self):
+        return layout_get_info(self.h)
+
+    def status(self):
+        return layout_status(self.h)
+
+    def sync(self):
+        layout_sync(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            layout_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class BatchLayout:
+    """Many graphs laid out together (one HIP graph replay for all epochs)."""
+
+    def __init__(self, graphs, k=5, epochs=50, *, update_mode=LAYOUT_UPDATE_AUTO,
+                 engine=LAYOUT_ENGINE_AUTO, eta0=1.0, bundle_edges=0, hub_split_edges=0,
+                 block_threads=0, grid_blocks=0, neg_weights=LAYOUT_NEG_UNIFORM):
+        o = layout_opts_init()
+        o.update_mode, o.engine, o.eta0 = update_mode, engine, eta0
+        o.bundle_edges, o.hub_split_edges = bundle_edges, hub_split_edges
+        o.block_threads, o.grid_blocks, o.neg_weights = block_threads, grid_blocks, neg_weights
+        self.n = [int(g["n"]) for g in graphs]
+        self.nnz = [int(np.asarray(g["row_ptr"])[-1]) for g in graphs]
+        self.k, self.epochs = int(k), int(epochs)
+        self.h = layout_batch_create(graphs, self.k, self.epochs, o)
+
+    def autotune(self, trial_epochs=2, cache_path=None):
+        return layout_batch_autotune(self.h, trial_epochs, cache_path)
+
+    def run(self):
+        layout_batch_run(self.h)
+        return self
+
+    def run_timed(self):
+        return layout_batch_run_timed(self.h)
+
+    def positions(self, g):
+        return layout_batch_get_positions(self.h, g, self.n[g])
+
+    def draws(self, g, epoch):
+        return layout_batch_debug_draws(self.h, g, epoch, self.nnz[g], self.k)
+
+    def info(self):
+        return layout_batch_get_info(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            layout_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

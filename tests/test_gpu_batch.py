@@ -1,0 +1,120 @@
+"""Batched layout (many graphs, one HIP graph replay): each graph's result is
+the same alone and in the mix, within the stated tolerances.
+
+* draws in the mix are bit-identical to the oracle's for that graph alone;
+* synchronous (Jacobi) epochs: batch vs single-graph path within 1e-5 x
+  diameter, per graph;
+* lock-free epochs: NP and SI of each graph within 0.01 of the same graph laid
+  out alone (the single-graph path).
+"""
+import numpy as np
+import pytest
+
+import synthgraph as S
+from oracle import metrics as M
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+SL = pytest.importorskip("paper_2608_01907_amd.snaplayout")
+
+
+def _diam(Y):
+    return float(np.linalg.norm(Y.max(0) - Y.min(0)))
+
+
+@pytest.fixture(scope="module")
+def mix():
+    """Small SBMs (LDS engine) and power-law graphs (global engine), plus an
+    edgeless graph and a two-node graph."""
+    gs = []
+    for q, n in enumerate([600, 1500, 3000, 9000]):
+        gs.append(S.small_sbm(n, 4, 12.0, seed=10 + q))
+    for q, (n, m) in enumerate([(30_000, 240_000), (50_000, 300_000)]):
+        gs.append(S.chung_lu_communities(n, m, tau=2.2, dmax=800.0, n_comm=20, intra=0.9,
+                                         seed=20 + q))
+    rp, col = S.csr_from_pairs(np.array([0]), np.array([1]), 2)
+    gs.append(S.Graph(rp, col, 2, np.zeros(2, np.int32), "pair"))
+    gs.append(S.Graph(np.zeros(6, np.int32), np.zeros(0, np.int32), 5, np.zeros(5, np.int32),
+                      "empty"))
+    return gs
+
+
+def _desc(gs, seed0=100):
+    return [{"row_ptr": g.row_ptr, "col_idx": g.col, "n": g.n, "seed": seed0 + q}
+            for q, g in enumerate(gs)]
+
+
+def test_batch_groups_and_draws_bit_exact(mix):
+    with SL.BatchLayout(_desc(mix), k=5, epochs=20) as B:
+        info = B.info()
+        assert info["graphs"] == len(mix)
+        assert info["lds_graphs"] >= 4 and info["global_graphs"] >= 2
+        for q, g in enumerate(mix):
+            if g.nnz == 0:
+                continue
+            for t in (0, 19):
+                ref = O.draw_negatives(g.row_ptr, g.col, g.n, 5, t, 100 + q)
+                assert np.array_equal(B.draws(q, t), ref), (q, t)
+
+
+def test_batch_jacobi_equals_single_graph(mix):
+    T, eta0 = 3, 0.05
+    with SL.BatchLayout(_desc(mix), k=4, epochs=T, update_mode=SL.LAYOUT_JACOBI, eta0=eta0) as B:
+        B.run()
+        got = [B.positions(q) for q in range(len(mix))]
+    for q, g in enumerate(mix):
+        with SL.Layout(g.row_ptr, g.col, g.n, k=4, epochs=T, seed=100 + q,
+                       update_mode=SL.LAYOUT_JACOBI, eta0=eta0) as L:
+            L.run()
+            alone = L.positions()
+        tol = 1e-5 * max(_diam(alone), 1e-6)
+        assert np.abs(got[q] - alone).max() <= tol, q
+
+
+def test_batch_hogwild_quality_alone_and_in_mix(mix):
+    T = 40
+    with SL.BatchLayout(_desc(mix), k=5, epochs=T) as B:
+        B.run()
+        inmix = [B.positions(q) for q in range(len(mix))]
+    for q, g in enumerate(mix):
+        if g.nnz == 0:
+            assert np.array_equal(inmix[q], O.init_positions(g.n, 100 + q).astype(np.float32))
+            continue
+        assert np.all(np.isfinite(inmix[q]))
+        if g.n < 500:
+            continue
+        with SL.Layout(g.row_ptr, g.col, g.n, k=5, epochs=T, seed=100 + q) as L:
+            L.run()
+            alone = L.positions()
+        qa = M.quality(g.row_ptr, g.col, alone, g.labels, sample=2000)
+        qm = M.quality(g.row_ptr, g.col, inmix[q], g.labels, sample=2000)
+        assert abs(qa["np"] - qm["np"]) <= 0.01 and abs(qa["si"] - qm["si"]) <= 0.01, (q, qa, qm)
+
+
+def test_batch_autotune_keeps_positions_and_runs_once(mix, tmp_path):
+    cache = str(tmp_path / "tune.txt")
+    with SL.BatchLayout(_desc(mix), k=5, epochs=4) as B:
+        before = [B.positions(q) for q in range(len(mix))]
+        res = B.autotune(trial_epochs=1, cache_path=cache)
+        assert res["bundle_edges"] in (8, 16, 32)
+        for q in range(len(mix)):
+            assert np.array_equal(B.positions(q), before[q])
+        B.run()
+        with pytest.raises(SL.LayoutError) as ei:
+            B.run()
+        assert ei.value.code == SL.LAYOUT_E_DONE
+    # a second batch of the same size class reuses the cached choice
+    with SL.BatchLayout(_desc(mix), k=5, epochs=4) as B2:
+        res2 = B2.autotune(trial_epochs=1, cache_path=cache)
+        assert res2["bundle_edges"] == res["bundle_edges"]
+    assert open(cache).read().count("\n") == 1
+
+
+def test_batch_rejects_bad_graph(mix):
+    bad = _desc(mix[:2])
+    bad.append({"row_ptr": np.array([0, 1, 1], np.int32), "col_idx": np.array([1], np.int32),
+                "n": 2, "seed": 0})
+    with pytest.raises(SL.LayoutError) as ei:
+        SL.BatchLayout(bad, k=3, epochs=2)
+    assert ei.value.code == SL.LAYOUT_E_BAD_GRAPH and "graph 2" in str(ei.value)
