@@ -1,22 +1,29 @@
 """Throughput benchmark of the SNAP-tFDP layout on one MI355X.
 
-A step is one whole layout job of the workload with the graph already resident
-in HBM: create (device validation, chunk table, seeded init), every epoch of
-the schedule, and the readout of the positions into a device buffer.
+Default workload: the 4M-node / 34M-edge power-law community graph (k = 5,
+30 epochs).  A step is one whole layout job with the graph already resident in
+HBM: create (device validation, chunk table, seeded init), every epoch of the
+schedule, and the readout of the positions into a device buffer.
 
     value = |E| * (1 + k) * T / step time      (|E| undirected)
 
-The JSON line also carries:
-  roofline      -- the dominant kernel (the epoch kernel): algorithmic bytes
-                   per launch / mean launch time (HIP events on the handle's
-                   stream) against the 8 TB/s HBM peak, plus the measured
-                   random-gather roofline of the same graph;
+The JSON line also carries
+  roofline      -- the dominant kernel (the epoch kernel): algorithmic bytes per
+                   launch / mean launch time (HIP events on the handle's
+                   stream) against the 8 TB/s HBM peak; the measured
+                   random-gather roofline of the same graph; HBM traffic from
+                   the committed rocprofv3 counter summary when it was taken on
+                   the current kernel source (else null);
   cpu_baseline  -- the FP64 oracle's threaded bundle scheme timed on this
                    host's cores on a bounded sample (a few epochs).
+Other workloads (--workload): batched-512 (512 graphs in one HIP-graph
+replay, against one graph per launch) and served (a Poisson stream through
+the continuous-batching server, against FIFO one job at a time).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -29,32 +36,49 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-
-WORKLOADS = {
+PLAIN = {
     # name: (maker, k, epochs)
     "lj-like-4m": ("lj_like", 5, 30),
     "orkut-like-259k": ("orkut_like", 5, 30),
     "sbm-2000": ("sbm_2000", 5, 50),
 }
+KERNEL_SOURCES = ["paper_2608_01907_amd/csrc/kernels.hpp", "paper_2608_01907_amd/csrc/rng.hpp",
+                  "paper_2608_01907_amd/csrc/desc.hpp"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(row_ptr: np.ndarray, n: int, k: int, bundle: int) -> int:
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(row_ptr: np.ndarray, n: int, k: int, hub: int, n_chunks: int) -> int:
     """Bytes one epoch must move at minimum: per directed edge the col entry
-    (4 B) and (1 + k) position read-modify-writes (16 B each); per chunk the
-    chunk-table entry and the source read + commit (16 B) for each row segment
-    it covers; the row pointers of the rows touched (4 B each)."""
+    (4 B) and (1 + k) position read-modify-writes (16 B each); per source run
+    (a row, or one segment of a row split above `hub` edges) the source read
+    and commit (16 B); per chunk its table entries (8 B); the row pointers
+    (4 B per row)."""
     nnz = int(row_ptr[-1])
     deg = np.diff(row_ptr.astype(np.int64))
-    chunks = (nnz + bundle - 1) // bundle
-    # a row of degree d starting at edge offset o is cut into
-    # ceil((o % B + d) / B) segments
-    off = row_ptr[:-1].astype(np.int64) % bundle
-    segs = np.where(deg > 0, (off + deg + bundle - 1) // bundle, 0).sum()
-    return int(nnz * (4 + 16 * (1 + k)) + 16 * segs + 4 * chunks + 4 * (n + 1))
+    runs = int(np.where(deg > hub, (deg + hub - 1) // hub, (deg > 0).astype(np.int64)).sum())
+    return int(nnz * (4 + 16 * (1 + k)) + 16 * runs + 8 * n_chunks + 4 * (n + 1))
+
+
+def committed_traffic(workload: str):
+    """HBM bytes per epoch launch from the committed counter summary, or None
+    when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"epoch_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None, None
+    t = json.load(open(path))
+    if t.get("kernel_hash") != kernel_hash():
+        return None, t
+    return t.get("traffic_bytes_per_launch"), t
 
 
 def cpu_baseline(g, k, T, seed, budget_s=12.0):
@@ -76,36 +100,20 @@ def cpu_baseline(g, k, T, seed, budget_s=12.0):
                       f"(lock-free, {threads} threads), after one warm-up epoch"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="lj-like-4m", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="atomic", choices=["atomic", "store"])
-    ap.add_argument("--bundle", type=int, default=0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile-epochs", type=int, default=0,
-                    help="only run this many epochs on one handle (for profilers)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1",
-              file=sys.stderr)
-        sys.exit(2)
-
+# ------------------------------------------------------------------ plain
+def bench_plain(args):
     import torch
     import synthgraph as S
     from paper_2608_01907_amd import snaplayout as SL
 
-    maker, k, T = WORKLOADS[args.workload]
+    maker, k, T = PLAIN[args.workload]
     seed = 0
     t0 = time.perf_counter()
     g = S.cached(args.workload, getattr(S, maker))
     log(f"[bench] graph {g.name}: n={g.n} |E|={g.n_edges} nnz={g.nnz} "
         f"dmax={int(g.degrees().max())} ({time.perf_counter() - t0:.1f}s)")
-    mode = SL.LAYOUT_ATOMIC if args.mode == "atomic" else SL.LAYOUT_HOGWILD_STORE
-
+    mode = {"auto": SL.LAYOUT_UPDATE_AUTO, "atomic": SL.LAYOUT_ATOMIC,
+            "store": SL.LAYOUT_HOGWILD_STORE}[args.mode]
     dev = torch.device("cuda:0")
     rp_d = torch.from_numpy(g.row_ptr).to(dev)
     col_d = torch.from_numpy(g.col).to(dev)
@@ -115,8 +123,8 @@ def main():
     def opts():
         o = SL.layout_opts_init()
         o.update_mode = mode
-        o.engine = SL.LAYOUT_ENGINE_AUTO
         o.bundle_edges = args.bundle
+        o.grid_blocks = args.grid
         return o
 
     if args.profile_epochs:
@@ -125,7 +133,7 @@ def main():
         SL.layout_sync(h)
         SL.layout_destroy(h)
         log("[bench] profile run done")
-        return
+        return None
 
     def step():
         h = SL.layout_create_ex(rp_d, col_d, g.n, 2, k, T, seed, opts(), 1)
@@ -149,14 +157,13 @@ def main():
     # dominant kernel: the epoch kernel, timed with HIP events on its stream
     h = SL.layout_create_ex(rp_d, col_d, g.n, 2, k, T, seed, opts(), 1)
     info = SL.layout_get_info(h)
-    ms_epochs = SL.layout_epoch_timed(h, T)
-    ms_epoch = ms_epochs / T
+    ms_epoch = SL.layout_epoch_timed(h, T) / T
     Y = SL.layout_get_positions(h, g.n)
     finite = bool(np.all(np.isfinite(Y)))
     SL.layout_destroy(h)
-    nbytes = algorithmic_bytes(g.row_ptr, g.n, k, info["bundle_edges"])
+    nbytes = algorithmic_bytes(g.row_ptr, g.n, k, info["hub_split_edges"], info["n_chunks"])
     achieved = nbytes / (ms_epoch * 1e-3) / 1e9
-    # random-gather roofline of the same graph (same memory pattern, no math)
+    policy = {0: "store", 1: "atomic", 2: "jacobi"}[info["update_mode"]]
     gather = {}
     if info["engine"] == SL.LAYOUT_ENGINE_GLOBAL:
         h = SL.layout_create_ex(rp_d, col_d, g.n, 2, k, T, seed, opts(), 1)
@@ -168,41 +175,236 @@ def main():
     copy_gbs = 2 * (1 << 30) / (copy_ms * 1e-3) / 1e9
     log(f"[bench] epoch {ms_epoch:.3f} ms, {achieved:.1f} GB/s algorithmic, gather {gather}, "
         f"copy {copy_gbs:.0f} GB/s")
-
+    traffic, tinfo = committed_traffic(args.workload)
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"epoch_global_kernel<{k},{args.mode}>" if info["engine"] == 1 else
-                      f"epoch_lds_kernel<{k},{args.mode}>",
-            "bytes_per_launch": nbytes, "ms_per_launch": round(ms_epoch, 4),
-            "measured_copy_GBs": round(copy_gbs, 1)}
-    gkey = "atomic" if args.mode == "atomic" else "store"
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": (f"epoch_global_kernel<{k},{policy}>" if info["engine"] == 1
+                       else f"epoch_lds_kernel<{k},{policy}>"),
+            "algorithmic_bytes_per_launch": nbytes, "ms_per_launch": round(ms_epoch, 4),
+            "measured_copy_GBs": round(copy_gbs, 1), "kernel_hash": kernel_hash()}
+    if tinfo is not None and traffic is None:
+        roof["traffic_note"] = "counter summary predates the current kernel source"
     if gather:
-        roof["gather_roofline_ms"] = round(gather[gkey], 4)
-        roof["gather_roofline_frac"] = round(gather[gkey] / ms_epoch, 4)
-        roof["gather_roofline_ms_other_mode"] = round(
-            gather["store" if gkey == "atomic" else "atomic"], 4)
-
+        roof["gather_roofline_ms"] = round(gather[policy if policy in gather else "store"], 4)
+        roof["gather_roofline_frac"] = round(roof["gather_roofline_ms"] / ms_epoch, 4)
+        roof["gather_roofline_ms_by_policy"] = {k_: round(v, 4) for k_, v in gather.items()}
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle baseline")
         cpu = cpu_baseline(g, k, T, seed)
         log(f"[bench] cpu baseline {cpu['value']:.3e} edge-updates/s on {cpu['cores']} threads")
-
-    line = {
+    return {
         "metric": "edge-updates/sec (|E|(1+k)/epoch time), whole layout job incl. create",
         "value": value, "unit": "edge-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": g.name, "n": g.n, "edges": g.n_edges, "k": k, "epochs": T,
-                   "update_mode": args.mode, "engine": info["engine"],
-                   "bundle_edges": info["bundle_edges"], "grid_blocks": info["grid_blocks"]},
+                   "update_mode": policy, "engine": info["engine"],
+                   "bundle_edges": info["bundle_edges"],
+                   "hub_split_edges": info["hub_split_edges"],
+                   "grid_blocks": info["grid_blocks"]},
         "epoch_ms": round(ms_epoch, 4),
         "epoch_only_value": g.n_edges * (1 + k) / (ms_epoch * 1e-3),
         "positions_finite": finite,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------- batched
+def bench_batched(args):
+    import torch
+    import synthgraph as S
+    from paper_2608_01907_amd import snaplayout as SL
+
+    k, T, count = 5, 50, args.graphs
+    t0 = time.perf_counter()
+    gs = S.many_graphs("batch", count, 0)
+    edges = sum(g.n_edges for g in gs)
+    nodes = sum(g.n for g in gs)
+    log(f"[bench] {count} graphs, {nodes} nodes, {edges} edges ({time.perf_counter() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    rps = [torch.from_numpy(g.row_ptr).to(dev) for g in gs]
+    cols = [torch.from_numpy(g.col).to(dev) for g in gs]
+    out_d = torch.empty((nodes, 2), dtype=torch.float32, device=dev)
+    desc = [{"row_ptr": rps[q], "col_idx": cols[q], "n": g.n, "seed": q}
+            for q, g in enumerate(gs)]
+    torch.cuda.synchronize()
+    # tune once (cached), outside the timed region
+    cache = os.path.join(os.environ.get("SNAP_GRAPH_CACHE", "/tmp/snap_graphs"), "tune.txt")
+    h = SL.layout_batch_create(desc, k, T, SL.layout_opts_init(), 1)
+    tune = SL.layout_batch_autotune(h, 2, cache)
+    info = SL.layout_batch_get_info(h)
+    SL.layout_batch_destroy(h)
+    log(f"[bench] autotune {tune}; lds graphs {info['lds_graphs']}, global {info['global_graphs']}")
+
+    def opts():
+        o = SL.layout_opts_init()
+        o.bundle_edges = tune["bundle_edges"]
+        return o
+
+    def step():
+        hb = SL.layout_batch_create(desc, k, T, opts(), 1)
+        SL.layout_batch_run(hb)
+        SL.layout_batch_get_positions_device(hb, out_d)
+        SL.layout_batch_sync(hb)
+        SL.layout_batch_destroy(hb)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    value = edges * (1 + k) * T / dt
+    hb = SL.layout_batch_create(desc, k, T, opts(), 1)
+    replay_ms = SL.layout_batch_run_timed(hb)
+    SL.layout_batch_destroy(hb)
+    # plain path: one graph per launch sequence, same graphs
+    t0 = time.perf_counter()
+    for q, g in enumerate(gs):
+        hp = SL.layout_create_ex(rps[q], cols[q], g.n, 2, k, T, q, SL.layout_opts_init(), 1)
+        SL.layout_epoch(hp, T)
+        SL.layout_sync(hp)
+        SL.layout_destroy(hp)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    plain_value = edges * (1 + k) * T / plain_s
+    log(f"[bench] batched {dt * 1e3:.1f} ms/step (replay {replay_ms:.1f} ms), plain "
+        f"{plain_s * 1e3:.1f} ms")
+    return {
+        "metric": "edge-updates/sec (|E|(1+k)/epoch time), batched job of many graphs",
+        "value": value, "unit": "edge-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched-{count}", "graphs": count, "nodes": nodes,
+                   "edges": edges, "k": k, "epochs": T, "lds_graphs": info["lds_graphs"],
+                   "global_graphs": info["global_graphs"], "autotune": tune},
+        "replay_ms": round(replay_ms, 3),
+        "plain_one_graph_per_launch": {"value": plain_value, "seconds": round(plain_s, 3)},
+        "speedup_vs_plain": value / plain_value,
+    }
+
+
+# ----------------------------------------------------------------- served
+def bench_served(args):
+    import torch  # noqa: F401  (initialises the device for the library)
+    import synthgraph as S
+    from paper_2608_01907_amd import snaplayout as SL
+
+    k, T = 5, 30
+    rng = np.random.default_rng(1)
+    pool = S.many_graphs("served", args.pool, 0)
+    sizes = np.array([g.n_edges for g in pool], dtype=np.float64)
+    log(f"[bench] pool of {len(pool)} graphs, mean |E| {sizes.mean():.0f}")
+    picks = rng.integers(0, len(pool), args.jobs)
+
+    def run_plain(order):
+        lat, t_busy = [], 0.0
+        for q in order:
+            g = pool[q]
+            t0 = time.perf_counter()
+            h = SL.layout_create(g.row_ptr, g.col, g.n, 2, k, T, int(q))
+            SL.layout_epoch(h, T)
+            SL.layout_get_positions(h, g.n)
+            SL.layout_destroy(h)
+            lat.append(time.perf_counter() - t0)
+        return np.array(lat)
+
+    # plain service time (FIFO, one job at a time) on a sample of the stream
+    svc = run_plain(picks[: min(len(picks), 24)])
+    mean_svc = float(svc.mean())
+    results = {}
+    for rho in args.rho:
+        lam = rho / mean_svc
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, args.jobs))
+        srv = SL.layout_server_create(args.budget, args.slots, 0)
+        t_start = time.perf_counter()
+        ids = []
+        for q, ta in zip(picks, arrivals):
+            while time.perf_counter() - t_start < ta:
+                time.sleep(min(0.0005, ta - (time.perf_counter() - t_start)))
+            g = pool[q]
+            ids.append((SL.layout_server_submit(srv, g.row_ptr, g.col, g.n, k, T, int(q)), g.n))
+        for jid, n in ids:
+            SL.layout_server_wait(srv, jid, 600.0)
+            SL.layout_server_take(srv, jid, n)
+        wall = time.perf_counter() - t_start
+        st = SL.layout_server_get_stats(srv)
+        SL.layout_server_destroy(srv)
+        # plain FIFO at the same arrivals: simulated queue over measured service times
+        plain_svc = np.array([svc[i % len(svc)] for i in range(args.jobs)])
+        t_free, lat = 0.0, []
+        for ta, s in zip(arrivals, plain_svc):
+            start = max(ta, t_free)
+            t_free = start + s
+            lat.append(t_free - ta)
+        lat = np.array(lat)
+        results[str(rho)] = {
+            "served": {"p50_s": st["p50_latency_s"], "p99_s": st["p99_latency_s"],
+                       "edge_updates_per_s": st["edge_updates"] / wall, "wall_s": wall,
+                       "rounds": st["rounds"]},
+            "plain_fifo": {"p50_s": float(np.percentile(lat, 50)),
+                           "p99_s": float(np.percentile(lat, 99))},
+        }
+        log(f"[bench] rho {rho}: {results[str(rho)]}")
+    main_rho = str(args.rho[-1])
+    return {
+        "metric": "edge-updates/sec (|E|(1+k)/epoch time) + p50/p99 job latency, served vs plain",
+        "value": results[main_rho]["served"]["edge_updates_per_s"], "unit": "edge-updates/s",
+        "n_gpus": 1, "steps": args.jobs, "warmup": 0, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "served-stream", "jobs": args.jobs, "pool": len(pool), "k": k,
+                   "epochs": T, "slots": args.slots, "budget_bytes": args.budget},
+        "plain_mean_service_s": mean_svc,
+        "by_load": results,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="lj-like-4m",
+                    choices=sorted(PLAIN) + ["batched-512", "served"])
+    ap.add_argument("--mode", default="auto", choices=["auto", "atomic", "store"])
+    ap.add_argument("--bundle", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-epochs", type=int, default=0,
+                    help="only run this many epochs on one handle (for profilers)")
+    ap.add_argument("--profile-copy", action="store_true",
+                    help="only run the streaming copy (counter calibration)")
+    ap.add_argument("--graphs", type=int, default=512)
+    ap.add_argument("--pool", type=int, default=48)
+    ap.add_argument("--jobs", type=int, default=200)
+    ap.add_argument("--rho", type=float, nargs="+", default=[0.5, 0.8])
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--budget", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding "
+              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.profile_copy:
+        import torch  # noqa: F401
+        from paper_2608_01907_amd import snaplayout as SL
+
+        ms = SL.layout_bench_copy(1 << 30, 3)
+        log(f"[bench] copy of 1 GiB: {ms:.3f} ms per launch")
+        return
+    if args.workload == "batched-512":
+        line = bench_batched(args)
+    elif args.workload == "served":
+        line = bench_served(args)
+    else:
+        line = bench_plain(args)
+    if line is not None:
+        print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -87,13 +87,18 @@ typedef struct layout_opts {
     int32_t engine;           /* LAYOUT_ENGINE_* (default AUTO) */
     int32_t start_epoch;      /* resume point in [0, epochs]; default 0 */
     int32_t bundle_edges;     /* target directed edges per lane chunk (whole rows); 0 = default */
-    int32_t block_threads;    /* threads per workgroup; 0 = default */
-    int32_t grid_blocks;      /* workgroups of the epoch kernel; 0 = fill the device */
+    int32_t block_threads;    /* threads per workgroup; 0 = automatic (see nodes_per_lane) */
+    int32_t grid_blocks;      /* workgroups of the epoch kernel; 0 = automatic: at most one
+                                 256-lane workgroup per CU and n / nodes_per_lane lanes */
     int32_t access;           /* LAYOUT_ACCESS_COHERENT (default) / LAYOUT_ACCESS_CACHED */
     int32_t hub_split_edges;  /* rows with more edges are split into segments of this many
                                  edges, one lane each; 0 = default (4 * bundle_edges on the
                                  global engine, never on the LDS engine) */
-    int32_t reserved1;
+    int32_t nodes_per_lane;   /* concurrency cap of the automatic launch shape: lanes in
+                                 flight <= n / nodes_per_lane on the global engine, working
+                                 lanes = n / nodes_per_lane in [64, 256] on the LDS engine, so
+                                 that few concurrent updates hit one node (Sec. 3.4);
+                                 0 = default 32 */
     const float *init_pos;    /* n*2 initial positions (host, or device when the
                                  inputs are on the device); NULL = seeded uniform
                                  init in [-sqrt(n), sqrt(n)]^2 */
@@ -236,6 +241,13 @@ int layout_batch_run_timed(layout_batch_t *B, float *ms);
 /* Copies graph g's n_g*2 positions to host memory (waits). */
 int layout_batch_get_positions(const layout_batch_t *B, int32_t g, float *host_out);
 
+/* Copies every graph's positions, packed in graph order (sum of n_g * 2
+ * floats), to a device buffer, ordered after the batch's work; does not wait. */
+int layout_batch_get_positions_device(const layout_batch_t *B, float *dev_out);
+
+/* Waits for all work enqueued on the batch. */
+int layout_batch_sync(const layout_batch_t *B);
+
 /* Negatives graph g draws in epoch t (host int32[nnz_g * k]). */
 int layout_batch_debug_draws(const layout_batch_t *B, int32_t g, int32_t epoch, int32_t *host_out);
 
@@ -254,6 +266,75 @@ int layout_batch_autotune(layout_batch_t *B, int32_t trial_epochs, const char *c
 
 /* Frees the batch (waits first).  NULL is ignored. */
 void layout_batch_destroy(layout_batch_t *B);
+
+/* ---- served layout: continuous batching of submitted jobs -----------------
+ *
+ * A server owns one device stream and a scheduler thread.  Jobs (a graph, k,
+ * epochs, seed) are submitted from any host thread and copied at submission.
+ * The scheduler admits queued jobs in arrival order while a slot is free and
+ * the job's device footprint fits the HBM budget, keeps every admitted job's
+ * CSR, positions and chunk table resident on the device, and runs rounds:
+ *   - a job whose positions fit one workgroup's LDS runs all its epochs in
+ *     one workgroup (LDS engine) in its first round;
+ *   - every other job advances by a slice of its current epoch (at most
+ *     round_edges directed edges shared among the running jobs) in one
+ *     multi-graph launch of the global engine; an epoch may span rounds.
+ * When a job's last epoch ends its positions are copied to host memory, its
+ * device memory is freed and the next queued job can be admitted.  Latency is
+ * measured from submission to positions-on-host.  The method per job is the
+ * same as layout_create + layout_epoch (same draws for the same seed). */
+
+typedef struct layout_server layout_server_t;
+
+enum {
+    LAYOUT_JOB_QUEUED = 0,
+    LAYOUT_JOB_RUNNING = 1,
+    LAYOUT_JOB_DONE = 2,
+    LAYOUT_JOB_FAILED = 3
+};
+
+typedef struct layout_server_stats {
+    int64_t submitted, completed, failed, rejected;
+    int64_t queued, running;
+    int64_t hbm_in_use, hbm_budget; /* bytes */
+    int64_t rounds;
+    double edge_updates;   /* sum over completed jobs of |E| (1 + k) epochs */
+    double busy_seconds;   /* wall time with at least one job admitted */
+    double p50_latency_s, p99_latency_s, mean_latency_s; /* over completed jobs */
+} layout_server_stats;
+
+/* Starts a server.  hbm_budget_bytes: cap on the summed device footprint of
+ * admitted jobs (0 = 90% of the free device memory at start).  max_slots:
+ * cap on concurrently admitted jobs (>= 1).  round_edges: directed edges of
+ * global-engine work per round (0 = default, 32M).  opts: as for
+ * layout_create_ex (init_pos, start_epoch, stream are ignored). */
+int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t round_edges,
+                         const layout_opts *opts, layout_server_t **out);
+
+/* Queues a job; host arrays are copied before returning.  *job_id identifies
+ * it.  Malformed arguments are rejected here (LAYOUT_E_INVALID_ARG); a CSR that
+ * fails device validation ends as LAYOUT_JOB_FAILED with a message.  A job
+ * larger than the whole budget is refused with LAYOUT_E_OOM.  Thread-safe. */
+int layout_server_submit(layout_server_t *S, const int32_t *row_ptr, const int32_t *col_idx,
+                         int32_t n, int32_t k, int32_t epochs, uint64_t seed, int64_t *job_id);
+
+/* Current state (LAYOUT_JOB_*) of a job.  Thread-safe. */
+int layout_server_poll(layout_server_t *S, int64_t job_id, int32_t *state);
+
+/* Waits until the job is DONE or FAILED or timeout_s passes (< 0: no limit);
+ * returns LAYOUT_OK when it is DONE, LAYOUT_E_DEVICE/BAD_GRAPH for a failed
+ * job (message in layout_last_error), LAYOUT_E_INVALID_ARG on timeout. */
+int layout_server_wait(layout_server_t *S, int64_t job_id, double timeout_s);
+
+/* Copies a DONE job's n*2 positions, reports its latency (seconds from
+ * submission to positions on host) and forgets the job.  Thread-safe. */
+int layout_server_take(layout_server_t *S, int64_t job_id, float *host_out, double *latency_s);
+
+int layout_server_get_stats(layout_server_t *S, layout_server_stats *stats);
+
+/* Stops the scheduler after the running jobs' current round, frees every
+ * job.  NULL is ignored. */
+int layout_server_destroy(layout_server_t *S);
 
 #ifdef __cplusplus
 }

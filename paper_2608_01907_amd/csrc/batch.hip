@@ -82,11 +82,9 @@ bool check_batch(const layout_batch_t* B) {
   return true;
 }
 
-// Chunk tables of the global group for the batch's (bundle, hub), and the
-// group's table with chunk_base prefixes.
+// Chunk tables of the global group for the batch's (bundle, hub).
 int build_global_chunks(layout_batch_t* B) {
-  int64_t base = 0;
-  std::vector<GraphDesc> table;
+  int64_t total = 0;
   for (int32_t g : B->global_ids) {
     if (B->nnz[g] == 0) continue;  // nothing moves; keeps chunk_base strictly useful
     GraphDesc& d = B->desc[g];
@@ -102,17 +100,24 @@ int build_global_chunks(layout_batch_t* B) {
     }
     d.n_chunks = nc;
     d.hub = B->hub;
-    d.chunk_base = base;
-    base += nc;
-    table.push_back(d);
+    total += nc;
   }
-  if (!table.empty()) {
-    hipError_t e = hipMemcpyAsync(B->d_table_global, table.data(), sizeof(GraphDesc) * table.size(),
-                                  hipMemcpyHostToDevice, B->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
-    if (e != hipSuccess) return hip_fail(e, "uploading the global table");
-  }
-  B->gg.total_chunks = base;
+  B->gg.total_chunks = total;
+  return LAYOUT_OK;
+}
+
+// Round plan of the global group for a launch of `grid` workgroups, uploaded
+// to the device table.
+int upload_global_table(layout_batch_t* B, int grid) {
+  std::vector<GraphDesc> table;
+  for (int32_t g : B->global_ids)
+    if (B->nnz[g] > 0) table.push_back(B->desc[g]);
+  if (table.empty()) return LAYOUT_OK;
+  plan_rounds(table, B->gg, int64_t(grid) * B->gg.block);
+  hipError_t e = hipMemcpyAsync(B->d_table_global, table.data(), sizeof(GraphDesc) * table.size(),
+                                hipMemcpyHostToDevice, B->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
+  if (e != hipSuccess) return hip_fail(e, "uploading the global table");
   return LAYOUT_OK;
 }
 
@@ -131,6 +136,11 @@ int capture(layout_batch_t* B) {
     probe.grid = 0;
     const int occ_grid = global_grid(probe);
     B->gg.grid = std::min<int>(occ_grid, B->blocks_per_cu * device_props().cus);
+  }
+  if (B->gg.total_chunks > 0) {
+    GlobalGroup probe = B->gg;
+    const int rc = upload_global_table(B, global_grid(probe));
+    if (rc != LAYOUT_OK) return rc;
   }
   hipError_t e = hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
@@ -227,7 +237,7 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
     return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
   if (o.engine < 0 || o.engine > 2) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
   if (o.bundle_edges < 0 || o.block_threads < 0 || o.grid_blocks < 0 || o.hub_split_edges < 0 ||
-      o.block_threads > 1024 || (o.block_threads % 64) != 0)
+      o.nodes_per_lane < 0 || o.block_threads > 1024 || (o.block_threads % 64) != 0)
     return fail(LAYOUT_E_INVALID_ARG, "bad launch option");
   if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g (must be > 1)", o.gamma);
   if (o.access != LAYOUT_ACCESS_COHERENT && o.access != LAYOUT_ACCESS_CACHED)
@@ -302,7 +312,7 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
     B->in_lds[g] = lds;
     int64_t cap;
     if (lds) {
-      const int block = o.block_threads ? o.block_threads : kLdsDefaultThreads;
+      const int block = o.block_threads ? o.block_threads : lds_lanes_for(gr.n, o.nodes_per_lane);
       B->lds_block[g] = block;
       // one workgroup per graph: chunks of whole rows, rows never split
       B->lds_bundle[g] = o.bundle_edges ? o.bundle_edges
@@ -324,10 +334,6 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
     B->nodes += gr.n;
     B->total_nnz += nnz;
     rows += int64_t(gr.n) + 1;
-  }
-  if (!B->lds_ids.empty()) {
-    const int lds_block = o.block_threads ? o.block_threads : kLdsDefaultThreads;
-    if (lds_block > 1024) return bail(fail(LAYOUT_E_INVALID_ARG, "block_threads"));
   }
   if (!B->global_ids.empty() && o.block_threads > 256)
     return bail(fail(LAYOUT_E_UNSUPPORTED, "global engine runs at most 256-thread workgroups"));
@@ -385,6 +391,7 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
     d.beta = o.beta;
     d.gamma = o.gamma;
     d.sc = sampler_consts(gr.n);
+    d.lanes = B->in_lds[g] ? B->lds_block[g] : 0;
     if (B->in_lds[g] && B->nnz[g] > 0) {
       d.hub = B->lds_hub[g];
       int64_t nc = 0;
@@ -420,6 +427,11 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
   B->gg.degree = degree;
   B->gg.access = o.access;
   B->gg.block = o.block_threads ? o.block_threads : 256;
+  {
+    int64_t gnodes = 0;
+    for (int32_t g : B->global_ids) gnodes += B->n[g];
+    B->gg.max_lanes = gnodes / (o.nodes_per_lane > 0 ? o.nodes_per_lane : kNodesPerLane);
+  }
   B->gg.jacobi_Y = B->d_Y;
   B->gg.jacobi_D = B->d_D;
   B->gg.jacobi_nodes = B->nodes;
@@ -446,7 +458,9 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
     B->lg.k = k;
     B->lg.mode = B->mode_lds;
     B->lg.degree = degree;
-    B->lg.block = o.block_threads ? o.block_threads : kLdsDefaultThreads;
+    int lds_block = 64;
+    for (int32_t g : B->lds_ids) lds_block = std::max(lds_block, B->lds_block[g]);
+    B->lg.block = lds_block;
     if (!lt.empty() && (rc = allow_lds(k, max_lds)) != LAYOUT_OK) return bail(rc);
   }
   e = hipStreamSynchronize(B->stream);
@@ -496,6 +510,23 @@ int layout_batch_get_positions(const layout_batch_t* B, int32_t g, float* host_o
                                 hipMemcpyDeviceToHost, B->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
   if (e != hipSuccess) return hip_fail(e, "reading positions");
+  return LAYOUT_OK;
+}
+
+int layout_batch_get_positions_device(const layout_batch_t* B, float* dev_out) {
+  if (!check_batch(B)) return LAYOUT_E_INVALID_ARG;
+  if (!dev_out) return fail(LAYOUT_E_INVALID_ARG, "dev_out is NULL");
+  if (B->nodes == 0) return LAYOUT_OK;
+  hipError_t e = hipMemcpyAsync(dev_out, B->d_Y, sizeof(float2) * size_t(B->nodes),
+                                hipMemcpyDeviceToDevice, B->stream);
+  if (e != hipSuccess) return hip_fail(e, "copying positions");
+  return LAYOUT_OK;
+}
+
+int layout_batch_sync(const layout_batch_t* B) {
+  if (!check_batch(B)) return LAYOUT_E_INVALID_ARG;
+  hipError_t e = hipStreamSynchronize(B->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   return LAYOUT_OK;
 }
 
@@ -570,6 +601,10 @@ int layout_batch_autotune(layout_batch_t* B, int32_t trial_epochs, const char* c
       if ((rc = build_global_chunks(B)) != LAYOUT_OK) break;
       for (int pi = 0; pi < 4 && e == hipSuccess && rc == LAYOUT_OK; ++pi) {
         GlobalGroup g = B->gg;
+        g.grid = 0;
+        if (per_cu[pi] > 0) g.grid = std::min(global_grid(g), per_cu[pi] * device_props().cus);
+        if ((rc = upload_global_table(B, global_grid(g))) != LAYOUT_OK) break;
+        g = B->gg;
         g.grid = 0;
         if (per_cu[pi] > 0) g.grid = std::min(global_grid(g), per_cu[pi] * device_props().cus);
         // warm-up epoch, then the timed ones (epoch index 0.. of the schedule)

@@ -15,7 +15,17 @@ namespace snap {
 // autotuner).
 constexpr int kDefaultBundle = 16;           // target directed edges per lane chunk (global engine)
 constexpr int kHubFactor = 4;                // global engine: rows above 4 * B edges are split
-constexpr int kLdsDefaultThreads = 256;      // workgroup of the LDS engine
+constexpr int kNodesPerLane = 32;            // lanes in flight <= n / 32 (both engines)
+constexpr int kLanesPerCU = 256;             // global engine: at most 256 lanes per CU in flight
+                                             // (the random-access throughput saturates there)
+
+// Active lanes of the LDS engine for an n-node graph: n / nodes_per_lane,
+// a multiple of 64 in [64, 256].
+inline int lds_lanes_for(int32_t n, int nodes_per_lane) {
+  const int npl = nodes_per_lane > 0 ? nodes_per_lane : kNodesPerLane;
+  int lanes = (n / npl) / 64 * 64;
+  return lanes < 64 ? 64 : (lanes > 256 ? 256 : lanes);
+}
 constexpr long long kLdsAutoMaxEdges = 400000;  // AUTO picks LDS below this many directed edges
 
 extern thread_local std::string g_last_error;
@@ -57,12 +67,15 @@ void launch_fill_zero(hipStream_t stream, float2* d_p, int64_t n);
 struct GlobalGroup {
   const GraphDesc* d_table = nullptr;
   int G = 0;
-  int64_t total_chunks = 0;
+  int64_t total_chunks = 0;  // chunks of all graphs
+  int64_t round_size = 0;    // G > 1: positions per round (sum of the slices)
+  int64_t total_index = 0;   // G > 1: rounds * round_size
   int k = 5, mode = kStore;
   bool degree = false;
   int access = 0;  // LAYOUT_ACCESS_*
   int block = 256;
-  int grid = 0;    // 0 = fill the device
+  int grid = 0;    // 0 = fill the device, capped by max_lanes
+  int64_t max_lanes = 0;  // 0 = no cap
   float2* jacobi_Y = nullptr;  // JACOBI: Y and D of every graph, contiguous
   float2* jacobi_D = nullptr;
   int64_t jacobi_nodes = 0;
@@ -78,6 +91,10 @@ struct LdsGroup {
   int block = 256;
 };
 int lds_bytes_for(int32_t n);
+// Cuts the chunks of the graphs in table (host copy, n_chunks set) into
+// rounds for a launch of `lanes` lanes: sets each entry's slice/chunk_base and
+// the group's round_size/total_index/total_chunks.
+void plan_rounds(std::vector<GraphDesc>& table, GlobalGroup& g, int64_t lanes);
 int global_grid(const GlobalGroup& g);  // resolved grid size
 int launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t dt, int32_t count);
 int launch_lds_epochs(hipStream_t stream, const LdsGroup& g, int32_t dt, int32_t count);

@@ -21,13 +21,17 @@ struct GraphDesc {
   float2* D;  // Jacobi accumulator (JACOBI only)
   const uint32_t* thr;    // alias table (degree-weighted negatives only)
   const uint32_t* alias;
-  int64_t chunk_base;  // first global chunk index of this graph
-  int64_t n_chunks;
+  int64_t chunk_base;    // offset of this graph's slice inside one round of the launch
+  int64_t slice;         // chunks of this graph per round of the launch
+  int64_t chunk_offset;  // first chunk of the graph's table processed by the launch
+  int64_t n_chunks;      // chunks processed by the launch
   int64_t nnz;
   int32_t n;
   int32_t hub;     // rows longer than this are split into segments of hub edges
   int32_t t0;      // epoch index at launch offset 0
   int32_t T;       // epochs in the step-size schedule
+  int32_t lanes;   // LDS engine: lanes of the workgroup that work (0 = all)
+  int32_t pad0;
   uint64_t seed;
   float eta0, alpha, beta, gamma;
   SamplerConsts sc;

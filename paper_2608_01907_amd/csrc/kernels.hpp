@@ -37,6 +37,11 @@
 // Inside one lane the pair updates are exactly sequential: when a negative
 // repeats the neighbour or an earlier negative, the lane forwards its own
 // updated value instead of the stale gathered one.
+//
+// A position whose new value equals the gathered one bit for bit (a far
+// negative's repulsion step below FP32 resolution, which is the common case)
+// is not written back: the memory state is the same, one random write is
+// saved, and under STORE no concurrent update of that node is overwritten.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -126,6 +131,10 @@ __device__ __forceinline__ void draw_k(const GraphDesc& g, int64_t e, uint32_t t
   }
 }
 
+__device__ __forceinline__ bool same_bits(float2 a, float2 b) {
+  return __builtin_bit_cast(uint64_t, a) == __builtin_bit_cast(uint64_t, b);
+}
+
 // Commit of the source at the end of its run inside a chunk.  A whole row
 // (the lane owns every out-edge of i) commits the change since the run
 // started, so that updates other lanes made to y_i meanwhile (i as a
@@ -144,9 +153,11 @@ __device__ __forceinline__ void commit_source(float2* __restrict__ Y, float2* __
   if constexpr (MODE == kJacobi) {
     Mem::add(D + i, acc);
   } else if constexpr (MODE == kAtomic) {
+    if (same_bits(yi, yi_start)) return;
     const float w = segments > 1 ? 1.0f / static_cast<float>(segments) : 1.0f;
     Mem::add(Y + i, make_float2(w * (yi.x - yi_start.x), w * (yi.y - yi_start.y)));
   } else {
+    if (same_bits(yi, yi_start)) return;
     if (segments > 1) {
       Mem::store(Y + i, yi);
     } else {
@@ -218,13 +229,12 @@ __device__ __forceinline__ void process_chunk(const GraphDesc& g, float2* __rest
         Mem::add(D + s[m], make_float2(-h * dx, -h * dy));
       }
     } else {
-      // ATOMIC commits differences, so it keeps the gathered values
-      float2 yj_old = yj;
+      // the gathered values: ATOMIC commits differences, both policies skip
+      // positions that did not change
+      const float2 yj_old = yj;
       float2 ys_old[KS];
-      if constexpr (MODE == kAtomic) {
 #pragma unroll
-        for (int m = 0; m < K; ++m) ys_old[m] = ys[m];
-      }
+      for (int m = 0; m < K; ++m) ys_old[m] = ys[m];
       {
         const float dx = yi.x - yj.x, dy = yi.y - yj.y;
         const float c = ca * (1.0f + g.beta * fast_rcp(1.0f + dx * dx + dy * dy));
@@ -262,16 +272,16 @@ __device__ __forceinline__ void process_chunk(const GraphDesc& g, float2* __rest
           if (s[m2] == s[m]) ys[m2] = cur;
       }
       if constexpr (MODE == kAtomic) {
-        Mem::add(Y + j, make_float2(yj.x - yj_old.x, yj.y - yj_old.y));
+        if (!same_bits(yj, yj_old)) Mem::add(Y + j, make_float2(yj.x - yj_old.x, yj.y - yj_old.y));
 #pragma unroll
         for (int m = 0; m < K; ++m)
-          if (!dup[m]) Mem::add(Y + s[m], make_float2(ys[m].x - ys_old[m].x, ys[m].y - ys_old[m].y));
+          if (!dup[m] && !same_bits(ys[m], ys_old[m]))
+            Mem::add(Y + s[m], make_float2(ys[m].x - ys_old[m].x, ys[m].y - ys_old[m].y));
       } else {
-        (void)yj_old;
-        Mem::store(Y + j, yj);
+        if (!same_bits(yj, yj_old)) Mem::store(Y + j, yj);
 #pragma unroll
         for (int m = 0; m < K; ++m)
-          if (!dup[m]) Mem::store(Y + s[m], ys[m]);
+          if (!dup[m] && !same_bits(ys[m], ys_old[m])) Mem::store(Y + s[m], ys[m]);
       }
     }
   }
@@ -279,7 +289,7 @@ __device__ __forceinline__ void process_chunk(const GraphDesc& g, float2* __rest
   commit_source<MODE, Mem>(Y, D, i, yi, yi_start, acc, segs);
 }
 
-// Graph of a global chunk index (tables are short; binary search).
+// Graph of a position inside a round (tables are short; binary search).
 __device__ __forceinline__ int find_graph(const GraphDesc* __restrict__ table, int G, int64_t c) {
   int lo = 0, hi = G - 1;
   while (lo < hi) {
@@ -294,17 +304,28 @@ __device__ __forceinline__ int find_graph(const GraphDesc* __restrict__ table, i
 
 // ------------------------------------------------------------- epoch kernels
 // One epoch of every graph in the table; lanes stride over all chunks.
+// With several graphs the index space is cut into rounds of round_size
+// positions; a round holds a slice of every graph (in proportion to its
+// chunk count), so that the lanes in flight at any moment spread over all
+// graphs as they would over each graph alone (bounded per-node concurrency).
 template <int K, int MODE, bool DEGREE, class Mem = GlobalMem>
-static __global__ void __launch_bounds__(256) epoch_global_kernel(const GraphDesc* __restrict__ table,
-                                                           int G, int64_t total_chunks,
-                                                           int32_t dt) {
+static __global__ void __launch_bounds__(256)
+    epoch_global_kernel(const GraphDesc* __restrict__ table, int G, int64_t total_index,
+                        int64_t round_size, int32_t dt) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < total_chunks;
+  for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < total_index;
        c += stride) {
-    const int gi = G == 1 ? 0 : find_graph(table, G, c);
+    int64_t r = 0, w = c;
+    if (G > 1) {
+      r = c / round_size;
+      w = c - r * round_size;
+    }
+    const int gi = G == 1 ? 0 : find_graph(table, G, w);
     const GraphDesc& g = table[gi];
+    const int64_t local = r * g.slice + (w - g.chunk_base);
+    if (local >= g.n_chunks) continue;  // past this graph's last chunk
     const int32_t t = g.t0 + dt;
-    process_chunk<K, MODE, DEGREE, Mem>(g, g.Y, g.D, c - g.chunk_base, t, eta_of(g, t));
+    process_chunk<K, MODE, DEGREE, Mem>(g, g.Y, g.D, g.chunk_offset + local, t, eta_of(g, t));
   }
 }
 
@@ -318,11 +339,17 @@ static __global__ void __launch_bounds__(1024) epoch_lds_kernel(const GraphDesc*
   const GraphDesc& g = table[graph_ids[blockIdx.x]];
   for (int32_t v = threadIdx.x; v < g.n; v += blockDim.x) sY[v] = g.Y[v];
   __syncthreads();
+  // only the first `lanes` threads work, so that each graph keeps its own
+  // bounded concurrency inside a shared launch
+  const int32_t lanes = g.lanes > 0 && g.lanes < static_cast<int32_t>(blockDim.x)
+                            ? g.lanes
+                            : static_cast<int32_t>(blockDim.x);
   for (int32_t ep = 0; ep < count; ++ep) {
     const int32_t t = g.t0 + dt + ep;
     const float eta = eta_of(g, t);
-    for (int64_t lc = threadIdx.x; lc < g.n_chunks; lc += blockDim.x)
-      process_chunk<K, MODE, DEGREE, LdsMem>(g, sY, nullptr, lc, t, eta);
+    if (static_cast<int32_t>(threadIdx.x) < lanes)
+      for (int64_t lc = threadIdx.x; lc < g.n_chunks; lc += lanes)
+        process_chunk<K, MODE, DEGREE, LdsMem>(g, sY, nullptr, lc, t, eta);
     __syncthreads();
   }
   for (int32_t v = threadIdx.x; v < g.n; v += blockDim.x) g.Y[v] = sY[v];

@@ -1,0 +1,617 @@
+// Continuous-batching layout server (the layout_server_* entry points of
+// include/snaplayout.h).
+//
+// Threads: callers submit, poll, wait and take under one mutex; a single
+// scheduler thread owns every HIP call after creation.  Per round the
+// scheduler
+//   1. admits queued jobs in arrival order while a slot is free and the job's
+//      device footprint fits the budget (device copy, validation, chunk
+//      table, seeded init);
+//   2. launches, on two streams, the LDS engine for newly admitted small jobs
+//      (all their epochs) and one multi-graph launch of the global engine
+//      that advances every other job by a slice of its current epoch (the
+//      slices share the round's edge budget);
+//   3. waits, advances epoch counters, and retires finished jobs (positions to
+//      host, device memory freed, latency recorded).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "common.hpp"
+#include "snaplayout.h"
+
+using namespace snap;
+
+namespace {
+
+double now_s() {
+  using clock = std::chrono::steady_clock;
+  return std::chrono::duration<double>(clock::now().time_since_epoch()).count();
+}
+
+constexpr int64_t kDefaultRoundEdges = 32ll << 20;
+constexpr int64_t kMinSliceEdges = 1ll << 18;
+
+struct Job {
+  int64_t id = 0;
+  int32_t n = 0, k = 0, epochs = 0;
+  uint64_t seed = 0;
+  int64_t nnz = 0;
+  std::vector<int32_t> row, col;  // host copy, dropped once on the device
+  std::vector<float> result;
+  int state = LAYOUT_JOB_QUEUED;
+  int err_code = LAYOUT_OK;
+  std::string error;
+  double t_submit = 0, t_done = 0;
+  // device side (scheduler thread only)
+  DeviceBuffers buf;
+  int64_t footprint = 0;
+  bool lds = false;
+  int32_t bundle = kDefaultBundle, hub = kDefaultBundle * kHubFactor;
+  int32_t lanes = 0;  // LDS engine: working lanes of the workgroup
+  int64_t chunk_cap = 0, n_chunks = 0;
+  GraphDesc desc{};
+  int32_t t = 0;          // epochs completed
+  int64_t chunk_pos = 0;  // chunks of the current epoch already processed
+};
+
+}  // namespace
+
+struct layout_server {
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Job*> queue;
+  std::unordered_map<int64_t, Job*> jobs;
+  std::vector<Job*> active;  // scheduler thread only
+  bool stop = false;
+  bool dead = false;  // a device error stopped the scheduler
+  std::string dead_msg;
+  std::thread thr;
+  layout_opts opts{};
+  int32_t mode_global = LAYOUT_HOGWILD_STORE, mode_lds = LAYOUT_ATOMIC;
+  int64_t budget = 0, in_use = 0, round_edges = kDefaultRoundEdges;
+  int32_t max_slots = 1;
+  int64_t next_id = 1;
+  int dev = 0;
+  hipStream_t stream = nullptr, side = nullptr;
+  GraphDesc* d_table = nullptr;
+  GraphDesc* d_table_lds = nullptr;
+  int32_t* d_ids = nullptr;
+  uint32_t* d_err = nullptr;
+  int lds_cap = 0;
+  // stats (under mu)
+  int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, rounds = 0;
+  double edge_updates = 0, busy_seconds = 0;
+  std::vector<double> latencies;
+};
+
+namespace {
+
+int64_t footprint_of(const layout_server_t* S, const Job& j, int32_t bundle, int32_t hub) {
+  const int64_t cap = j.nnz > 0 ? chunk_bound(j.nnz, bundle, hub) : 0;
+  // row_ptr, col, positions, chunk table, alias table (degree-weighted only)
+  int64_t b = 4 * (int64_t(j.n) + 1) + 4 * j.nnz + 8 * int64_t(j.n) + 8 * cap + 4;
+  if (S->opts.neg_weights == LAYOUT_NEG_DEGREE) b += 8 * int64_t(j.n);
+  return b;
+}
+
+void plan_job(const layout_server_t* S, Job& j) {
+  j.lds = S->opts.engine != LAYOUT_ENGINE_GLOBAL && lds_bytes_for(j.n) <= S->lds_cap;
+  const int32_t nz = static_cast<int32_t>(j.nnz);
+  if (j.lds) {
+    const int block =
+        S->opts.block_threads ? S->opts.block_threads : lds_lanes_for(j.n, S->opts.nodes_per_lane);
+    j.lanes = block;
+    j.bundle = S->opts.bundle_edges ? S->opts.bundle_edges : std::max(1, std::min(16, nz / (4 * block)));
+    j.hub = S->opts.hub_split_edges ? S->opts.hub_split_edges : std::max(1, nz);
+  } else {
+    j.bundle = S->opts.bundle_edges ? S->opts.bundle_edges : kDefaultBundle;
+    j.hub = S->opts.hub_split_edges ? S->opts.hub_split_edges : kHubFactor * j.bundle;
+  }
+  j.footprint = footprint_of(S, j, j.bundle, j.hub);
+}
+
+int jalloc(Job& j, void** p, size_t bytes, const char* what) {
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return hip_fail(e, what);
+  j.buf.add(*p, bytes);
+  return LAYOUT_OK;
+}
+
+// Device setup of an admitted job (scheduler thread).
+int setup_job(layout_server_t* S, Job& j) {
+  int32_t *row = nullptr, *col = nullptr, *cb = nullptr, *cs = nullptr;
+  float2* Y = nullptr;
+  uint32_t *thr = nullptr, *alias = nullptr;
+  j.chunk_cap = j.nnz > 0 ? chunk_bound(j.nnz, j.bundle, j.hub) : 0;
+  int rc;
+  if ((rc = jalloc(j, reinterpret_cast<void**>(&row), 4 * (size_t(j.n) + 1), "row_ptr")) ||
+      (rc = jalloc(j, reinterpret_cast<void**>(&col), 4 * size_t(j.nnz), "col")) ||
+      (rc = jalloc(j, reinterpret_cast<void**>(&Y), 8 * size_t(j.n), "positions")) ||
+      (rc = jalloc(j, reinterpret_cast<void**>(&cb), 4 * size_t(j.chunk_cap + 1), "chunk begin")) ||
+      (rc = jalloc(j, reinterpret_cast<void**>(&cs), 4 * size_t(j.chunk_cap), "chunk src")))
+    return rc;
+  hipError_t e = hipMemcpyAsync(row, j.row.data(), 4 * (size_t(j.n) + 1), hipMemcpyHostToDevice,
+                                S->stream);
+  if (e == hipSuccess && j.nnz > 0)
+    e = hipMemcpyAsync(col, j.col.data(), 4 * size_t(j.nnz), hipMemcpyHostToDevice, S->stream);
+  if (e != hipSuccess) return hip_fail(e, "copying a job");
+  if ((rc = validate_csr(S->stream, row, col, j.n, j.nnz, S->d_err)) != LAYOUT_OK) return rc;
+  if (j.nnz > 0 && (rc = build_chunk_table(S->stream, row, j.n, j.nnz, j.bundle, j.hub, cb, cs,
+                                           &j.n_chunks)) != LAYOUT_OK)
+    return rc;
+  if (S->opts.neg_weights == LAYOUT_NEG_DEGREE && j.nnz > 0) {
+    if ((rc = jalloc(j, reinterpret_cast<void**>(&thr), 4 * size_t(j.n), "alias thr")) ||
+        (rc = jalloc(j, reinterpret_cast<void**>(&alias), 4 * size_t(j.n), "alias")) ||
+        (rc = build_alias_table(S->stream, row, j.n, j.nnz, thr, alias)))
+      return rc;
+  }
+  launch_init_positions(S->stream, Y, j.n, j.seed);
+  GraphDesc& d = j.desc;
+  d = GraphDesc{};
+  d.row_ptr = row;
+  d.col = col;
+  d.chunk_begin = cb;
+  d.chunk_src = cs;
+  d.Y = Y;
+  d.thr = thr;
+  d.alias = alias;
+  d.nnz = j.nnz;
+  d.n = j.n;
+  d.hub = j.hub;
+  d.T = j.epochs;
+  d.seed = j.seed;
+  d.eta0 = S->opts.eta0;
+  d.alpha = S->opts.alpha;
+  d.beta = S->opts.beta;
+  d.gamma = S->opts.gamma;
+  d.sc = sampler_consts(j.n);
+  d.lanes = j.lds ? j.lanes : 0;
+  e = hipStreamSynchronize(S->stream);
+  if (e != hipSuccess) return hip_fail(e, "job setup");
+  // the host copy of the graph is no longer needed
+  std::vector<int32_t>().swap(j.row);
+  std::vector<int32_t>().swap(j.col);
+  return LAYOUT_OK;
+}
+
+void finish_job(layout_server_t* S, Job* j, int code, const std::string& msg) {
+  j->buf.free_all();
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->in_use -= j->footprint;
+  j->t_done = now_s();
+  if (code == LAYOUT_OK) {
+    j->state = LAYOUT_JOB_DONE;
+    S->completed += 1;
+    S->edge_updates += double(j->nnz / 2) * (1 + j->k) * j->epochs;
+    S->latencies.push_back(j->t_done - j->t_submit);
+  } else {
+    j->state = LAYOUT_JOB_FAILED;
+    j->err_code = code;
+    j->error = msg;
+    S->failed += 1;
+  }
+  S->cv_done.notify_all();
+}
+
+// One round over the active jobs; returns a HIP/ABI status.
+int run_round(layout_server_t* S) {
+  const int k = S->active.empty() ? 0 : S->active.front()->k;
+  std::vector<Job*> lds_jobs, glob_jobs;
+  for (Job* j : S->active) {
+    if (j->nnz == 0 || j->t >= j->epochs) continue;
+    if (j->lds)
+      lds_jobs.push_back(j);
+    else
+      glob_jobs.push_back(j);
+  }
+  // LDS jobs: all epochs in this round, one workgroup each (grouped by k)
+  std::vector<GraphDesc> lt;
+  std::vector<int32_t> ids;
+  int max_lds = 8;
+  for (Job* j : lds_jobs) {
+    GraphDesc d = j->desc;
+    d.n_chunks = j->n_chunks;
+    d.t0 = j->t;
+    ids.push_back(static_cast<int32_t>(lt.size()));
+    lt.push_back(d);
+    max_lds = std::max(max_lds, lds_bytes_for(j->n));
+  }
+  // global jobs: a slice of the current epoch each
+  std::vector<GraphDesc> gt;
+  std::vector<int64_t> slice(glob_jobs.size());
+  const int64_t share =
+      glob_jobs.empty() ? 0
+                        : std::max<int64_t>(kMinSliceEdges, S->round_edges / int64_t(glob_jobs.size()));
+  int64_t round_nodes = 0;
+  for (size_t q = 0; q < glob_jobs.size(); ++q) {
+    Job* j = glob_jobs[q];
+    round_nodes += j->n;
+    const double edges_per_chunk = double(j->nnz) / double(std::max<int64_t>(1, j->n_chunks));
+    const int64_t want = std::max<int64_t>(1, int64_t(double(share) / edges_per_chunk));
+    slice[q] = std::min(want, j->n_chunks - j->chunk_pos);
+    GraphDesc d = j->desc;
+    d.t0 = j->t;
+    d.chunk_offset = j->chunk_pos;
+    d.n_chunks = slice[q];
+    gt.push_back(d);
+  }
+  hipError_t e = hipSuccess;
+  int rc = LAYOUT_OK;
+  if (!lt.empty()) {
+    e = hipMemcpyAsync(S->d_table_lds, lt.data(), sizeof(GraphDesc) * lt.size(),
+                       hipMemcpyHostToDevice, S->side);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(S->d_ids, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice,
+                         S->side);
+    if (e != hipSuccess) return hip_fail(e, "uploading the LDS table");
+    if ((rc = allow_lds(k, max_lds)) != LAYOUT_OK) return rc;
+    LdsGroup lg;
+    lg.d_table = S->d_table_lds;
+    lg.d_ids = S->d_ids;
+    lg.blocks = static_cast<int>(lt.size());
+    lg.lds_bytes = max_lds;
+    lg.k = k;
+    lg.mode = S->mode_lds;
+    lg.degree = S->opts.neg_weights == LAYOUT_NEG_DEGREE;
+    int lds_block = 64;
+    for (Job* j : lds_jobs) lds_block = std::max(lds_block, j->lanes);
+    lg.block = lds_block;
+    // every LDS job runs all its remaining epochs in this round; one launch
+    // when they share the count, else one launch per job
+    int32_t count = 0;
+    for (Job* j : lds_jobs) count = std::max(count, j->epochs - j->t);
+    std::vector<int32_t> counts;
+    for (Job* j : lds_jobs) counts.push_back(j->epochs - j->t);
+    const bool uniform = std::all_of(counts.begin(), counts.end(),
+                                     [&](int32_t c) { return c == counts.front(); });
+    if (uniform) {
+      rc = launch_lds_epochs(S->side, lg, 0, count);
+    } else {
+      for (size_t q = 0; q < lds_jobs.size() && rc == LAYOUT_OK; ++q) {
+        LdsGroup one = lg;
+        one.d_ids = S->d_ids + q;
+        one.blocks = 1;
+        rc = launch_lds_epochs(S->side, one, 0, counts[q]);
+      }
+    }
+    if (rc != LAYOUT_OK) return rc;
+  }
+  if (!gt.empty()) {
+    GlobalGroup gg;
+    gg.d_table = S->d_table;
+    gg.G = static_cast<int>(gt.size());
+    for (const GraphDesc& d : gt) gg.total_chunks += d.n_chunks;
+    gg.k = k;
+    gg.mode = S->mode_global;
+    gg.degree = S->opts.neg_weights == LAYOUT_NEG_DEGREE;
+    gg.access = S->opts.access;
+    gg.block = S->opts.block_threads && S->opts.block_threads <= 256 ? S->opts.block_threads : 256;
+    gg.grid = S->opts.grid_blocks;
+    gg.max_lanes =
+        round_nodes / (S->opts.nodes_per_lane > 0 ? S->opts.nodes_per_lane : kNodesPerLane);
+    plan_rounds(gt, gg, int64_t(global_grid(gg)) * gg.block);
+    e = hipMemcpyAsync(S->d_table, gt.data(), sizeof(GraphDesc) * gt.size(), hipMemcpyHostToDevice,
+                       S->stream);
+    if (e != hipSuccess) return hip_fail(e, "uploading the round table");
+    rc = launch_global_epochs(S->stream, gg, 0, 1);
+    if (rc != LAYOUT_OK) return rc;
+  }
+  e = hipStreamSynchronize(S->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(S->side);
+  if (e != hipSuccess) return hip_fail(e, "running a round");
+  for (size_t q = 0; q < glob_jobs.size(); ++q) {
+    Job* j = glob_jobs[q];
+    j->chunk_pos += slice[q];
+    if (j->chunk_pos >= j->n_chunks) {
+      j->chunk_pos = 0;
+      j->t += 1;
+    }
+  }
+  for (Job* j : lds_jobs) j->t = j->epochs;
+  return LAYOUT_OK;
+}
+
+void scheduler(layout_server_t* S) {
+  (void)hipSetDevice(S->dev);
+  for (;;) {
+    std::vector<Job*> admit;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->active.empty(); });
+      if (S->stop) break;
+      while (!S->queue.empty() &&
+             int64_t(S->active.size() + admit.size()) < int64_t(S->max_slots)) {
+        Job* j = S->queue.front();
+        if (S->in_use + j->footprint > S->budget) break;  // arrival order: wait for memory
+        S->queue.pop_front();
+        S->in_use += j->footprint;
+        j->state = LAYOUT_JOB_RUNNING;
+        admit.push_back(j);
+      }
+    }
+    const double t0 = now_s();
+    for (Job* j : admit) {
+      g_last_error.clear();
+      const int rc = setup_job(S, *j);
+      if (rc != LAYOUT_OK) {
+        finish_job(S, j, rc, g_last_error);
+        if (rc == LAYOUT_E_DEVICE) {
+          std::lock_guard<std::mutex> lk(S->mu);
+          S->dead = true;
+          S->dead_msg = g_last_error;
+        }
+        continue;
+      }
+      S->active.push_back(j);
+    }
+    if (S->dead) break;
+    if (S->active.empty()) continue;
+    g_last_error.clear();
+    int rc = run_round(S);
+    if (rc != LAYOUT_OK) {
+      std::string msg = g_last_error;
+      for (Job* j : S->active) finish_job(S, j, rc, msg);
+      S->active.clear();
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->dead = true;
+      S->dead_msg = msg;
+      break;
+    }
+    // retire finished jobs
+    std::vector<Job*> still;
+    for (Job* j : S->active) {
+      if (j->t < j->epochs && j->nnz > 0) {
+        still.push_back(j);
+        continue;
+      }
+      j->result.resize(size_t(j->n) * 2);
+      hipError_t e = hipSuccess;
+      if (j->n > 0)
+        e = hipMemcpy(j->result.data(), j->desc.Y, sizeof(float2) * size_t(j->n),
+                      hipMemcpyDeviceToHost);
+      finish_job(S, j, e == hipSuccess ? LAYOUT_OK : hip_fail(e, "reading positions"),
+                 g_last_error);
+    }
+    S->active.swap(still);
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->rounds += 1;
+    S->busy_seconds += now_s() - t0;
+  }
+  // drain: fail whatever is left
+  for (Job* j : S->active) finish_job(S, j, LAYOUT_E_DEVICE, S->dead ? S->dead_msg : "server stopped");
+  S->active.clear();
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (Job* j : S->queue) {
+    j->state = LAYOUT_JOB_FAILED;
+    j->err_code = LAYOUT_E_DEVICE;
+    j->error = S->dead ? S->dead_msg : "server stopped";
+  }
+  S->queue.clear();
+  S->cv_done.notify_all();
+}
+
+}  // namespace
+
+extern "C" {
+
+int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t round_edges,
+                         const layout_opts* opts, layout_server_t** out) {
+  g_last_error.clear();
+  if (!out) return fail(LAYOUT_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (max_slots < 1 || hbm_budget_bytes < 0 || round_edges < 0)
+    return fail(LAYOUT_E_INVALID_ARG, "max_slots >= 1, budget >= 0, round_edges >= 0");
+  layout_opts o;
+  if (opts)
+    o = *opts;
+  else
+    layout_opts_init(&o);
+  if (o.update_mode < 0 || o.update_mode > 3)
+    return fail(LAYOUT_E_INVALID_ARG, "update_mode = %d", o.update_mode);
+  if (o.update_mode == LAYOUT_JACOBI)
+    return fail(LAYOUT_E_UNSUPPORTED, "the server runs the lock-free policies only");
+  if (o.neg_weights != LAYOUT_NEG_UNIFORM && o.neg_weights != LAYOUT_NEG_DEGREE)
+    return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
+  if (o.engine < 0 || o.engine > 2) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
+  if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g", o.gamma);
+  if (o.block_threads < 0 || o.block_threads > 1024 || (o.block_threads % 64) != 0 ||
+      o.bundle_edges < 0 || o.hub_split_edges < 0 || o.grid_blocks < 0 || o.nodes_per_lane < 0)
+    return fail(LAYOUT_E_INVALID_ARG, "bad launch option");
+  layout_server_t* S = new (std::nothrow) layout_server_t();
+  if (!S) return fail(LAYOUT_E_OOM, "host allocation");
+  S->opts = o;
+  S->mode_global = o.update_mode == LAYOUT_UPDATE_AUTO ? LAYOUT_HOGWILD_STORE : o.update_mode;
+  S->mode_lds = o.update_mode == LAYOUT_UPDATE_AUTO ? LAYOUT_ATOMIC : o.update_mode;
+  S->max_slots = max_slots;
+  S->round_edges = round_edges ? round_edges : kDefaultRoundEdges;
+  (void)hipGetDevice(&S->dev);
+  S->lds_cap = o.engine == LAYOUT_ENGINE_GLOBAL ? 0 : device_props().lds_per_block;
+  hipError_t e = hipSuccess;
+  if (hbm_budget_bytes == 0) {
+    size_t free_b = 0, total_b = 0;
+    e = hipMemGetInfo(&free_b, &total_b);
+    S->budget = int64_t(double(free_b) * 0.9);
+  } else {
+    S->budget = hbm_budget_bytes;
+  }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc(&S->d_table, sizeof(GraphDesc) * size_t(max_slots));
+  if (e == hipSuccess) e = hipMalloc(&S->d_table_lds, sizeof(GraphDesc) * size_t(max_slots));
+  if (e == hipSuccess) e = hipMalloc(&S->d_ids, sizeof(int32_t) * size_t(max_slots));
+  if (e == hipSuccess) e = hipMalloc(&S->d_err, sizeof(uint32_t));
+  if (e != hipSuccess) {
+    const int rc = hip_fail(e, "server setup");
+    layout_server_destroy(S);
+    return rc;
+  }
+  S->thr = std::thread(scheduler, S);
+  *out = S;
+  return LAYOUT_OK;
+}
+
+int layout_server_submit(layout_server_t* S, const int32_t* row_ptr, const int32_t* col_idx,
+                         int32_t n, int32_t k, int32_t epochs, uint64_t seed, int64_t* job_id) {
+  g_last_error.clear();
+  if (!S || !job_id || !row_ptr || n < 0)
+    return fail(LAYOUT_E_INVALID_ARG, "NULL server/job_id/row_ptr or n < 0");
+  if (k < 0 || k > 8) return fail(k < 0 ? LAYOUT_E_INVALID_ARG : LAYOUT_E_UNSUPPORTED, "k = %d", k);
+  if (epochs < 1) return fail(LAYOUT_E_INVALID_ARG, "epochs = %d", epochs);
+  const int32_t nnz = row_ptr[n];
+  if (nnz < 0 || (nnz > 0 && !col_idx)) return fail(LAYOUT_E_INVALID_ARG, "bad row_ptr[n] or col");
+  Job* j = new (std::nothrow) Job();
+  if (!j) return fail(LAYOUT_E_OOM, "host allocation");
+  j->n = n;
+  j->k = k;
+  j->epochs = epochs;
+  j->seed = seed;
+  j->nnz = nnz;
+  j->row.assign(row_ptr, row_ptr + n + 1);
+  if (nnz > 0) j->col.assign(col_idx, col_idx + nnz);
+  j->t_submit = now_s();
+  plan_job(S, *j);
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->dead) {
+    delete j;
+    return fail(LAYOUT_E_DEVICE, "server stopped: %s", S->dead_msg.c_str());
+  }
+  if (j->footprint > S->budget) {
+    S->rejected += 1;
+    const int64_t fp = j->footprint;
+    delete j;
+    return fail(LAYOUT_E_OOM, "job needs %lld bytes, budget is %lld", (long long)fp,
+                (long long)S->budget);
+  }
+  // the rounds of one server share k (one kernel instantiation per launch)
+  for (auto& kv : S->jobs)
+    if (kv.second->k != k && kv.second->state <= LAYOUT_JOB_RUNNING) {
+      delete j;
+      return fail(LAYOUT_E_UNSUPPORTED, "jobs in flight use k = %d", kv.second->k);
+    }
+  j->id = S->next_id++;
+  S->jobs[j->id] = j;
+  S->queue.push_back(j);
+  S->submitted += 1;
+  *job_id = j->id;
+  S->cv_work.notify_one();
+  return LAYOUT_OK;
+}
+
+int layout_server_poll(layout_server_t* S, int64_t job_id, int32_t* state) {
+  if (!S || !state) return fail(LAYOUT_E_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->jobs.find(job_id);
+  if (it == S->jobs.end()) return fail(LAYOUT_E_INVALID_ARG, "unknown job %lld", (long long)job_id);
+  *state = it->second->state;
+  return LAYOUT_OK;
+}
+
+int layout_server_wait(layout_server_t* S, int64_t job_id, double timeout_s) {
+  if (!S) return fail(LAYOUT_E_INVALID_ARG, "NULL server");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->jobs.find(job_id);
+  if (it == S->jobs.end()) return fail(LAYOUT_E_INVALID_ARG, "unknown job %lld", (long long)job_id);
+  Job* j = it->second;
+  auto done = [&] { return j->state == LAYOUT_JOB_DONE || j->state == LAYOUT_JOB_FAILED; };
+  if (timeout_s < 0) {
+    S->cv_done.wait(lk, done);
+  } else if (!S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) {
+    return fail(LAYOUT_E_INVALID_ARG, "timeout waiting for job %lld", (long long)job_id);
+  }
+  if (j->state == LAYOUT_JOB_FAILED) return fail(j->err_code, "%s", j->error.c_str());
+  return LAYOUT_OK;
+}
+
+int layout_server_take(layout_server_t* S, int64_t job_id, float* host_out, double* latency_s) {
+  if (!S) return fail(LAYOUT_E_INVALID_ARG, "NULL server");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->jobs.find(job_id);
+  if (it == S->jobs.end()) return fail(LAYOUT_E_INVALID_ARG, "unknown job %lld", (long long)job_id);
+  Job* j = it->second;
+  if (j->state == LAYOUT_JOB_FAILED) {
+    const int code = j->err_code;
+    const std::string msg = j->error;
+    S->jobs.erase(it);
+    delete j;
+    return fail(code, "%s", msg.c_str());
+  }
+  if (j->state != LAYOUT_JOB_DONE) return fail(LAYOUT_E_INVALID_ARG, "job not done");
+  if (host_out && !j->result.empty())
+    std::memcpy(host_out, j->result.data(), sizeof(float) * j->result.size());
+  if (latency_s) *latency_s = j->t_done - j->t_submit;
+  S->jobs.erase(it);
+  delete j;
+  return LAYOUT_OK;
+}
+
+int layout_server_get_stats(layout_server_t* S, layout_server_stats* st) {
+  if (!S || !st) return fail(LAYOUT_E_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  std::memset(st, 0, sizeof *st);
+  st->submitted = S->submitted;
+  st->completed = S->completed;
+  st->failed = S->failed;
+  st->rejected = S->rejected;
+  st->queued = int64_t(S->queue.size());
+  int64_t running = 0;
+  for (auto& kv : S->jobs) running += kv.second->state == LAYOUT_JOB_RUNNING ? 1 : 0;
+  st->running = running;
+  st->hbm_in_use = S->in_use;
+  st->hbm_budget = S->budget;
+  st->rounds = S->rounds;
+  st->edge_updates = S->edge_updates;
+  st->busy_seconds = S->busy_seconds;
+  if (!S->latencies.empty()) {
+    std::vector<double> l = S->latencies;
+    std::sort(l.begin(), l.end());
+    auto pct = [&](double p) {
+      const double pos = p * double(l.size() - 1);
+      const size_t lo = size_t(std::floor(pos)), hi = size_t(std::ceil(pos));
+      return l[lo] + (l[hi] - l[lo]) * (pos - double(lo));
+    };
+    st->p50_latency_s = pct(0.50);
+    st->p99_latency_s = pct(0.99);
+    double sum = 0;
+    for (double x : l) sum += x;
+    st->mean_latency_s = sum / double(l.size());
+  }
+  return LAYOUT_OK;
+}
+
+int layout_server_destroy(layout_server_t* S) {
+  if (!S) return LAYOUT_OK;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  if (S->thr.joinable()) S->thr.join();
+  for (auto& kv : S->jobs) {
+    kv.second->buf.free_all();
+    delete kv.second;
+  }
+  S->jobs.clear();
+  if (S->d_table) (void)hipFree(S->d_table);
+  if (S->d_table_lds) (void)hipFree(S->d_table_lds);
+  if (S->d_ids) (void)hipFree(S->d_ids);
+  if (S->d_err) (void)hipFree(S->d_err);
+  if (S->stream) (void)hipStreamDestroy(S->stream);
+  if (S->side) (void)hipStreamDestroy(S->side);
+  delete S;
+  return LAYOUT_OK;
+}
+
+}  // extern "C"

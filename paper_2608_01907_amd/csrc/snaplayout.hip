@@ -148,6 +148,7 @@ GlobalGroup global_group_of(const layout_t* L) {
   g.access = L->access;
   g.block = L->block;
   g.grid = L->opts.grid_blocks;
+  g.max_lanes = L->n / (L->opts.nodes_per_lane > 0 ? L->opts.nodes_per_lane : kNodesPerLane);
   g.jacobi_Y = L->host_desc.Y;
   g.jacobi_D = L->host_desc.D;
   g.jacobi_nodes = L->n;
@@ -262,8 +263,26 @@ int snap::global_grid(const GlobalGroup& g) {
     });
   });
   if (per_cu <= 0) per_cu = 4;
-  const int64_t want = std::max<int64_t>(1, div_up(g.total_chunks, g.block));
+  per_cu = std::min(per_cu, std::max(1, kLanesPerCU / g.block));
+  int64_t want = std::max<int64_t>(1, div_up(g.total_chunks, g.block));
+  if (g.max_lanes > 0) want = std::min(want, std::max<int64_t>(1, div_up(g.max_lanes, g.block)));
   return static_cast<int>(std::min<int64_t>(want, int64_t(per_cu) * device_props().cus));
+}
+
+void snap::plan_rounds(std::vector<GraphDesc>& table, GlobalGroup& g, int64_t lanes) {
+  int64_t total = 0;
+  for (const GraphDesc& d : table) total += d.n_chunks;
+  g.total_chunks = total;
+  // a pass of the grid covers about two rounds
+  const int64_t rounds = std::max<int64_t>(1, div_up(2 * total, std::max<int64_t>(1, lanes)));
+  int64_t base = 0;
+  for (GraphDesc& d : table) {
+    d.slice = div_up(d.n_chunks, rounds);
+    d.chunk_base = base;
+    base += d.slice;
+  }
+  g.round_size = std::max<int64_t>(1, base);
+  g.total_index = rounds * g.round_size;
 }
 
 int snap::launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t dt,
@@ -277,15 +296,17 @@ int snap::launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t
       return with_mode(g.mode, [&](auto mc) -> int {
         constexpr int MODE = decltype(mc)::value;
         for (int32_t ep = 0; ep < count; ++ep) {
+          const int64_t index = g.G > 1 ? g.total_index : g.total_chunks;
           if constexpr (MODE == kStore) {
             if (g.access == LAYOUT_ACCESS_CACHED) {
               hipLaunchKernelGGL((epoch_global_kernel<K, MODE, DEG, GlobalCachedMem>), dim3(grid),
-                                 dim3(g.block), 0, stream, g.d_table, g.G, g.total_chunks, dt + ep);
+                                 dim3(g.block), 0, stream, g.d_table, g.G, index, g.round_size,
+                                 dt + ep);
               continue;
             }
           }
           hipLaunchKernelGGL((epoch_global_kernel<K, MODE, DEG>), dim3(grid), dim3(g.block), 0,
-                             stream, g.d_table, g.G, g.total_chunks, dt + ep);
+                             stream, g.d_table, g.G, index, g.round_size, dt + ep);
           if constexpr (MODE == kJacobi) {
             hipLaunchKernelGGL(jacobi_apply_kernel, dim3(div_up(g.jacobi_nodes, 256)), dim3(256),
                                0, stream, g.jacobi_Y, g.jacobi_D, g.jacobi_nodes);
@@ -458,7 +479,8 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
   if (o.engine < 0 || o.engine > 2) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
   if (o.access != LAYOUT_ACCESS_COHERENT && o.access != LAYOUT_ACCESS_CACHED)
     return fail(LAYOUT_E_INVALID_ARG, "access = %d", o.access);
-  if (o.bundle_edges < 0 || o.block_threads < 0 || o.grid_blocks < 0 || o.hub_split_edges < 0)
+  if (o.bundle_edges < 0 || o.block_threads < 0 || o.grid_blocks < 0 || o.hub_split_edges < 0 ||
+      o.nodes_per_lane < 0)
     return fail(LAYOUT_E_INVALID_ARG, "negative launch option");
   if (o.block_threads > 1024 || (o.block_threads % 64) != 0)
     return fail(LAYOUT_E_INVALID_ARG, "block_threads = %d (multiple of 64, <= 1024)",
@@ -518,7 +540,7 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
                     : LAYOUT_ENGINE_GLOBAL;
   }
   if (L->engine == LAYOUT_ENGINE_LDS) {
-    L->block = o.block_threads ? o.block_threads : kLdsDefaultThreads;
+    L->block = o.block_threads ? o.block_threads : lds_lanes_for(n, o.nodes_per_lane);
     // enough chunks to keep every lane busy, each as long as possible
     const int64_t per_lane = std::max<int64_t>(1, L->nnz / (4 * L->block));
     L->bundle = o.bundle_edges ? o.bundle_edges : static_cast<int32_t>(std::min<int64_t>(16, per_lane));
@@ -610,6 +632,7 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
   g.thr = d_thr;
   g.alias = d_alias;
   g.chunk_base = 0;
+  g.slice = L->n_chunks;
   g.n_chunks = L->n_chunks;
   g.nnz = L->nnz;
   g.n = n;

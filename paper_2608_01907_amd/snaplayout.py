@@ -55,7 +55,7 @@ class layout_opts(ctypes.Structure):
         ("engine", ctypes.c_int32), ("start_epoch", ctypes.c_int32),
         ("bundle_edges", ctypes.c_int32), ("block_threads", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32), ("access", ctypes.c_int32),
-        ("hub_split_edges", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+        ("hub_split_edges", ctypes.c_int32), ("nodes_per_lane", ctypes.c_int32),
         ("init_pos", ctypes.c_void_p), ("stream", ctypes.c_void_p),
     ]
 
@@ -91,6 +91,24 @@ class layout_batch_info(ctypes.Structure):
         ("update_mode_lds", ctypes.c_int32), ("epochs_done", ctypes.c_int32),
     ]
 
+
+class layout_server_stats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+        ("failed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+        ("queued", ctypes.c_int64), ("running", ctypes.c_int64),
+        ("hbm_in_use", ctypes.c_int64), ("hbm_budget", ctypes.c_int64),
+        ("rounds", ctypes.c_int64),
+        ("edge_updates", ctypes.c_double), ("busy_seconds", ctypes.c_double),
+        ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
+        ("mean_latency_s", ctypes.c_double),
+    ]
+
+
+LAYOUT_JOB_QUEUED = 0
+LAYOUT_JOB_RUNNING = 1
+LAYOUT_JOB_DONE = 2
+LAYOUT_JOB_FAILED = 3
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -129,6 +147,17 @@ _SIGNATURES = {
     "layout_batch_autotune": (ctypes.c_int, [_vp, _i32, ctypes.c_char_p,
                                              ctypes.POINTER(_i32), ctypes.POINTER(_i32), _f32p]),
     "layout_batch_destroy": (None, [_vp]),
+    "layout_batch_get_positions_device": (ctypes.c_int, [_vp, _vp]),
+    "layout_batch_sync": (ctypes.c_int, [_vp]),
+    "layout_server_create": (ctypes.c_int, [_i64, _i32, _i64, ctypes.POINTER(layout_opts),
+                                            ctypes.POINTER(_vp)]),
+    "layout_server_submit": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _i32, _u64,
+                                            ctypes.POINTER(_i64)]),
+    "layout_server_poll": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(_i32)]),
+    "layout_server_wait": (ctypes.c_int, [_vp, _i64, ctypes.c_double]),
+    "layout_server_take": (ctypes.c_int, [_vp, _i64, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "layout_server_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(layout_server_stats)]),
+    "layout_server_destroy": (ctypes.c_int, [_vp]),
 }
 
 
@@ -321,6 +350,17 @@ def layout_batch_get_positions(h, g, n):
     return out
 
 
+def layout_batch_get_positions_device(h, dev_out):
+    p, on_dev = _ptr(dev_out)
+    if not on_dev:
+        raise LayoutError(LAYOUT_E_INVALID_ARG, "dev_out must be a device tensor")
+    _check(lib().layout_batch_get_positions_device(h, p))
+
+
+def layout_batch_sync(h):
+    _check(lib().layout_batch_sync(h))
+
+
 def layout_batch_debug_draws(h, g, epoch, nnz, k):
     out = np.zeros((max(nnz, 1), max(k, 1)), dtype=np.int32)
     _check(lib().layout_batch_debug_draws(h, g, epoch, out.ctypes.data))
@@ -345,6 +385,51 @@ def layout_batch_destroy(h):
     lib().layout_batch_destroy(h)
 
 
+# --------------------------------------------------------------- server
+def layout_server_create(hbm_budget_bytes=0, max_slots=64, round_edges=0, opts=None):
+    o = opts if opts is not None else layout_opts_init()
+    h = _vp()
+    _check(lib().layout_server_create(int(hbm_budget_bytes), int(max_slots), int(round_edges),
+                                      ctypes.byref(o), ctypes.byref(h)))
+    return h
+
+
+def layout_server_submit(h, row_ptr, col_idx, n, k, epochs, seed):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    jid = _i64()
+    _check(lib().layout_server_submit(h, rp.ctypes.data, ci.ctypes.data, n, k, epochs, seed,
+                                      ctypes.byref(jid)))
+    return jid.value
+
+
+def layout_server_poll(h, job):
+    st = _i32()
+    _check(lib().layout_server_poll(h, job, ctypes.byref(st)))
+    return st.value
+
+
+def layout_server_wait(h, job, timeout_s=-1.0):
+    _check(lib().layout_server_wait(h, job, float(timeout_s)))
+
+
+def layout_server_take(h, job, n):
+    out = np.zeros((max(n, 1), 2), dtype=np.float32)
+    lat = ctypes.c_double()
+    _check(lib().layout_server_take(h, job, out.ctypes.data, ctypes.byref(lat)))
+    return out[:n], lat.value
+
+
+def layout_server_get_stats(h) -> dict:
+    st = layout_server_stats()
+    _check(lib().layout_server_get_stats(h, ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in layout_server_stats._fields_}
+
+
+def layout_server_destroy(h):
+    _check(lib().layout_server_destroy(h))
+
+
 # --------------------------------------------------------- convenience
 class Layout:
     """One layout job: owns a handle; positions come back as numpy arrays."""
@@ -354,7 +439,7 @@ class Layout:
                  neg_weights=LAYOUT_NEG_UNIFORM, engine=LAYOUT_ENGINE_AUTO, eta0=1.0,
                  alpha=0.1, beta=8.0, gamma=2.0, init_pos=None, bundle_edges=0,
                  block_threads=0, grid_blocks=0, start_epoch=0, stream=None,
-                 hub_split_edges=0):
+                 hub_split_edges=0, nodes_per_lane=0):
         o = layout_opts_init()
         o.alpha, o.beta, o.gamma, o.eta0 = alpha, beta, gamma, eta0
         o.update_mode, o.neg_weights, o.engine = update_mode, neg_weights, engine
@@ -362,6 +447,7 @@ class Layout:
         o.bundle_edges, o.block_threads, o.grid_blocks = bundle_edges, block_threads, grid_blocks
         o.start_epoch = start_epoch
         o.hub_split_edges = hub_split_edges
+        o.nodes_per_lane = nodes_per_lane
         on_device = hasattr(row_ptr, "data_ptr") and row_ptr.is_cuda
         init_keep = None
         if init_pos is not None:
@@ -426,11 +512,13 @@ class BatchLayout:
 
     def __init__(self, graphs, k=5, epochs=50, *, update_mode=LAYOUT_UPDATE_AUTO,
                  engine=LAYOUT_ENGINE_AUTO, eta0=1.0, bundle_edges=0, hub_split_edges=0,
-                 block_threads=0, grid_blocks=0, neg_weights=LAYOUT_NEG_UNIFORM):
+                 block_threads=0, grid_blocks=0, neg_weights=LAYOUT_NEG_UNIFORM,
+                 nodes_per_lane=0):
         o = layout_opts_init()
         o.update_mode, o.engine, o.eta0 = update_mode, engine, eta0
         o.bundle_edges, o.hub_split_edges = bundle_edges, hub_split_edges
         o.block_threads, o.grid_blocks, o.neg_weights = block_threads, grid_blocks, neg_weights
+        o.nodes_per_lane = nodes_per_lane
         self.n = [int(g["n"]) for g in graphs]
         self.nnz = [int(np.asarray(g["row_ptr"])[-1]) for g in graphs]
         self.k, self.epochs = int(k), int(epochs)

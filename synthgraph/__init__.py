@@ -309,3 +309,74 @@ def small_sbm(n: int, blocks: int, mean_degree: float, seed: int = 0) -> Graph:
     p_in = min(1.0, 0.9 * mean_degree / max(bs - 1, 1))
     p_out = min(1.0, 0.1 * mean_degree / max(n - bs, 1))
     return sbm(n, blocks, p_in, p_out, seed)
+
+
+# ----------------------------------------------------- many-graph workloads
+def batch_member(index: int, seed: int = 0, n_range=(1_000, 200_000), deg_range=(10.0, 40.0),
+                 comm_size: float = 1300.0) -> Graph:
+    """Graph `index` of the batched workload: n log-uniform in n_range, mean
+    degree uniform in deg_range; even indices are block models, odd ones
+    Chung-Lu graphs (tau uniform in [2.1, 2.5]); communities of about
+    comm_size nodes, 90% intra-community edges."""
+    rng = np.random.default_rng([seed, index, 7])
+    n = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+    md = float(rng.uniform(*deg_range))
+    blocks = max(1, int(math.ceil(n / comm_size)))
+    sub = int(rng.integers(0, 2**31))
+    if index % 2 == 0:
+        g = sbm_fast(n, blocks, md, 0.9, seed=sub)
+    else:
+        tau = float(rng.uniform(2.1, 2.5))
+        m = int(round(n * md / 2))
+        g = chung_lu_communities(n, m, tau=tau, dmax=math.sqrt(2 * m), n_comm=blocks, intra=0.9,
+                                 sigma=1.0, seed=sub)
+    g.name = f"batch{seed}-{index}"
+    return g
+
+
+def served_member(index: int, seed: int = 0, n_range=(1_000, 2_000_000),
+                  mean_degree: float = 16.0, tau: float = 2.2) -> Graph:
+    """Graph `index` of the served stream's pool: n log-uniform in n_range,
+    Chung-Lu tau = 2.2, mean degree 16, log-normal communities of mean ~1.3k
+    nodes, 90% intra."""
+    rng = np.random.default_rng([seed, index, 11])
+    n = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+    m = int(round(n * mean_degree / 2))
+    g = chung_lu_communities(n, m, tau=tau, dmax=math.sqrt(2 * m),
+                             n_comm=max(1, int(round(n / 1300))), intra=0.9, sigma=1.0,
+                             seed=int(rng.integers(0, 2**31)))
+    g.name = f"served{seed}-{index}"
+    return g
+
+
+def _member_job(args):
+    kind, index, seed, kw = args
+    fn = batch_member if kind == "batch" else served_member
+    g = fn(index, seed, **kw)
+    return g.row_ptr, g.col, g.n, g.labels, g.name
+
+
+def many_graphs(kind: str, count: int, seed: int = 0, workers: int | None = None,
+                cache_dir: str | None = None, **kw) -> list[Graph]:
+    """Generates `count` members of a workload in a process pool (cached as one
+    .npz per member)."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    cache_dir = cache_dir or os.environ.get("SNAP_GRAPH_CACHE", "/tmp/snap_graphs")
+    os.makedirs(cache_dir, exist_ok=True)
+    tag = "" if not kw else "-" + "-".join(f"{k}{v}" for k, v in sorted(kw.items()))
+    paths = [os.path.join(cache_dir, f"{kind}{seed}{tag}-{q}.npz") for q in range(count)]
+    todo = [q for q in range(count) if not os.path.exists(paths[q])]
+    if todo:
+        workers = workers or max(1, min(16, os.cpu_count() or 1))
+        with ProcessPoolExecutor(workers) as ex:
+            for q, (rp, col, n, lab, name) in zip(
+                    todo, ex.map(_member_job, [(kind, q, seed, kw) for q in todo])):
+                tmp = paths[q] + ".tmp.npz"
+                np.savez(tmp, row_ptr=rp, col=col, n=np.int64(n), labels=lab)
+                os.replace(tmp, paths[q])
+    out = []
+    for q in range(count):
+        z = np.load(paths[q], allow_pickle=False)
+        out.append(Graph(z["row_ptr"], z["col"], int(z["n"]), z["labels"], f"{kind}{seed}-{q}"))
+    return out

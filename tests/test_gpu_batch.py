@@ -73,23 +73,36 @@ def test_batch_jacobi_equals_single_graph(mix):
 
 
 def test_batch_hogwild_quality_alone_and_in_mix(mix):
+    """Lock-free runs are not bit-reproducible, so each side is the mean over
+    two seeds (the same two seeds alone and in the mix)."""
     T = 40
-    with SL.BatchLayout(_desc(mix), k=5, epochs=T) as B:
-        B.run()
-        inmix = [B.positions(q) for q in range(len(mix))]
+    seeds = (100, 700)
+    inmix = {}
+    for s0 in seeds:
+        with SL.BatchLayout(_desc(mix, s0), k=5, epochs=T) as B:
+            B.run()
+            for q in range(len(mix)):
+                inmix[(q, s0)] = B.positions(q)
     for q, g in enumerate(mix):
         if g.nnz == 0:
-            assert np.array_equal(inmix[q], O.init_positions(g.n, 100 + q).astype(np.float32))
+            for s0 in seeds:
+                ref = O.init_positions(g.n, s0 + q).astype(np.float32)
+                assert np.array_equal(inmix[(q, s0)], ref)
             continue
-        assert np.all(np.isfinite(inmix[q]))
+        assert all(np.all(np.isfinite(inmix[(q, s0)])) for s0 in seeds)
         if g.n < 500:
             continue
-        with SL.Layout(g.row_ptr, g.col, g.n, k=5, epochs=T, seed=100 + q) as L:
-            L.run()
-            alone = L.positions()
-        qa = M.quality(g.row_ptr, g.col, alone, g.labels, sample=2000)
-        qm = M.quality(g.row_ptr, g.col, inmix[q], g.labels, sample=2000)
-        assert abs(qa["np"] - qm["np"]) <= 0.01 and abs(qa["si"] - qm["si"]) <= 0.01, (q, qa, qm)
+        qa, qm = [], []
+        for s0 in seeds:
+            with SL.Layout(g.row_ptr, g.col, g.n, k=5, epochs=T, seed=s0 + q) as L:
+                L.run()
+                alone = L.positions()
+            qa.append(M.quality(g.row_ptr, g.col, alone, g.labels, sample=2000))
+            qm.append(M.quality(g.row_ptr, g.col, inmix[(q, s0)], g.labels, sample=2000))
+        for key in ("np", "si"):
+            a_ = np.mean([x[key] for x in qa])
+            m_ = np.mean([x[key] for x in qm])
+            assert abs(a_ - m_) <= 0.01, (q, key, qa, qm)
 
 
 def test_batch_autotune_keeps_positions_and_runs_once(mix, tmp_path):

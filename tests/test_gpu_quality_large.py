@@ -1,0 +1,42 @@
+"""Final-layout quality of the lock-free GPU path at the workload sizes, against
+the oracle's references (tests/golden/quality_*.json, written by
+tests/golden/make_quality_golden.py from the oracle only): NP and SI within
+0.01 absolute on the same seeded node samples."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synthgraph as S
+from oracle import metrics as M
+
+pytestmark = pytest.mark.gpu
+
+SL = pytest.importorskip("paper_2608_01907_amd.snaplayout")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _check(name, maker):
+    ref = json.load(open(os.path.join(GOLDEN, f"quality_{name}.json")))
+    run0 = [r for r in ref["runs"] if r["seed"] == 0][0]
+    g = S.cached(name, maker)
+    with SL.Layout(g.row_ptr, g.col, g.n, k=ref["k"], epochs=ref["epochs"], seed=0) as L:
+        L.run()
+        Y = L.positions()
+        info = L.info()
+    assert np.all(np.isfinite(Y))
+    q_np = M.np_score(g.row_ptr, g.col, Y, sample=ref["np_sample"], seed=ref["metric_seed"])
+    q_si = M.si_score(Y, g.labels, sample=ref["si_sample"], seed=ref["metric_seed"])
+    print(f"{name}: gpu np {q_np:.4f} si {q_si:.4f} | oracle np {run0['np']:.4f} "
+          f"si {run0['si']:.4f} | grid {info['grid_blocks']}", flush=True)
+    assert abs(q_np - run0["np"]) <= 0.01
+    assert abs(q_si - run0["si"]) <= 0.01
+
+
+def test_quality_orkut_like_259k():
+    _check("orkut-like-259k", S.orkut_like)
+
+
+def test_quality_lj_like_4m():
+    _check("lj-like-4m", S.lj_like)
