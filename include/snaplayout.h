@@ -59,8 +59,10 @@ enum {
 enum {
     LAYOUT_ACCESS_COHERENT = 0, /* device-scope loads/stores: every lane sees the value last
                                    written anywhere on the device */
-    LAYOUT_ACCESS_CACHED = 1    /* plain loads/stores through the per-XCD L2 (HOGWILD_STORE
+    LAYOUT_ACCESS_CACHED = 1,   /* plain loads/stores through the per-XCD L2 (HOGWILD_STORE
                                    only); writes of other XCDs show up after eviction */
+    LAYOUT_ACCESS_CACHED_READS = 2 /* plain loads (may hit a line another XCD has since
+                                   written), device-scope stores (HOGWILD_STORE only) */
 };
 
 /* Distribution of the negatives. */
@@ -90,7 +92,7 @@ typedef struct layout_opts {
     int32_t block_threads;    /* threads per workgroup; 0 = automatic (see nodes_per_lane) */
     int32_t grid_blocks;      /* workgroups of the epoch kernel; 0 = automatic: at most one
                                  256-lane workgroup per CU and n / nodes_per_lane lanes */
-    int32_t access;           /* LAYOUT_ACCESS_COHERENT (default) / LAYOUT_ACCESS_CACHED */
+    int32_t access;           /* LAYOUT_ACCESS_COHERENT (default) / _CACHED / _CACHED_READS */
     int32_t hub_split_edges;  /* rows with more edges are split into segments of this many
                                  edges, one lane each; 0 = default (4 * bundle_edges on the
                                  global engine, never on the LDS engine) */

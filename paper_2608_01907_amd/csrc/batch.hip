@@ -103,6 +103,10 @@ int build_global_chunks(layout_batch_t* B) {
     total += nc;
   }
   B->gg.total_chunks = total;
+  std::vector<GraphDesc> table;
+  for (int32_t g : B->global_ids)
+    if (B->nnz[g] > 0) table.push_back(B->desc[g]);
+  B->gg.max_lanes = table.empty() ? 0 : fair_lanes(table, B->opts.nodes_per_lane);
   return LAYOUT_OK;
 }
 
@@ -240,7 +244,7 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
       o.nodes_per_lane < 0 || o.block_threads > 1024 || (o.block_threads % 64) != 0)
     return fail(LAYOUT_E_INVALID_ARG, "bad launch option");
   if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g (must be > 1)", o.gamma);
-  if (o.access != LAYOUT_ACCESS_COHERENT && o.access != LAYOUT_ACCESS_CACHED)
+  if (o.access < LAYOUT_ACCESS_COHERENT || o.access > LAYOUT_ACCESS_CACHED_READS)
     return fail(LAYOUT_E_INVALID_ARG, "access = %d", o.access);
 
   layout_batch_t* B = new (std::nothrow) layout_batch_t();
@@ -256,7 +260,7 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
   const bool jacobi = o.update_mode == LAYOUT_JACOBI;
   B->mode_global = o.update_mode == LAYOUT_UPDATE_AUTO ? LAYOUT_HOGWILD_STORE : o.update_mode;
   B->mode_lds = o.update_mode == LAYOUT_UPDATE_AUTO ? LAYOUT_ATOMIC : o.update_mode;
-  if (B->mode_global != LAYOUT_HOGWILD_STORE && o.access == LAYOUT_ACCESS_CACHED)
+  if (B->mode_global != LAYOUT_HOGWILD_STORE && o.access != LAYOUT_ACCESS_COHERENT)
     return bail(fail(LAYOUT_E_UNSUPPORTED, "cached access needs HOGWILD_STORE"));
   B->bundle = o.bundle_edges ? o.bundle_edges : kDefaultBundle;
   B->hub = o.hub_split_edges ? o.hub_split_edges : kHubFactor * B->bundle;
@@ -427,11 +431,6 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
   B->gg.degree = degree;
   B->gg.access = o.access;
   B->gg.block = o.block_threads ? o.block_threads : 256;
-  {
-    int64_t gnodes = 0;
-    for (int32_t g : B->global_ids) gnodes += B->n[g];
-    B->gg.max_lanes = gnodes / (o.nodes_per_lane > 0 ? o.nodes_per_lane : kNodesPerLane);
-  }
   B->gg.jacobi_Y = B->d_Y;
   B->gg.jacobi_D = B->d_D;
   B->gg.jacobi_nodes = B->nodes;

@@ -95,6 +95,9 @@ int lds_bytes_for(int32_t n);
 // rounds for a launch of `lanes` lanes: sets each entry's slice/chunk_base and
 // the group's round_size/total_index/total_chunks.
 void plan_rounds(std::vector<GraphDesc>& table, GlobalGroup& g, int64_t lanes);
+// Lanes of a multi-graph launch such that every graph g, which receives lanes
+// in proportion to its chunk count, has at most n_g / nodes_per_lane of them.
+int64_t fair_lanes(const std::vector<GraphDesc>& table, int nodes_per_lane);
 int global_grid(const GlobalGroup& g);  // resolved grid size
 int launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t dt, int32_t count);
 int launch_lds_epochs(hipStream_t stream, const LdsGroup& g, int32_t dt, int32_t count);

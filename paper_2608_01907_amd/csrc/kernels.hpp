@@ -78,6 +78,12 @@ struct GlobalCachedMem {
   static __device__ __forceinline__ void store(float2* p, float2 v) { *p = v; }
 };
 
+// Plain loads through the L2, device-scope stores (STORE policy only).
+struct GlobalCachedReadMem {
+  static __device__ __forceinline__ float2 load(const float2* p) { return *p; }
+  static __device__ __forceinline__ void store(float2* p, float2 v) { GlobalMem::store(p, v); }
+};
+
 // LDS-resident positions (one workgroup owns the whole graph).
 struct LdsMem {
   static __device__ __forceinline__ float2 load(const float2* p) {

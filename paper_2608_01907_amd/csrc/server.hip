@@ -235,10 +235,8 @@ int run_round(layout_server_t* S) {
   const int64_t share =
       glob_jobs.empty() ? 0
                         : std::max<int64_t>(kMinSliceEdges, S->round_edges / int64_t(glob_jobs.size()));
-  int64_t round_nodes = 0;
   for (size_t q = 0; q < glob_jobs.size(); ++q) {
     Job* j = glob_jobs[q];
-    round_nodes += j->n;
     const double edges_per_chunk = double(j->nnz) / double(std::max<int64_t>(1, j->n_chunks));
     const int64_t want = std::max<int64_t>(1, int64_t(double(share) / edges_per_chunk));
     slice[q] = std::min(want, j->n_chunks - j->chunk_pos);
@@ -300,8 +298,7 @@ int run_round(layout_server_t* S) {
     gg.access = S->opts.access;
     gg.block = S->opts.block_threads && S->opts.block_threads <= 256 ? S->opts.block_threads : 256;
     gg.grid = S->opts.grid_blocks;
-    gg.max_lanes =
-        round_nodes / (S->opts.nodes_per_lane > 0 ? S->opts.nodes_per_lane : kNodesPerLane);
+    gg.max_lanes = fair_lanes(gt, S->opts.nodes_per_lane);
     plan_rounds(gt, gg, int64_t(global_grid(gg)) * gg.block);
     e = hipMemcpyAsync(S->d_table, gt.data(), sizeof(GraphDesc) * gt.size(), hipMemcpyHostToDevice,
                        S->stream);
@@ -427,6 +424,11 @@ int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t ro
     return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
   if (o.engine < 0 || o.engine > 2) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
   if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g", o.gamma);
+  if (o.access < LAYOUT_ACCESS_COHERENT || o.access > LAYOUT_ACCESS_CACHED_READS)
+    return fail(LAYOUT_E_INVALID_ARG, "access = %d", o.access);
+  if (o.access != LAYOUT_ACCESS_COHERENT && o.update_mode != LAYOUT_UPDATE_AUTO &&
+      o.update_mode != LAYOUT_HOGWILD_STORE)
+    return fail(LAYOUT_E_UNSUPPORTED, "cached access needs HOGWILD_STORE");
   if (o.block_threads < 0 || o.block_threads > 1024 || (o.block_threads % 64) != 0 ||
       o.bundle_edges < 0 || o.hub_split_edges < 0 || o.grid_blocks < 0 || o.nodes_per_lane < 0)
     return fail(LAYOUT_E_INVALID_ARG, "bad launch option");

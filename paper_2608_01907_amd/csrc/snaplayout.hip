@@ -285,6 +285,19 @@ void snap::plan_rounds(std::vector<GraphDesc>& table, GlobalGroup& g, int64_t la
   g.total_index = rounds * g.round_size;
 }
 
+int64_t snap::fair_lanes(const std::vector<GraphDesc>& table, int nodes_per_lane) {
+  const int npl = nodes_per_lane > 0 ? nodes_per_lane : kNodesPerLane;
+  int64_t total = 0;
+  for (const GraphDesc& d : table) total += d.n_chunks;
+  double best = -1.0;
+  for (const GraphDesc& d : table) {
+    if (d.n_chunks <= 0) continue;
+    const double cap = double(d.n) / npl * double(total) / double(d.n_chunks);
+    if (best < 0 || cap < best) best = cap;
+  }
+  return best < 1.0 ? 1 : static_cast<int64_t>(best);
+}
+
 int snap::launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t dt,
                                int32_t count) {
   if (g.total_chunks == 0 || count <= 0) return LAYOUT_OK;
@@ -302,6 +315,12 @@ int snap::launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t
               hipLaunchKernelGGL((epoch_global_kernel<K, MODE, DEG, GlobalCachedMem>), dim3(grid),
                                  dim3(g.block), 0, stream, g.d_table, g.G, index, g.round_size,
                                  dt + ep);
+              continue;
+            }
+            if (g.access == LAYOUT_ACCESS_CACHED_READS) {
+              hipLaunchKernelGGL((epoch_global_kernel<K, MODE, DEG, GlobalCachedReadMem>),
+                                 dim3(grid), dim3(g.block), 0, stream, g.d_table, g.G, index,
+                                 g.round_size, dt + ep);
               continue;
             }
           }
@@ -477,7 +496,7 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
   if (o.start_epoch < 0 || o.start_epoch > epochs)
     return fail(LAYOUT_E_INVALID_ARG, "start_epoch = %d", o.start_epoch);
   if (o.engine < 0 || o.engine > 2) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
-  if (o.access != LAYOUT_ACCESS_COHERENT && o.access != LAYOUT_ACCESS_CACHED)
+  if (o.access < LAYOUT_ACCESS_COHERENT || o.access > LAYOUT_ACCESS_CACHED_READS)
     return fail(LAYOUT_E_INVALID_ARG, "access = %d", o.access);
   if (o.bundle_edges < 0 || o.block_threads < 0 || o.grid_blocks < 0 || o.hub_split_edges < 0 ||
       o.nodes_per_lane < 0)
@@ -556,7 +575,7 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
                 ? o.update_mode
                 : (L->engine == LAYOUT_ENGINE_LDS ? LAYOUT_ATOMIC : LAYOUT_HOGWILD_STORE);
   L->access = o.access;
-  if (L->access == LAYOUT_ACCESS_CACHED &&
+  if (L->access != LAYOUT_ACCESS_COHERENT &&
       (L->mode != LAYOUT_HOGWILD_STORE || L->engine != LAYOUT_ENGINE_GLOBAL))
     return bail(fail(LAYOUT_E_UNSUPPORTED,
                      "cached access is only defined for HOGWILD_STORE on the global engine"));
@@ -837,9 +856,9 @@ int layout_bench_gather(layout_t* L, int32_t mode, int32_t access, int32_t reps,
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (!ms || reps < 1) return fail(LAYOUT_E_INVALID_ARG, "ms NULL or reps < 1");
   if (mode != kStore && mode != kAtomic) return fail(LAYOUT_E_INVALID_ARG, "mode %d", mode);
-  if (access != LAYOUT_ACCESS_COHERENT && access != LAYOUT_ACCESS_CACHED)
+  if (access < LAYOUT_ACCESS_COHERENT || access > LAYOUT_ACCESS_CACHED_READS)
     return fail(LAYOUT_E_INVALID_ARG, "access %d", access);
-  if (access == LAYOUT_ACCESS_CACHED && mode != kStore)
+  if (access != LAYOUT_ACCESS_COHERENT && mode != kStore)
     return fail(LAYOUT_E_UNSUPPORTED, "cached access only with the store policy");
   if (L->nnz == 0) {
     *ms = 0.f;
@@ -866,6 +885,10 @@ int layout_bench_gather(layout_t* L, int32_t mode, int32_t access, int32_t reps,
           if (access == LAYOUT_ACCESS_CACHED) {
             if constexpr (MODE == kStore)
               hipLaunchKernelGGL((gather_rmw_kernel<K, MODE, GlobalCachedMem>), dim3(grid),
+                                 dim3(256), 0, L->stream, L->d_table, L->n_chunks);
+          } else if (access == LAYOUT_ACCESS_CACHED_READS) {
+            if constexpr (MODE == kStore)
+              hipLaunchKernelGGL((gather_rmw_kernel<K, MODE, GlobalCachedReadMem>), dim3(grid),
                                  dim3(256), 0, L->stream, L->d_table, L->n_chunks);
           } else {
             hipLaunchKernelGGL((gather_rmw_kernel<K, MODE, GlobalMem>), dim3(grid), dim3(256), 0,

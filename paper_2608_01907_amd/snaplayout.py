@@ -28,6 +28,7 @@ LAYOUT_JACOBI = 2
 LAYOUT_UPDATE_AUTO = 3
 LAYOUT_ACCESS_COHERENT = 0
 LAYOUT_ACCESS_CACHED = 1
+LAYOUT_ACCESS_CACHED_READS = 2
 LAYOUT_NEG_UNIFORM = 0
 LAYOUT_NEG_DEGREE = 1
 LAYOUT_ENGINE_AUTO = 0
