@@ -253,15 +253,18 @@ def bench_batched(args):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    log("[bench] warm-up done")
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for q in range(args.steps):
         step()
+        log(f"[bench] step {q + 1}/{args.steps}")
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     value = edges * (1 + k) * T / dt
     hb = SL.layout_batch_create(desc, k, T, opts(), 1)
     replay_ms = SL.layout_batch_run_timed(hb)
     SL.layout_batch_destroy(hb)
+    log(f"[bench] batched {dt * 1e3:.1f} ms/step, replay {replay_ms:.1f} ms; timing the plain path")
     # plain path: one graph per launch sequence, same graphs
     t0 = time.perf_counter()
     for q, g in enumerate(gs):
@@ -269,6 +272,9 @@ def bench_batched(args):
         SL.layout_epoch(hp, T)
         SL.layout_sync(hp)
         SL.layout_destroy(hp)
+        if (q + 1) % 64 == 0:
+            log(f"[bench] plain path: {q + 1}/{len(gs)} graphs, "
+                f"{time.perf_counter() - t0:.1f}s")
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
     plain_value = edges * (1 + k) * T / plain_s
@@ -316,6 +322,7 @@ def bench_served(args):
     # plain service time (FIFO, one job at a time) on a sample of the stream
     svc = run_plain(picks[: min(len(picks), 24)])
     mean_svc = float(svc.mean())
+    log(f"[bench] plain mean service time {mean_svc * 1e3:.1f} ms")
     results = {}
     for rho in args.rho:
         lam = rho / mean_svc
@@ -328,9 +335,12 @@ def bench_served(args):
                 time.sleep(min(0.0005, ta - (time.perf_counter() - t_start)))
             g = pool[q]
             ids.append((SL.layout_server_submit(srv, g.row_ptr, g.col, g.n, k, T, int(q)), g.n))
-        for jid, n in ids:
+        log(f"[bench] rho {rho}: {len(ids)} jobs submitted")
+        for q, (jid, n) in enumerate(ids):
             SL.layout_server_wait(srv, jid, 600.0)
             SL.layout_server_take(srv, jid, n)
+            if (q + 1) % 50 == 0:
+                log(f"[bench] rho {rho}: {q + 1}/{len(ids)} jobs done")
         wall = time.perf_counter() - t_start
         st = SL.layout_server_get_stats(srv)
         SL.layout_server_destroy(srv)

@@ -59,10 +59,14 @@ enum {
 enum {
     LAYOUT_ACCESS_COHERENT = 0, /* device-scope loads/stores: every lane sees the value last
                                    written anywhere on the device */
-    LAYOUT_ACCESS_CACHED = 1,   /* plain loads/stores through the per-XCD L2 (HOGWILD_STORE
+    LAYOUT_ACCESS_CACHED = 1    /* plain loads/stores through the per-XCD L2 (HOGWILD_STORE
                                    only); writes of other XCDs show up after eviction */
-    LAYOUT_ACCESS_CACHED_READS = 2 /* plain loads (may hit a line another XCD has since
-                                   written), device-scope stores (HOGWILD_STORE only) */
+};
+
+/* Initial layout when no positions are given. */
+enum {
+    LAYOUT_INIT_UNIFORM = 0, /* seeded uniform in [-sqrt(n), sqrt(n)]^2 */
+    LAYOUT_INIT_PMDS = 1     /* Pivot MDS (Sec. 4.1), see layout_pmds */
 };
 
 /* Distribution of the negatives. */
@@ -92,7 +96,7 @@ typedef struct layout_opts {
     int32_t block_threads;    /* threads per workgroup; 0 = automatic (see nodes_per_lane) */
     int32_t grid_blocks;      /* workgroups of the epoch kernel; 0 = automatic: at most one
                                  256-lane workgroup per CU and n / nodes_per_lane lanes */
-    int32_t access;           /* LAYOUT_ACCESS_COHERENT (default) / _CACHED / _CACHED_READS */
+    int32_t access;           /* LAYOUT_ACCESS_COHERENT (default) / LAYOUT_ACCESS_CACHED */
     int32_t hub_split_edges;  /* rows with more edges are split into segments of this many
                                  edges, one lane each; 0 = default (4 * bundle_edges on the
                                  global engine, never on the LDS engine) */
@@ -101,15 +105,43 @@ typedef struct layout_opts {
                                  lanes = n / nodes_per_lane in [64, 256] on the LDS engine, so
                                  that few concurrent updates hit one node (Sec. 3.4);
                                  0 = default 32 */
+    int32_t init_mode;        /* LAYOUT_INIT_UNIFORM (default) / LAYOUT_INIT_PMDS; ignored
+                                 when init_pos is given */
+    int32_t pmds_pivots;      /* pivots of LAYOUT_INIT_PMDS, 1..64; 0 = default 50 */
     const float *init_pos;    /* n*2 initial positions (host, or device when the
-                                 inputs are on the device); NULL = seeded uniform
-                                 init in [-sqrt(n), sqrt(n)]^2 */
+                                 inputs are on the device); NULL = init_mode */
     void *stream;             /* hipStream_t for all work of the handle; NULL = a
                                  stream owned by the library */
 } layout_opts;
 
 /* Fills *opts with the defaults listed above. */
 void layout_opts_init(layout_opts *opts);
+
+/* Pivot MDS layout of one graph (the initial layout of Sec. 4.1; Brandes and
+ * Pich, GD 2006), also used by layout_create_ex when init_mode is
+ * LAYOUT_INIT_PMDS.  Definition: the first pivot is the node of largest degree
+ * (smallest index on ties); each further pivot is the node of the first
+ * pivot's connected component farthest (in hops) from the pivots chosen so far
+ * (smallest index on ties); min(pivots, component size) pivots.  With d_ij the
+ * hop distance from pivot j to node i and C the double-centred matrix
+ * -1/2 (d_ij^2 - column mean - row mean + grand mean) over the component,
+ * v1, v2 the eigenvectors of the two largest eigenvalues mu1, mu2 of C^T C,
+ * the component's coordinates are s (C v1 / mu1^(1/4), C v2 / mu2^(1/4)),
+ * with s the least-squares fit of |y_i - y_pivot| to d_ij (an axis with
+ * mu <= 1e-6 mu1 is 0).  Nodes outside the
+ * component take the seeded uniform draws of the plain init (seed) in
+ * [-R, R]^2, R = the largest |coordinate| of the component layout.
+ * row_ptr/col_idx: host arrays, or device arrays if inputs_on_device = 1 (a
+ * valid CSR as for layout_create; validated on the device).  pivots: 1..64,
+ * 0 = 50.  Y_out: host n*2 FP32 (x, y interleaved).  pivots_out (nullable):
+ * host [pivots], the pivots in order of choice.  dist_out (nullable): host
+ * [pivots * n] int32, row j = hop distances from pivot j (-1 = unreachable).
+ * *pivots_used (nullable) = pivots taken.  Blocking; device memory is
+ * allocated for the call (pivots x n int32 distances) and freed before return.
+ * Errors: E_INVALID_ARG, E_BAD_GRAPH, E_OOM, E_DEVICE. */
+int layout_pmds(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t pivots,
+                uint64_t seed, int32_t inputs_on_device, float *Y_out, int32_t *pivots_out,
+                int32_t *dist_out, int32_t *pivots_used);
 
 /* Creates a layout job with default options.  Validates the CSR on the device,
  * builds the chunk table, initialises positions.  Returns when the job is
@@ -170,6 +202,30 @@ typedef struct layout_info {
 } layout_info;
 
 int layout_get_info(const layout_t *L, layout_info *info);
+
+/* ---------------------------------------------------------- energy monitors
+ * The t-forces of Table 1 are the negative gradients (Eq. (2)) of the pair
+ * potentials U_a(q) = alpha (q/2 + (beta/2) ln(1+q)) and
+ * U_r(q) = (1+q)^(1-gamma) / (2 (gamma-1)) of the squared distance q.  Both
+ * calls read the handle's current positions after the epochs already
+ * launched, accumulate in FP64 (terms in FP32), and return when the values
+ * are on the host.  The first call allocates 16 bytes of device memory that
+ * the handle keeps. */
+
+/* Energy that the samples of one epoch see (Sec. 3.3): *attr_out = sum over
+ * the directed edges (i, j) of U_a(|y_i - y_j|^2); *rep_out = sum over the
+ * directed edges e = (i, .) and the k negatives s drawn for e in epoch
+ * `epoch` (the same draws as the epoch kernel) of U_r(|y_i - y_s|^2).
+ * O(nnz (1 + k)).  Errors: NULL outputs or epoch < 0 -> E_INVALID_ARG. */
+int layout_sampled_energy(layout_t *L, int32_t epoch, double *attr_out, double *rep_out);
+
+/* The degree-weighted objective that the sampling realises in expectation
+ * (Eq. (4) with the weight of Sec. 3.3): *attr_out as above (each undirected
+ * edge counted in both directions), *rep_out = k/(n-1) * sum over unordered
+ * pairs {i, j} of (d_i + d_j) U_r(|y_i - y_j|^2).  O(n^2): meant for graphs of
+ * up to a few hundred thousand nodes.  The mean of layout_sampled_energy over
+ * epochs at fixed positions tends to this value.  Errors as above. */
+int layout_effective_energy(layout_t *L, double *attr_out, double *rep_out);
 
 /* Writes the k negatives the epoch kernels draw for every directed edge in
  * epoch t (host array nnz*k, int32, edge-major).  Does not change positions. */

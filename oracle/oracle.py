@@ -65,6 +65,9 @@ def lib():
         L.oracle_philox_bulk.restype = None
         L.oracle_init_positions.argtypes = [ctypes.c_int64, ctypes.c_uint64, _f64p]
         L.oracle_init_positions.restype = None
+        L.oracle_init_positions_scaled.argtypes = [ctypes.c_int64, ctypes.c_uint64,
+                                                   ctypes.c_float, _f64p]
+        L.oracle_init_positions_scaled.restype = None
         L.oracle_alias_build.argtypes = [_i64p, ctypes.c_int64, _u32p, _u32p]
         L.oracle_alias_build.restype = ctypes.c_int
         L.oracle_draw_negatives.argtypes = [
@@ -88,11 +91,11 @@ def lib():
         L.oracle_sampled_energy.argtypes = [
             _i32p, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
             ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _u32p, _u32p,
-            _f64p]
+            _f64p, _f64p]
         L.oracle_sampled_energy.restype = ctypes.c_double
         L.oracle_effective_energy.argtypes = [
             _i32p, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
-            ctypes.c_double, _f64p]
+            ctypes.c_double, _f64p, _f64p]
         L.oracle_effective_energy.restype = ctypes.c_double
         L.oracle_threaded_run.argtypes = [
             _i32p, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
@@ -133,6 +136,13 @@ def init_positions(n, seed):
     """Seeded uniform init in [-sqrt(n), sqrt(n)]^2 (FP32 values, widened)."""
     Y = np.zeros(2 * max(n, 1), dtype=np.float64)
     lib().oracle_init_positions(int(n), int(seed), Y)
+    return Y[: 2 * n].reshape(n, 2)
+
+
+def init_positions_scaled(n, seed, scale):
+    """The same uniform draws in [-scale, scale]^2 (scale taken as FP32)."""
+    Y = np.zeros(2 * max(n, 1), dtype=np.float64)
+    lib().oracle_init_positions_scaled(int(n), int(seed), float(scale), Y)
     return Y[: 2 * n].reshape(n, 2)
 
 
@@ -202,18 +212,26 @@ def jacobi_epoch(row_ptr, col, n, k, t, T, seed, Y, mode=NEG_UNIFORM, thr=None, 
 
 
 def sampled_energy(row_ptr, col, n, k, t, seed, Y, mode=NEG_UNIFORM, thr=None, alias=None,
-                   alpha=ALPHA, beta=BETA, gamma=GAMMA):
+                   alpha=ALPHA, beta=BETA, gamma=GAMMA, parts=False):
+    """Energy seen by the samples of epoch t at fixed Y (Sec. 3.3); with
+    parts=True the pair (attraction, repulsion)."""
     rp, c = _csr(row_ptr, col)
     thr, alias = _tables(n, thr, alias)
     Yin = np.ascontiguousarray(np.asarray(Y, dtype=np.float64).reshape(-1))
-    return lib().oracle_sampled_energy(rp, c, int(n), int(k), int(t), int(seed), alpha, beta,
-                                       gamma, int(mode), thr, alias, Yin)
+    out = np.zeros(2, dtype=np.float64)
+    total = lib().oracle_sampled_energy(rp, c, int(n), int(k), int(t), int(seed), alpha, beta,
+                                        gamma, int(mode), thr, alias, Yin, out)
+    return (float(out[0]), float(out[1])) if parts else total
 
 
-def effective_energy(row_ptr, col, n, k, Y, alpha=ALPHA, beta=BETA, gamma=GAMMA):
+def effective_energy(row_ptr, col, n, k, Y, alpha=ALPHA, beta=BETA, gamma=GAMMA, parts=False):
+    """Degree-weighted objective of Eq. (4) with the weight of Sec. 3.3; with
+    parts=True the pair (attraction, weighted repulsion)."""
     rp, c = _csr(row_ptr, col)
     Yin = np.ascontiguousarray(np.asarray(Y, dtype=np.float64).reshape(-1))
-    return lib().oracle_effective_energy(rp, c, int(n), int(k), alpha, beta, gamma, Yin)
+    out = np.zeros(2, dtype=np.float64)
+    total = lib().oracle_effective_energy(rp, c, int(n), int(k), alpha, beta, gamma, Yin, out)
+    return (float(out[0]), float(out[1])) if parts else total
 
 
 def threaded_run(row_ptr, col, n, k, T, seed, nthreads, Y0=None, t_begin=0, t_end=None,

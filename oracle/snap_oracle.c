@@ -134,11 +134,10 @@ static uint32_t ws_word(word_stream *ws)
 }
 
 /* ------------------------------------------------------------ init layout */
-/* Uniform initial positions in [-sqrt(n), sqrt(n)]^2, produced in FP32 (one
- * rounding) and widened exactly to FP64. */
-void oracle_init_positions(int64_t n, uint64_t seed, double *Y)
+/* Uniform positions in [-scale, scale]^2 for nodes [0, n), produced in FP32
+ * (one rounding) and widened exactly to FP64. */
+void oracle_init_positions_scaled(int64_t n, uint64_t seed, float s, double *Y)
 {
-    float s = sqrtf((float)n);
     uint64_t key[2] = {seed, KEY_DOMAIN};
     for (int64_t i = 0; i < n; ++i) {
         uint64_t ctr[4] = {(uint64_t)i, 0, 0, TAG_INIT};
@@ -151,6 +150,12 @@ void oracle_init_positions(int64_t n, uint64_t seed, double *Y)
             Y[2 * i + c] = (double)coord;
         }
     }
+}
+
+/* The initial layout: uniform in [-sqrt(n), sqrt(n)]^2. */
+void oracle_init_positions(int64_t n, uint64_t seed, double *Y)
+{
+    oracle_init_positions_scaled(n, seed, sqrtf((float)n), Y);
 }
 
 /* -------------------------------------------------------------- alias table */
@@ -450,39 +455,46 @@ static double energy_rep(const force_params *fp, double q)
 
 /* Energy actually sampled in epoch t at fixed Y: the sum over directed edges of
  * the attraction energy plus the repulsion energies of the drawn pairs (the
- * "actual energy" of Sec. 3.3). */
+ * "actual energy" of Sec. 3.3).  parts (nullable) receives {attraction,
+ * repulsion}. */
 double oracle_sampled_energy(const int32_t *row_ptr, const int32_t *col, int32_t n, int32_t k,
                              int64_t t, uint64_t seed, double alpha, double beta, double gamma,
                              int32_t mode, const uint32_t *thr, const uint32_t *alias,
-                             const double *Y)
+                             const double *Y, double *parts)
 {
     force_params fp = {alpha, beta, gamma, 1.0};
     sampler sp = {n, mode, thr, alias};
     int32_t *neg = (int32_t *)malloc(sizeof(int32_t) * (size_t)(k > 0 ? k : 1));
-    double total = 0.0;
+    double ea = 0.0, er = 0.0;
     for (int32_t i = 0; i < n; ++i) {
         for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
             int32_t j = col[e];
             double dx = Y[2 * i] - Y[2 * j], dy = Y[2 * i + 1] - Y[2 * j + 1];
-            total += energy_attr(&fp, dx * dx + dy * dy);
+            ea += energy_attr(&fp, dx * dx + dy * dy);
             draw_negatives(&sp, seed, e, t, i, k, neg);
             for (int32_t m = 0; m < k; ++m) {
                 int32_t s = neg[m];
                 double sx = Y[2 * i] - Y[2 * s], sy = Y[2 * i + 1] - Y[2 * s + 1];
-                total += energy_rep(&fp, sx * sx + sy * sy);
+                er += energy_rep(&fp, sx * sx + sy * sy);
             }
         }
     }
     free(neg);
-    return total;
+    if (parts) {
+        parts[0] = ea;
+        parts[1] = er;
+    }
+    return ea + er;
 }
 
 /* The degree-weighted objective the sampling realises in expectation
  * (Eq. (4) with the weight k(d_i+d_j)/(n-1) of Sec. 3.3):
  *   U_eff = 2 sum_{undirected (i,j)} U_a + (k/(n-1)) sum_{i<j} (d_i+d_j) U_r.
- * O(n^2); for small graphs only. */
+ * O(n^2); for small graphs only.  parts (nullable) receives {attraction,
+ * weighted repulsion}. */
 double oracle_effective_energy(const int32_t *row_ptr, const int32_t *col, int32_t n, int32_t k,
-                               double alpha, double beta, double gamma, const double *Y)
+                               double alpha, double beta, double gamma, const double *Y,
+                               double *parts)
 {
     force_params fp = {alpha, beta, gamma, 1.0};
     double ea = 0.0, er = 0.0;
@@ -498,7 +510,12 @@ double oracle_effective_energy(const int32_t *row_ptr, const int32_t *col, int32
             double dx = Y[2 * i] - Y[2 * j], dy = Y[2 * i + 1] - Y[2 * j + 1];
             er += (di + dj) * energy_rep(&fp, dx * dx + dy * dy);
         }
-    return ea + (double)k / (double)(n - 1) * er;
+    er *= n > 1 ? (double)k / (double)(n - 1) : 0.0;
+    if (parts) {
+        parts[0] = ea;
+        parts[1] = er;
+    }
+    return ea + er;
 }
 
 /* ------------------------------------------------ threaded bundle scheme */

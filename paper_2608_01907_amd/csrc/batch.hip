@@ -244,8 +244,10 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
       o.nodes_per_lane < 0 || o.block_threads > 1024 || (o.block_threads % 64) != 0)
     return fail(LAYOUT_E_INVALID_ARG, "bad launch option");
   if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g (must be > 1)", o.gamma);
-  if (o.access < LAYOUT_ACCESS_COHERENT || o.access > LAYOUT_ACCESS_CACHED_READS)
+  if (o.access < LAYOUT_ACCESS_COHERENT || o.access > LAYOUT_ACCESS_CACHED)
     return fail(LAYOUT_E_INVALID_ARG, "access = %d", o.access);
+  if (o.init_mode != LAYOUT_INIT_UNIFORM)
+    return fail(LAYOUT_E_UNSUPPORTED, "init_mode = %d (only the seeded uniform init here)", o.init_mode);
 
   layout_batch_t* B = new (std::nothrow) layout_batch_t();
   if (!B) return fail(LAYOUT_E_OOM, "host allocation");

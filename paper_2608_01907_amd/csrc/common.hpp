@@ -60,6 +60,14 @@ int build_alias_table(hipStream_t stream, const int32_t* d_row, int32_t n, int64
 int validate_csr(hipStream_t stream, const int32_t* d_row, const int32_t* d_col, int32_t n,
                  int64_t nnz, uint32_t* d_err);
 void launch_init_positions(hipStream_t stream, float2* d_Y, int32_t n, uint64_t seed);
+// Pivot MDS positions of a validated CSR (pmds.hip).  d_pivots_out (nullable,
+// device, [pivots]) receives the pivots, d_dist_out (nullable, device,
+// pivots x n) the hop distances; *pivots_used the pivots taken.  Synchronises
+// the stream (the scratch it allocates is freed on return).
+constexpr int32_t kDefaultPivots = 50;
+int pmds_positions(hipStream_t stream, const int32_t* d_row, const int32_t* d_col, int32_t n,
+                   int32_t pivots, uint64_t seed, float2* d_Y, int32_t* d_pivots_out,
+                   int32_t* d_dist_out, int32_t* pivots_used);
 void launch_fill_zero(hipStream_t stream, float2* d_p, int64_t n);
 
 // Graphs whose epochs run on the global engine, one launch per epoch for all

@@ -78,12 +78,6 @@ struct GlobalCachedMem {
   static __device__ __forceinline__ void store(float2* p, float2 v) { *p = v; }
 };
 
-// Plain loads through the L2, device-scope stores (STORE policy only).
-struct GlobalCachedReadMem {
-  static __device__ __forceinline__ float2 load(const float2* p) { return *p; }
-  static __device__ __forceinline__ void store(float2* p, float2 v) { GlobalMem::store(p, v); }
-};
-
 // LDS-resident positions (one workgroup owns the whole graph).
 struct LdsMem {
   static __device__ __forceinline__ float2 load(const float2* p) {
@@ -452,16 +446,20 @@ static __global__ void validate_edges_kernel(const int32_t* __restrict__ row_ptr
 // Coordinate c of node v comes from the top 24 bits of word x_c of the block
 // (v, 0, 0, tag 1): a signed 24-bit integer times 2^-23 (exact) times s (one
 // rounding).
-static __global__ void init_positions_kernel(float2* __restrict__ Y, int32_t n, uint64_t seed,
-                                      float scale) {
-  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
+__device__ __forceinline__ float2 init_coords(int32_t v, uint64_t seed, float scale) {
   const U64x4 x = philox4x64_10(static_cast<uint64_t>(v), 0, 0, kTagInit, seed, kKeyDomain);
   const int32_t a = static_cast<int32_t>(x.x0 >> 40) - (1 << 23);
   const int32_t b = static_cast<int32_t>(x.x1 >> 40) - (1 << 23);
   const float ua = __fmul_rn(static_cast<float>(a), 0x1p-23f);
   const float ub = __fmul_rn(static_cast<float>(b), 0x1p-23f);
-  Y[v] = make_float2(__fmul_rn(ua, scale), __fmul_rn(ub, scale));
+  return make_float2(__fmul_rn(ua, scale), __fmul_rn(ub, scale));
+}
+
+static __global__ void init_positions_kernel(float2* __restrict__ Y, int32_t n, uint64_t seed,
+                                      float scale) {
+  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  Y[v] = init_coords(v, seed, scale);
 }
 
 // Debug: the negatives the epoch kernels draw for every edge in epoch t.

@@ -424,8 +424,10 @@ int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t ro
     return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
   if (o.engine < 0 || o.engine > 2) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
   if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g", o.gamma);
-  if (o.access < LAYOUT_ACCESS_COHERENT || o.access > LAYOUT_ACCESS_CACHED_READS)
+  if (o.access < LAYOUT_ACCESS_COHERENT || o.access > LAYOUT_ACCESS_CACHED)
     return fail(LAYOUT_E_INVALID_ARG, "access = %d", o.access);
+  if (o.init_mode != LAYOUT_INIT_UNIFORM)
+    return fail(LAYOUT_E_UNSUPPORTED, "init_mode = %d (only the seeded uniform init here)", o.init_mode);
   if (o.access != LAYOUT_ACCESS_COHERENT && o.update_mode != LAYOUT_UPDATE_AUTO &&
       o.update_mode != LAYOUT_HOGWILD_STORE)
     return fail(LAYOUT_E_UNSUPPORTED, "cached access needs HOGWILD_STORE");

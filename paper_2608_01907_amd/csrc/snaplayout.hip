@@ -17,6 +17,7 @@
 #include "alias.hpp"
 #include "chunks.hpp"
 #include "common.hpp"
+#include "energy.hpp"
 #include "kernels.hpp"
 #include "snaplayout.h"
 
@@ -125,6 +126,7 @@ struct layout {
   GraphDesc host_desc{};
   GraphDesc* d_table = nullptr;  // one entry
   int32_t* d_graph_ids = nullptr;
+  double* d_energy = nullptr;  // two FP64 accumulators of the energy monitors
 };
 
 namespace {
@@ -317,12 +319,6 @@ int snap::launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t
                                  dt + ep);
               continue;
             }
-            if (g.access == LAYOUT_ACCESS_CACHED_READS) {
-              hipLaunchKernelGGL((epoch_global_kernel<K, MODE, DEG, GlobalCachedReadMem>),
-                                 dim3(grid), dim3(g.block), 0, stream, g.d_table, g.G, index,
-                                 g.round_size, dt + ep);
-              continue;
-            }
           }
           hipLaunchKernelGGL((epoch_global_kernel<K, MODE, DEG>), dim3(grid), dim3(g.block), 0,
                              stream, g.d_table, g.G, index, g.round_size, dt + ep);
@@ -448,6 +444,44 @@ bool check_handle(const layout_t* L) {
 }  // namespace
 
 // --------------------------------------------------------------------- ABI
+// ---------------------------------------------------------- energy monitors
+namespace {
+
+int energy_buffer(layout_t* L) {
+  if (L->d_energy) return LAYOUT_OK;
+  return alloc(L, reinterpret_cast<void**>(&L->d_energy), 2 * sizeof(double),
+               "energy accumulators");
+}
+
+// out[0] = attraction over the directed edges, out[1] = repulsion shape over
+// the negatives of epoch t (K = 0 when with_rep is false).
+int launch_sampled_energy(layout_t* L, int32_t t, bool with_rep) {
+  if (L->n_chunks == 0) return LAYOUT_OK;
+  const int64_t want = div_up(L->n_chunks, 256);
+  const int grid = static_cast<int>(std::min<int64_t>(want, 4096));
+  const int k = with_rep ? L->k : 0;
+  return with_k(k, [&](auto kc) -> int {
+    constexpr int K = decltype(kc)::value;
+    return with_degree(L->opts.neg_weights == LAYOUT_NEG_DEGREE, [&](auto dc) -> int {
+      constexpr bool DEG = decltype(dc)::value;
+      hipLaunchKernelGGL((sampled_energy_kernel<K, DEG>), dim3(grid), dim3(256), 0, L->stream,
+                         L->d_table, L->n_chunks, t, L->d_energy);
+      return LAYOUT_OK;
+    });
+  });
+}
+
+int read_energy(layout_t* L, double* out) {
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, L->d_energy, 2 * sizeof(double), hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_fail(e, "energy monitor");
+  return LAYOUT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* layout_last_error(void) { return g_last_error.c_str(); }
@@ -496,8 +530,12 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
   if (o.start_epoch < 0 || o.start_epoch > epochs)
     return fail(LAYOUT_E_INVALID_ARG, "start_epoch = %d", o.start_epoch);
   if (o.engine < 0 || o.engine > 2) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
-  if (o.access < LAYOUT_ACCESS_COHERENT || o.access > LAYOUT_ACCESS_CACHED_READS)
+  if (o.access < LAYOUT_ACCESS_COHERENT || o.access > LAYOUT_ACCESS_CACHED)
     return fail(LAYOUT_E_INVALID_ARG, "access = %d", o.access);
+  if (o.init_mode != LAYOUT_INIT_UNIFORM && o.init_mode != LAYOUT_INIT_PMDS)
+    return fail(LAYOUT_E_INVALID_ARG, "init_mode = %d", o.init_mode);
+  if (o.pmds_pivots < 0 || o.pmds_pivots > 64)
+    return fail(LAYOUT_E_INVALID_ARG, "pmds_pivots = %d (1..64, 0 = default)", o.pmds_pivots);
   if (o.bundle_edges < 0 || o.block_threads < 0 || o.grid_blocks < 0 || o.hub_split_edges < 0 ||
       o.nodes_per_lane < 0)
     return fail(LAYOUT_E_INVALID_ARG, "negative launch option");
@@ -635,6 +673,11 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
     if (o.init_pos) {
       e = hipMemcpyAsync(d_Y, o.init_pos, sizeof(float2) * size_t(n), kind, L->stream);
       if (e != hipSuccess) return bail(hip_fail(e, "copying init_pos"));
+    } else if (o.init_mode == LAYOUT_INIT_PMDS) {
+      if ((rc = pmds_positions(L->stream, d_row, d_col, n,
+                               o.pmds_pivots ? o.pmds_pivots : kDefaultPivots, seed, d_Y,
+                               nullptr, nullptr, nullptr)) != LAYOUT_OK)
+        return bail(rc);
     } else {
       launch_init_positions(L->stream, d_Y, n, seed);
     }
@@ -781,6 +824,52 @@ void layout_destroy(layout_t* L) {
   delete L;
 }
 
+
+int layout_sampled_energy(layout_t* L, int32_t epoch, double* attr_out, double* rep_out) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (!attr_out || !rep_out) return fail(LAYOUT_E_INVALID_ARG, "NULL output");
+  if (epoch < 0) return fail(LAYOUT_E_INVALID_ARG, "epoch = %d", epoch);
+  int rc = energy_buffer(L);
+  if (rc != LAYOUT_OK) return rc;
+  hipError_t e = hipMemsetAsync(L->d_energy, 0, 2 * sizeof(double), L->stream);
+  if (e != hipSuccess) return hip_fail(e, "clearing energy accumulators");
+  rc = launch_sampled_energy(L, epoch, true);
+  if (rc != LAYOUT_OK) return rc;
+  double out[2] = {0.0, 0.0};
+  rc = read_energy(L, out);
+  if (rc != LAYOUT_OK) return rc;
+  *attr_out = out[0];
+  *rep_out = out[1] / (2.0 * (double(L->opts.gamma) - 1.0));
+  return LAYOUT_OK;
+}
+
+int layout_effective_energy(layout_t* L, double* attr_out, double* rep_out) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (!attr_out || !rep_out) return fail(LAYOUT_E_INVALID_ARG, "NULL output");
+  int rc = energy_buffer(L);
+  if (rc != LAYOUT_OK) return rc;
+  hipError_t e = hipMemsetAsync(L->d_energy, 0, 2 * sizeof(double), L->stream);
+  if (e != hipSuccess) return hip_fail(e, "clearing energy accumulators");
+  rc = launch_sampled_energy(L, 0, false);
+  if (rc != LAYOUT_OK) return rc;
+  if (L->n > 1 && L->k > 0) {
+    const int tiles = static_cast<int>(div_up(L->n, 256));
+    // enough workgroups to fill the chip when the row tiles are few
+    const int ysplit = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(tiles, div_up(2048, tiles))));
+    hipLaunchKernelGGL(pair_energy_kernel, dim3(tiles, ysplit), dim3(256), 0, L->stream,
+                       L->host_desc.Y, L->host_desc.row_ptr, L->n, L->opts.gamma,
+                       L->d_energy);
+  }
+  double out[2] = {0.0, 0.0};
+  rc = read_energy(L, out);
+  if (rc != LAYOUT_OK) return rc;
+  *attr_out = out[0];
+  // ordered pairs count each unordered pair twice
+  const double w = L->n > 1 ? double(L->k) / double(L->n - 1) : 0.0;
+  *rep_out = w * 0.5 * out[1] / (2.0 * (double(L->opts.gamma) - 1.0));
+  return LAYOUT_OK;
+}
+
 int layout_get_info(const layout_t* L, layout_info* info) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (!info) return fail(LAYOUT_E_INVALID_ARG, "info is NULL");
@@ -856,7 +945,7 @@ int layout_bench_gather(layout_t* L, int32_t mode, int32_t access, int32_t reps,
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (!ms || reps < 1) return fail(LAYOUT_E_INVALID_ARG, "ms NULL or reps < 1");
   if (mode != kStore && mode != kAtomic) return fail(LAYOUT_E_INVALID_ARG, "mode %d", mode);
-  if (access < LAYOUT_ACCESS_COHERENT || access > LAYOUT_ACCESS_CACHED_READS)
+  if (access < LAYOUT_ACCESS_COHERENT || access > LAYOUT_ACCESS_CACHED)
     return fail(LAYOUT_E_INVALID_ARG, "access %d", access);
   if (access != LAYOUT_ACCESS_COHERENT && mode != kStore)
     return fail(LAYOUT_E_UNSUPPORTED, "cached access only with the store policy");
@@ -885,10 +974,6 @@ int layout_bench_gather(layout_t* L, int32_t mode, int32_t access, int32_t reps,
           if (access == LAYOUT_ACCESS_CACHED) {
             if constexpr (MODE == kStore)
               hipLaunchKernelGGL((gather_rmw_kernel<K, MODE, GlobalCachedMem>), dim3(grid),
-                                 dim3(256), 0, L->stream, L->d_table, L->n_chunks);
-          } else if (access == LAYOUT_ACCESS_CACHED_READS) {
-            if constexpr (MODE == kStore)
-              hipLaunchKernelGGL((gather_rmw_kernel<K, MODE, GlobalCachedReadMem>), dim3(grid),
                                  dim3(256), 0, L->stream, L->d_table, L->n_chunks);
           } else {
             hipLaunchKernelGGL((gather_rmw_kernel<K, MODE, GlobalMem>), dim3(grid), dim3(256), 0,

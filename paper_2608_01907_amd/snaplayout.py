@@ -28,7 +28,8 @@ LAYOUT_JACOBI = 2
 LAYOUT_UPDATE_AUTO = 3
 LAYOUT_ACCESS_COHERENT = 0
 LAYOUT_ACCESS_CACHED = 1
-LAYOUT_ACCESS_CACHED_READS = 2
+LAYOUT_INIT_UNIFORM = 0
+LAYOUT_INIT_PMDS = 1
 LAYOUT_NEG_UNIFORM = 0
 LAYOUT_NEG_DEGREE = 1
 LAYOUT_ENGINE_AUTO = 0
@@ -57,6 +58,7 @@ class layout_opts(ctypes.Structure):
         ("bundle_edges", ctypes.c_int32), ("block_threads", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32), ("access", ctypes.c_int32),
         ("hub_split_edges", ctypes.c_int32), ("nodes_per_lane", ctypes.c_int32),
+        ("init_mode", ctypes.c_int32), ("pmds_pivots", ctypes.c_int32),
         ("init_pos", ctypes.c_void_p), ("stream", ctypes.c_void_p),
     ]
 
@@ -133,6 +135,12 @@ _SIGNATURES = {
     "layout_last_error": (ctypes.c_char_p, []),
     "layout_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(layout_info)]),
     "layout_debug_draws": (ctypes.c_int, [_vp, _i32, _vp]),
+    "layout_pmds": (ctypes.c_int, [_vp, _vp, _i32, _i32, _u64, _i32, _vp, _vp, _vp,
+                                   ctypes.POINTER(_i32)]),
+    "layout_sampled_energy": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double)]),
+    "layout_effective_energy": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
+                                               ctypes.POINTER(ctypes.c_double)]),
     "layout_debug_alias": (ctypes.c_int, [_vp, _vp, _vp]),
     "layout_debug_chunks": (ctypes.c_int, [_vp, _vp, _vp]),
     "layout_bench_gather": (ctypes.c_int, [_vp, _i32, _i32, _i32, _f32p]),
@@ -277,6 +285,46 @@ def layout_debug_draws(h, epoch, nnz, k):
     out = np.zeros((max(nnz, 1), max(k, 1)), dtype=np.int32)
     _check(lib().layout_debug_draws(h, epoch, out.ctypes.data))
     return out[:nnz, :k]
+
+
+def layout_pmds(row_ptr, col_idx, n, pivots=0, seed=0, want_detail=False):
+    """Pivot MDS layout (n x 2 float32); with want_detail also the pivots and
+    their hop distances (pivots x n, -1 = unreachable)."""
+    on_device = hasattr(row_ptr, "data_ptr") and row_ptr.is_cuda
+    if on_device:
+        rp, ci = row_ptr.data_ptr(), col_idx.data_ptr()
+    else:
+        rp_a = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci_a = np.ascontiguousarray(col_idx, dtype=np.int32)
+        rp, ci = rp_a.ctypes.data, (ci_a.ctypes.data if ci_a.size else rp_a.ctypes.data)
+    Y = np.zeros((max(n, 1), 2), dtype=np.float32)
+    p = pivots if pivots else 50
+    piv = np.zeros(p, dtype=np.int32)
+    dist = np.zeros((p, max(n, 1)), dtype=np.int32) if want_detail else None
+    used = _i32()
+    _check(lib().layout_pmds(rp, ci, int(n), int(pivots), int(seed), int(on_device),
+                             Y.ctypes.data, piv.ctypes.data,
+                             dist.ctypes.data if dist is not None else None,
+                             ctypes.byref(used)))
+    Y = Y[:n]
+    if not want_detail:
+        return Y
+    u = used.value
+    return Y, piv[:u].copy(), dist[:u, :n].copy()
+
+
+def layout_sampled_energy(h, epoch):
+    """(attraction, repulsion) energy seen by the samples of `epoch`."""
+    a, r = ctypes.c_double(), ctypes.c_double()
+    _check(lib().layout_sampled_energy(h, epoch, ctypes.byref(a), ctypes.byref(r)))
+    return a.value, r.value
+
+
+def layout_effective_energy(h):
+    """(attraction, weighted repulsion) of the degree-weighted objective."""
+    a, r = ctypes.c_double(), ctypes.c_double()
+    _check(lib().layout_effective_energy(h, ctypes.byref(a), ctypes.byref(r)))
+    return a.value, r.value
 
 
 def layout_debug_chunks(h):
@@ -440,8 +488,10 @@ class Layout:
                  neg_weights=LAYOUT_NEG_UNIFORM, engine=LAYOUT_ENGINE_AUTO, eta0=1.0,
                  alpha=0.1, beta=8.0, gamma=2.0, init_pos=None, bundle_edges=0,
                  block_threads=0, grid_blocks=0, start_epoch=0, stream=None,
-                 hub_split_edges=0, nodes_per_lane=0):
+                 hub_split_edges=0, nodes_per_lane=0, init_mode=LAYOUT_INIT_UNIFORM,
+                 pmds_pivots=0):
         o = layout_opts_init()
+        o.init_mode, o.pmds_pivots = init_mode, pmds_pivots
         o.alpha, o.beta, o.gamma, o.eta0 = alpha, beta, gamma, eta0
         o.update_mode, o.neg_weights, o.engine = update_mode, neg_weights, engine
         o.access = access
@@ -483,6 +533,12 @@ class Layout:
 
     def info(self):
         return layout_get_info(self.h)
+
+    def sampled_energy(self, epoch):
+        return layout_sampled_energy(self.h, epoch)
+
+    def effective_energy(self):
+        return layout_effective_energy(self.h)
 
     def status(self):
         return layout_status(self.h)

@@ -1,0 +1,123 @@
+"""Energy monitors on the GPU against the FP64 oracle (Sec. 3.3).
+
+* sampled energy of epoch t (attraction over the directed edges, repulsion
+  over the drawn negatives): same draws as the oracle, terms in FP32, sums in
+  FP64 -> relative error of each part within 1e-5 (every term is positive, so
+  the relative error of a sum is bounded by that of its terms: a few FP32 ulp);
+* effective (degree-weighted) energy: all pairs, 256-term FP32 partial sums ->
+  relative error within 2e-5;
+* the expectation identity of Sec. 3.3 at a size the O(n^2) oracle cannot
+  reach: the mean sampled repulsion over many epochs' draws at fixed positions
+  equals the GPU's effective repulsion within 5 standard errors.
+"""
+import numpy as np
+import pytest
+
+import synthgraph as S
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+SL = pytest.importorskip("paper_2608_01907_amd.snaplayout")
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def d1():
+    return S.sbm_2000(0)
+
+
+@pytest.fixture(scope="module")
+def pl20k():
+    return S.chung_lu_communities(20_000, 160_000, tau=2.2, dmax=1500.0, n_comm=20, intra=0.9,
+                                  seed=3)
+
+
+@pytest.mark.parametrize("gamma", [2.0, 3.0])
+@pytest.mark.parametrize("which,epochs_run,t", [("d1", 0, 0), ("d1", 10, 7), ("pl20k", 3, 29)])
+def test_sampled_energy_matches_oracle(which, epochs_run, t, gamma, d1, pl20k):
+    g = {"d1": d1, "pl20k": pl20k}[which]
+    with SL.Layout(g.row_ptr, g.col, g.n, k=5, epochs=30, seed=9, gamma=gamma) as L:
+        if epochs_run:
+            L.run(epochs_run)
+        Y = L.positions().astype(np.float64)
+        ga, gr = L.sampled_energy(t)
+    oa, orr = O.sampled_energy(g.row_ptr, g.col, g.n, 5, t, 9, Y, gamma=gamma, parts=True)
+    assert _rel(ga, oa) <= 1e-5, (ga, oa)
+    assert _rel(gr, orr) <= 1e-5, (gr, orr)
+
+
+def test_sampled_energy_degree_weighted_draws(d1):
+    thr, alias = O.alias_build(d1.degrees())
+    with SL.Layout(d1.row_ptr, d1.col, d1.n, k=4, epochs=10, seed=2,
+                   neg_weights=SL.LAYOUT_NEG_DEGREE) as L:
+        L.run(2)
+        Y = L.positions().astype(np.float64)
+        ga, gr = L.sampled_energy(3)
+    oa, orr = O.sampled_energy(d1.row_ptr, d1.col, d1.n, 4, 3, 2, Y, mode=O.NEG_DEGREE, thr=thr,
+                               alias=alias, parts=True)
+    assert _rel(ga, oa) <= 1e-5 and _rel(gr, orr) <= 1e-5, (ga, oa, gr, orr)
+
+
+@pytest.mark.parametrize("gamma", [2.0, 3.0])
+@pytest.mark.parametrize("which", ["d1", "pl20k"])
+def test_effective_energy_matches_oracle(which, gamma, d1, pl20k):
+    g = {"d1": d1, "pl20k": pl20k}[which]
+    if which == "pl20k" and gamma == 3.0:
+        pytest.skip("one large case is enough for the pair sweep")
+    with SL.Layout(g.row_ptr, g.col, g.n, k=5, epochs=30, seed=1, gamma=gamma) as L:
+        L.run(5)
+        Y = L.positions().astype(np.float64)
+        ga, gr = L.effective_energy()
+    oa, orr = O.effective_energy(g.row_ptr, g.col, g.n, 5, Y, gamma=gamma, parts=True)
+    assert _rel(ga, oa) <= 1e-5, (ga, oa)
+    assert _rel(gr, orr) <= 2e-5, (gr, orr)
+
+
+def test_expectation_identity_on_gpu():
+    """Mean over 400 epochs' draws at fixed positions -> the effective
+    repulsion (Sec. 3.3), on a 60k-node graph (3.6e9 ordered pairs)."""
+    g = S.chung_lu_communities(60_000, 400_000, tau=2.2, dmax=2000.0, n_comm=30, intra=0.9,
+                               seed=8)
+    with SL.Layout(g.row_ptr, g.col, g.n, k=5, epochs=400, seed=5) as L:
+        L.run(3)  # some structure, then positions stay fixed while sampling
+        _, eff = L.effective_energy()
+        reps = np.array([L.sampled_energy(t)[1] for t in range(400)])
+    se = reps.std(ddof=1) / np.sqrt(reps.size)
+    z = (reps.mean() - eff) / se
+    assert abs(z) < 5.0, (reps.mean(), eff, se, z)
+
+
+def test_energy_edge_cases():
+    # no edges: both parts vanish (every degree is 0)
+    rp = np.zeros(11, dtype=np.int32)
+    with SL.Layout(rp, np.zeros(0, np.int32), 10, k=5, epochs=3, seed=2) as L:
+        assert L.sampled_energy(0) == (0.0, 0.0)
+        assert L.effective_energy() == (0.0, 0.0)
+    # k = 0: attraction only
+    rp, col = S.csr_from_pairs(np.array([0, 1]), np.array([1, 2]), 6)
+    with SL.Layout(rp, col, 6, k=0, epochs=3, seed=1) as L:
+        Y = L.positions().astype(np.float64)
+        ga, gr = L.sampled_energy(1)
+        ea, er = L.effective_energy()
+    oa, _ = O.sampled_energy(rp, col, 6, 0, 1, 1, Y, parts=True)
+    assert gr == 0.0 and er == 0.0 and _rel(ga, oa) <= 1e-6 and _rel(ea, oa) <= 1e-6
+    # two nodes, one edge, closed form: U_a(q) twice, U_r(q) once per directed edge
+    rp, col = S.csr_from_pairs(np.array([0]), np.array([1]), 2)
+    Y0 = np.array([[0.0, 0.0], [3.0, 4.0]], dtype=np.float32)
+    with SL.Layout(rp, col, 2, k=1, epochs=3, seed=1, init_pos=Y0) as L:
+        ga, gr = L.sampled_energy(0)
+        ea, er = L.effective_energy()
+    q = 25.0
+    ua = 0.1 * (0.5 * q + 4.0 * np.log1p(q))
+    ur = 1.0 / (2.0 * (1.0 + q))
+    assert _rel(ga, 2 * ua) <= 1e-6 and _rel(gr, 2 * ur) <= 1e-6
+    # k/(n-1) * (d_0 + d_1) * U_r = 1 * 2 * U_r
+    assert _rel(ea, 2 * ua) <= 1e-6 and _rel(er, 2 * ur) <= 1e-6
+    with SL.Layout(rp, col, 2, k=1, epochs=3, seed=1) as L:
+        with pytest.raises(SL.LayoutError) as ei:
+            L.sampled_energy(-1)
+        assert ei.value.code == SL.LAYOUT_E_INVALID_ARG

@@ -77,12 +77,12 @@ def test_draws_two_nodes():
 
 
 # ---------------------------------------------------------------- Jacobi
-def _jacobi_check(g, k, seed, eta0, t=0, T=30):
+def _jacobi_check(g, k, seed, eta0, t=0, T=30, gamma=2.0):
     Y0 = O.init_positions(g.n, seed).astype(np.float32)
     ref, absd = O.jacobi_epoch(g.row_ptr, g.col, g.n, k, t, T, seed, Y0.astype(np.float64),
-                               eta0=eta0, want_abs=True)
+                               eta0=eta0, gamma=gamma, want_abs=True)
     with _layout(g, k=k, epochs=T, seed=seed, update_mode=SL.LAYOUT_JACOBI, eta0=eta0,
-                 engine=SL.LAYOUT_ENGINE_GLOBAL, init_pos=Y0, start_epoch=t) as L:
+                 gamma=gamma, engine=SL.LAYOUT_ENGINE_GLOBAL, init_pos=Y0, start_epoch=t) as L:
         L.run(1)
         Y = L.positions().astype(np.float64)
     err = np.abs(Y - ref).max()
@@ -95,6 +95,13 @@ def test_jacobi_epoch_d1_eta1(d1):
     assert err <= tol, (err, tol)
 
 
+@pytest.mark.parametrize("gamma", [1.5, 3.0])
+def test_jacobi_epoch_general_gamma(d1, gamma):
+    """Repulsion exponents other than the t-FDP row's 2 (the pow path)."""
+    err, tol = _jacobi_check(d1, 5, 6, 1.0, gamma=gamma)
+    assert err <= tol, (err, tol)
+
+
 @pytest.mark.parametrize("t", [0, 13])
 def test_jacobi_epoch_power_law(pl20k, t):
     dmax = int(pl20k.degrees().max())
@@ -103,17 +110,17 @@ def test_jacobi_epoch_power_law(pl20k, t):
 
 
 # ------------------------------------------------- single-lane trajectory
-@pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("engine", [1, 2])
-def test_single_lane_epoch_matches_serial_oracle(d1, mode, engine):
+@pytest.mark.parametrize("mode,engine,gamma", [
+    (0, 1, 2.0), (1, 1, 2.0), (0, 2, 2.0), (1, 2, 2.0), (0, 1, 3.0), (1, 2, 1.5)])
+def test_single_lane_epoch_matches_serial_oracle(d1, mode, engine, gamma):
     """One lane owns every edge (chunk = all edges): the kernel then runs the
     serial algorithm in CSR order; compare with the oracle in that order."""
     seed, T = 4, 50
     Y0 = O.init_positions(d1.n, seed).astype(np.float32)
     ref = O.serial_run(d1.row_ptr, d1.col, d1.n, 5, T, seed, Y0=Y0.astype(np.float64),
-                       t_begin=0, t_end=1, order=O.ORDER_CSR)
+                       t_begin=0, t_end=1, order=O.ORDER_CSR, gamma=gamma)
     with _layout(d1, k=5, epochs=T, seed=seed, update_mode=mode, engine=engine, init_pos=Y0,
-                 bundle_edges=d1.nnz, grid_blocks=1, block_threads=64) as L:
+                 gamma=gamma, bundle_edges=d1.nnz, grid_blocks=1, block_threads=64) as L:
         assert L.info()["n_chunks"] == 1
         L.run(1)
         Y = L.positions().astype(np.float64)
