@@ -267,7 +267,7 @@ def bench_batched(args):
     log(f"[bench] batched {dt * 1e3:.1f} ms/step, replay {replay_ms:.1f} ms; timing the plain path")
     # plain path: one graph per launch sequence, same graphs
     t0 = time.perf_counter()
-    for q, g in enumerate(gs):
+    for q, g in enumerate([] if args.no_plain else gs):
         hp = SL.layout_create_ex(rps[q], cols[q], g.n, 2, k, T, q, SL.layout_opts_init(), 1)
         SL.layout_epoch(hp, T)
         SL.layout_sync(hp)
@@ -277,7 +277,7 @@ def bench_batched(args):
                 f"{time.perf_counter() - t0:.1f}s")
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
-    plain_value = edges * (1 + k) * T / plain_s
+    plain_value = edges * (1 + k) * T / plain_s if not args.no_plain else None
     log(f"[bench] batched {dt * 1e3:.1f} ms/step (replay {replay_ms:.1f} ms), plain "
         f"{plain_s * 1e3:.1f} ms")
     return {
@@ -289,8 +289,9 @@ def bench_batched(args):
                    "edges": edges, "k": k, "epochs": T, "lds_graphs": info["lds_graphs"],
                    "global_graphs": info["global_graphs"], "autotune": tune},
         "replay_ms": round(replay_ms, 3),
-        "plain_one_graph_per_launch": {"value": plain_value, "seconds": round(plain_s, 3)},
-        "speedup_vs_plain": value / plain_value,
+        "plain_one_graph_per_launch": (None if args.no_plain else
+                                       {"value": plain_value, "seconds": round(plain_s, 3)}),
+        "speedup_vs_plain": value / plain_value if plain_value else None,
     }
 
 
@@ -390,6 +391,8 @@ def main():
     ap.add_argument("--profile-copy", action="store_true",
                     help="only run the streaming copy (counter calibration)")
     ap.add_argument("--graphs", type=int, default=512)
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched workload: skip timing the one-graph-at-a-time path")
     ap.add_argument("--pool", type=int, default=48)
     ap.add_argument("--jobs", type=int, default=200)
     ap.add_argument("--rho", type=float, nargs="+", default=[0.5, 0.8])

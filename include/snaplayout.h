@@ -77,9 +77,13 @@ enum {
 
 /* Which kernel family runs the epochs. */
 enum {
-    LAYOUT_ENGINE_AUTO = 0,   /* LDS for small graphs, global otherwise */
+    LAYOUT_ENGINE_AUTO = 0,   /* LDS for small graphs, XCD-local for graphs whose positions
+                                 fit one XCD's L2, global otherwise */
     LAYOUT_ENGINE_GLOBAL = 1, /* positions in device memory, all CUs */
-    LAYOUT_ENGINE_LDS = 2     /* positions in one workgroup's LDS (n * 8 B must fit) */
+    LAYOUT_ENGINE_LDS = 2,    /* positions in one workgroup's LDS (n * 8 B must fit) */
+    LAYOUT_ENGINE_XCD = 3     /* positions in device memory, each epoch on the CUs of one
+                                 XCD (accelerator complex die) with plain loads/stores that
+                                 hit its L2; HOGWILD_STORE only; n * 8 B <= 3 MiB */
 };
 
 typedef struct layout layout_t;
@@ -101,10 +105,11 @@ typedef struct layout_opts {
                                  edges, one lane each; 0 = default (4 * bundle_edges on the
                                  global engine, never on the LDS engine) */
     int32_t nodes_per_lane;   /* concurrency cap of the automatic launch shape: lanes in
-                                 flight <= n / nodes_per_lane on the global engine, working
-                                 lanes = n / nodes_per_lane in [64, 256] on the LDS engine, so
-                                 that few concurrent updates hit one node (Sec. 3.4);
-                                 0 = default 32 */
+                                 flight <= n / nodes_per_lane on the global and XCD-local
+                                 engines (workgroups of that many lanes rounded up to 64, at
+                                 most 256), working lanes = n / nodes_per_lane in [64, 256] on
+                                 the LDS engine, so that few concurrent updates hit one node
+                                 (Sec. 3.4); 0 = default 32 */
     int32_t init_mode;        /* LAYOUT_INIT_UNIFORM (default) / LAYOUT_INIT_PMDS; ignored
                                  when init_pos is given */
     int32_t pmds_pivots;      /* pivots of LAYOUT_INIT_PMDS, 1..64; 0 = default 50 */

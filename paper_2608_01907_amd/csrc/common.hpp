@@ -27,6 +27,9 @@ inline int lds_lanes_for(int32_t n, int nodes_per_lane) {
   return lanes < 64 ? 64 : (lanes > 256 ? 256 : lanes);
 }
 constexpr long long kLdsAutoMaxEdges = 400000;  // AUTO picks LDS below this many directed edges
+constexpr int kXcds = 8;                             // accelerator complex dies of the device
+constexpr long long kXcdMaxPositionBytes = 3 << 20;  // XCD-local engine: positions within 3 MiB
+                                                     // of the 4 MiB L2 of one XCD
 
 extern thread_local std::string g_last_error;
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));

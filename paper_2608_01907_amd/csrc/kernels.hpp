@@ -78,6 +78,17 @@ struct GlobalCachedMem {
   static __device__ __forceinline__ void store(float2* p, float2 v) { *p = v; }
 };
 
+// Positions touched by the CUs of one XCD only (the XCD-local engine): plain
+// loads and stores are coherent through that XCD's L2, and hit there when the
+// positions fit it.  A per-CU L1 line may lag another CU's store by the
+// line's short L1 lifetime, which is one more stale read of the lock-free
+// scheme.  HOGWILD_STORE only.
+struct XcdLocalMem {
+  static __device__ __forceinline__ float2 load(const float2* p) { return *p; }
+  static __device__ __forceinline__ void store(float2* p, float2 v) { *p = v; }
+  static __device__ __forceinline__ void add(float2* p, float2 v) { GlobalMem::add(p, v); }
+};
+
 // LDS-resident positions (one workgroup owns the whole graph).
 struct LdsMem {
   static __device__ __forceinline__ float2 load(const float2* p) {
@@ -243,22 +254,26 @@ __device__ __forceinline__ void process_chunk(const GraphDesc& g, float2* __rest
         yj.x += c * dx;
         yj.y += c * dy;
       }
+      // Forward this lane's own newer value when a negative repeats the
+      // neighbour or an earlier negative.  Written as per-element selects so
+      // that every array index stays a compile-time constant (a data-
+      // dependent index would put the arrays in scratch memory).
       bool dup[KS];
 #pragma unroll
       for (int m = 0; m < K; ++m) {
-        // forward this lane's own newer value when the negative repeats
+        const bool is_j = s[m] == static_cast<uint32_t>(j);
         float2 cur = ys[m];
-        dup[m] = false;
-        if (s[m] == static_cast<uint32_t>(j)) {
-          cur = yj;
-          dup[m] = true;
-        }
+        cur.x = is_j ? yj.x : cur.x;
+        cur.y = is_j ? yj.y : cur.y;
+        bool d = is_j;
 #pragma unroll
-        for (int m2 = 0; m2 < m; ++m2)
-          if (s[m2] == s[m]) {
-            cur = ys[m2];
-            dup[m] = true;
-          }
+        for (int m2 = 0; m2 < m; ++m2) {
+          const bool same = s[m2] == s[m];
+          cur.x = same ? ys[m2].x : cur.x;
+          cur.y = same ? ys[m2].y : cur.y;
+          d = d || same;
+        }
+        dup[m] = d;
         const float dx = yi.x - cur.x, dy = yi.y - cur.y;
         const float h = eta * rep_coef(dx * dx + dy * dy, g.gamma);
         yi.x += h * dx;
@@ -266,10 +281,14 @@ __device__ __forceinline__ void process_chunk(const GraphDesc& g, float2* __rest
         cur.x -= h * dx;
         cur.y -= h * dy;
         ys[m] = cur;
-        if (s[m] == static_cast<uint32_t>(j)) yj = cur;
+        yj.x = is_j ? cur.x : yj.x;
+        yj.y = is_j ? cur.y : yj.y;
 #pragma unroll
-        for (int m2 = 0; m2 < m; ++m2)
-          if (s[m2] == s[m]) ys[m2] = cur;
+        for (int m2 = 0; m2 < m; ++m2) {
+          const bool same = s[m2] == s[m];
+          ys[m2].x = same ? cur.x : ys[m2].x;
+          ys[m2].y = same ? cur.y : ys[m2].y;
+        }
       }
       if constexpr (MODE == kAtomic) {
         if (!same_bits(yj, yj_old)) Mem::add(Y + j, make_float2(yj.x - yj_old.x, yj.y - yj_old.y));
@@ -326,6 +345,46 @@ static __global__ void __launch_bounds__(256)
     if (local >= g.n_chunks) continue;  // past this graph's last chunk
     const int32_t t = g.t0 + dt;
     process_chunk<K, MODE, DEGREE, Mem>(g, g.Y, g.D, g.chunk_offset + local, t, eta_of(g, t));
+  }
+}
+
+// Index of the accelerator complex die (XCD) that runs this wave: hardware
+// register XCC_ID, bits [3:0].
+__device__ __forceinline__ int32_t xcd_id() {
+  return static_cast<int32_t>(__builtin_amdgcn_s_getreg((15 << 11) | 20) & 0xF);
+}
+
+// One epoch of one graph on the CUs of a single XCD.  The first workgroup to
+// start makes its XCD the owner of the epoch (*owner starts at -1);
+// workgroups on other XCDs leave at once, so the launch needs about
+// (XCDs x wanted workgroups) workgroups.  Each wave of the owner XCD takes
+// 64 chunks at a time from *counter (starts at 0) until the table is done, so
+// the epoch completes however workgroups are spread over the XCDs.
+template <int K, bool DEGREE>
+static __global__ void __launch_bounds__(256)
+    epoch_xcd_kernel(const GraphDesc* __restrict__ table, int32_t* owner, int32_t* counter,
+                     int32_t dt) {
+  __shared__ int32_t mine;
+  if (threadIdx.x == 0) {
+    const int32_t x = xcd_id();
+    const int32_t prev = atomicCAS(owner, -1, x);
+    mine = (prev == -1 || prev == x) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!mine) return;
+  const GraphDesc& g = table[0];
+  const int32_t t = g.t0 + dt;
+  const float eta = eta_of(g, t);
+  const int lane = static_cast<int>(threadIdx.x & 63);
+  const int32_t n_chunks = static_cast<int32_t>(g.n_chunks);
+  while (true) {
+    int32_t base = 0;
+    if (lane == 0) base = atomicAdd(counter, 64);
+    base = __shfl(base, 0, 64);
+    if (base >= n_chunks) break;
+    const int32_t c = base + lane;
+    if (c < n_chunks)
+      process_chunk<K, kStore, DEGREE, XcdLocalMem>(g, g.Y, g.D, g.chunk_offset + c, t, eta);
   }
 }
 

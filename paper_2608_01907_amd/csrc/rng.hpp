@@ -62,12 +62,30 @@ __device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_
   return U64x4{c0, c1, c2, c3};
 }
 
-// Sequential u32 words of one counter family (a, b, *, tag).
+// Sequential u32 words of one counter family (a, b, *, tag): block 0 gives
+// words lo(x0), hi(x0), lo(x1), ..., hi(x3), then block 1, and so on.  The
+// unread words of the current block sit in a register queue that shifts down
+// by one per word, so every register index is a compile-time constant (a
+// data-dependent word index would make the compiler keep the block in an
+// indexed scratch array).
 struct WordStream {
   uint64_t seed, a, b, tag;
   uint64_t block;
-  int pos;  // next word inside the current block, 0..8
-  U64x4 x;
+  int avail;  // unread words of the current block, 0..8
+  uint32_t w0, w1, w2, w3, w4, w5, w6, w7;
+
+  __device__ __forceinline__ void fill() {
+    const U64x4 x = philox4x64_10(a, b, block, tag, seed, kKeyDomain);
+    w0 = static_cast<uint32_t>(x.x0);
+    w1 = static_cast<uint32_t>(x.x0 >> 32);
+    w2 = static_cast<uint32_t>(x.x1);
+    w3 = static_cast<uint32_t>(x.x1 >> 32);
+    w4 = static_cast<uint32_t>(x.x2);
+    w5 = static_cast<uint32_t>(x.x2 >> 32);
+    w6 = static_cast<uint32_t>(x.x3);
+    w7 = static_cast<uint32_t>(x.x3 >> 32);
+    avail = 8;
+  }
 
   __device__ __forceinline__ void open(uint64_t seed_, uint64_t a_, uint64_t b_, uint64_t tag_) {
     seed = seed_;
@@ -75,19 +93,23 @@ struct WordStream {
     b = b_;
     tag = tag_;
     block = 0;
-    pos = 0;
-    x = philox4x64_10(a, b, 0, tag, seed, kKeyDomain);
+    fill();
   }
 
   __device__ __forceinline__ uint32_t next() {
-    if (pos == 8) {
+    if (avail == 0) {
       ++block;
-      pos = 0;
-      x = philox4x64_10(a, b, block, tag, seed, kKeyDomain);
+      fill();
     }
-    const uint64_t w = pos < 2 ? x.x0 : (pos < 4 ? x.x1 : (pos < 6 ? x.x2 : x.x3));
-    const uint32_t r = (pos & 1) ? static_cast<uint32_t>(w >> 32) : static_cast<uint32_t>(w);
-    ++pos;
+    const uint32_t r = w0;
+    w0 = w1;
+    w1 = w2;
+    w2 = w3;
+    w3 = w4;
+    w4 = w5;
+    w5 = w6;
+    w6 = w7;
+    --avail;
     return r;
   }
 };

@@ -127,6 +127,8 @@ struct layout {
   GraphDesc* d_table = nullptr;  // one entry
   int32_t* d_graph_ids = nullptr;
   double* d_energy = nullptr;  // two FP64 accumulators of the energy monitors
+  int32_t* d_xcd_owner = nullptr;    // XCD-local engine: owner XCD of each epoch (-1 = none yet)
+  int32_t* d_xcd_counter = nullptr;  // XCD-local engine: chunks handed out in each epoch
 };
 
 namespace {
@@ -170,9 +172,42 @@ LdsGroup lds_group_of(const layout_t* L) {
   return g;
 }
 
+// XCD-local engine: workgroups that do the work (at most one per CU of the
+// XCD, n / nodes_per_lane lanes), and the launch size that puts about that
+// many on the owner XCD when workgroups are spread evenly over the XCDs.
+int xcd_workers(const layout_t* L) {
+  if (L->opts.grid_blocks > 0) return L->opts.grid_blocks;
+  const DeviceProps& dp = device_props();
+  const int cus_per_xcd = std::max(1, dp.cus / kXcds);
+  const int npl = L->opts.nodes_per_lane > 0 ? L->opts.nodes_per_lane : kNodesPerLane;
+  const int64_t lanes = std::max<int64_t>(1, L->n / npl);
+  return static_cast<int>(std::min<int64_t>(cus_per_xcd, std::max<int64_t>(1, div_up(lanes, L->block))));
+}
+
+int launch_xcd_epochs(layout_t* L, int32_t count) {
+  const DeviceProps& dp = device_props();
+  const int xcds = dp.cus >= kXcds ? kXcds : 1;
+  const int grid = xcd_workers(L) * xcds;
+  return with_k(L->k, [&](auto kc) -> int {
+    constexpr int K = decltype(kc)::value;
+    return with_degree(L->opts.neg_weights == LAYOUT_NEG_DEGREE, [&](auto dc) -> int {
+      constexpr bool DEG = decltype(dc)::value;
+      for (int32_t ep = 0; ep < count; ++ep) {
+        const int32_t t = L->t + ep;
+        hipLaunchKernelGGL((epoch_xcd_kernel<K, DEG>), dim3(grid), dim3(L->block), 0, L->stream,
+                           L->d_table, L->d_xcd_owner + t, L->d_xcd_counter + t, t);
+      }
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "epoch_xcd_kernel launch");
+      return LAYOUT_OK;
+    });
+  });
+}
+
 int launch_epochs(layout_t* L, int32_t count) {
   if (L->nnz == 0) return LAYOUT_OK;  // no edge, nothing moves
   if (L->engine == LAYOUT_ENGINE_LDS) return launch_lds_epochs(L->stream, lds_group_of(L), L->t, count);
+  if (L->engine == LAYOUT_ENGINE_XCD) return launch_xcd_epochs(L, count);
   return launch_global_epochs(L->stream, global_group_of(L), L->t, count);
 }
 
@@ -529,7 +564,7 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
     return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
   if (o.start_epoch < 0 || o.start_epoch > epochs)
     return fail(LAYOUT_E_INVALID_ARG, "start_epoch = %d", o.start_epoch);
-  if (o.engine < 0 || o.engine > 2) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
+  if (o.engine < 0 || o.engine > 3) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
   if (o.access < LAYOUT_ACCESS_COHERENT || o.access > LAYOUT_ACCESS_CACHED)
     return fail(LAYOUT_E_INVALID_ARG, "access = %d", o.access);
   if (o.init_mode != LAYOUT_INIT_UNIFORM && o.init_mode != LAYOUT_INIT_PMDS)
@@ -591,10 +626,22 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
     L->engine = LAYOUT_ENGINE_LDS;
   } else if (o.engine == LAYOUT_ENGINE_GLOBAL) {
     L->engine = LAYOUT_ENGINE_GLOBAL;
+  } else if (o.engine == LAYOUT_ENGINE_XCD) {
+    if (int64_t(n) * 8 > kXcdMaxPositionBytes)
+      return bail(fail(LAYOUT_E_UNSUPPORTED, "XCD-local engine: %d nodes need %lld B (> %lld)", n,
+                       (long long)n * 8, (long long)kXcdMaxPositionBytes));
+    if (o.update_mode != LAYOUT_UPDATE_AUTO && o.update_mode != LAYOUT_HOGWILD_STORE)
+      return bail(fail(LAYOUT_E_UNSUPPORTED, "XCD-local engine runs HOGWILD_STORE only"));
+    L->engine = LAYOUT_ENGINE_XCD;
   } else {
-    L->engine = (lds_fits && L->nnz <= kLdsAutoMaxEdges && o.update_mode != LAYOUT_JACOBI)
-                    ? LAYOUT_ENGINE_LDS
-                    : LAYOUT_ENGINE_GLOBAL;
+    const bool store_ok = o.update_mode == LAYOUT_UPDATE_AUTO || o.update_mode == LAYOUT_HOGWILD_STORE;
+    if (lds_fits && L->nnz <= kLdsAutoMaxEdges && o.update_mode != LAYOUT_JACOBI)
+      L->engine = LAYOUT_ENGINE_LDS;
+    else if (store_ok && int64_t(n) * 8 <= kXcdMaxPositionBytes &&
+             o.access == LAYOUT_ACCESS_COHERENT)
+      L->engine = LAYOUT_ENGINE_XCD;
+    else
+      L->engine = LAYOUT_ENGINE_GLOBAL;
   }
   if (L->engine == LAYOUT_ENGINE_LDS) {
     L->block = o.block_threads ? o.block_threads : lds_lanes_for(n, o.nodes_per_lane);
@@ -605,7 +652,11 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
     L->hub = o.hub_split_edges ? o.hub_split_edges
                                : static_cast<int32_t>(std::max<int64_t>(1, L->nnz));
   } else {
-    L->block = o.block_threads ? o.block_threads : 256;
+    // a whole workgroup works on the graph, so small graphs get small
+    // workgroups: n / nodes_per_lane lanes rounded up to whole wavefronts
+    const int npl = o.nodes_per_lane > 0 ? o.nodes_per_lane : kNodesPerLane;
+    const int64_t want = div_up(std::max<int64_t>(1, n / npl), 64) * 64;
+    L->block = o.block_threads ? o.block_threads : static_cast<int32_t>(std::min<int64_t>(256, want));
     L->bundle = o.bundle_edges ? o.bundle_edges : kDefaultBundle;
     L->hub = o.hub_split_edges ? o.hub_split_edges : kHubFactor * L->bundle;
   }
@@ -617,8 +668,10 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
       (L->mode != LAYOUT_HOGWILD_STORE || L->engine != LAYOUT_ENGINE_GLOBAL))
     return bail(fail(LAYOUT_E_UNSUPPORTED,
                      "cached access is only defined for HOGWILD_STORE on the global engine"));
-  if (L->engine == LAYOUT_ENGINE_GLOBAL && L->block > 256)
-    return bail(fail(LAYOUT_E_UNSUPPORTED, "global engine runs at most 256-thread workgroups"));
+  if ((L->engine == LAYOUT_ENGINE_GLOBAL || L->engine == LAYOUT_ENGINE_XCD) && L->block > 256)
+    return bail(fail(LAYOUT_E_UNSUPPORTED, "global engines run at most 256-thread workgroups"));
+  if (L->engine == LAYOUT_ENGINE_XCD && L->access != LAYOUT_ACCESS_COHERENT)
+    return bail(fail(LAYOUT_E_UNSUPPORTED, "the XCD-local engine has its own access rule"));
   const int64_t chunk_cap = L->nnz > 0 ? chunk_bound(L->nnz, L->bundle, L->hub) : 0;
 
   // device buffers
@@ -683,6 +736,15 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
     }
   }
   if (d_D) launch_fill_zero(L->stream, d_D, n);
+  if (L->engine == LAYOUT_ENGINE_XCD) {
+    const size_t b = sizeof(int32_t) * size_t(epochs);
+    if ((rc = alloc(L, reinterpret_cast<void**>(&L->d_xcd_owner), b, "epoch owners")) ||
+        (rc = alloc(L, reinterpret_cast<void**>(&L->d_xcd_counter), b, "epoch counters")))
+      return bail(rc);
+    e = hipMemsetAsync(L->d_xcd_owner, 0xFF, b, L->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(L->d_xcd_counter, 0, b, L->stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "clearing epoch counters"));
+  }
 
   GraphDesc& g = L->host_desc;
   g.row_ptr = d_row;
@@ -877,7 +939,9 @@ int layout_get_info(const layout_t* L, layout_info* info) {
   info->bundle_edges = L->bundle;
   info->block_threads = L->block;
   info->grid_blocks = 0;
-  if (L->engine == LAYOUT_ENGINE_GLOBAL && L->nnz > 0) {
+  if (L->engine == LAYOUT_ENGINE_XCD && L->nnz > 0) {
+    info->grid_blocks = xcd_workers(L);  // working workgroups, on one XCD
+  } else if (L->engine == LAYOUT_ENGINE_GLOBAL && L->nnz > 0) {
     info->grid_blocks = global_grid(global_group_of(L));
   } else if (L->engine == LAYOUT_ENGINE_LDS) {
     info->grid_blocks = 1;

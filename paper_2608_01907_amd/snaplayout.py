@@ -35,6 +35,7 @@ LAYOUT_NEG_DEGREE = 1
 LAYOUT_ENGINE_AUTO = 0
 LAYOUT_ENGINE_GLOBAL = 1
 LAYOUT_ENGINE_LDS = 2
+LAYOUT_ENGINE_XCD = 3
 
 _NAMES = {
     LAYOUT_E_INVALID_ARG: "LAYOUT_E_INVALID_ARG", LAYOUT_E_BAD_GRAPH: "LAYOUT_E_BAD_GRAPH",

@@ -111,7 +111,7 @@ def test_jacobi_epoch_power_law(pl20k, t):
 
 # ------------------------------------------------- single-lane trajectory
 @pytest.mark.parametrize("mode,engine,gamma", [
-    (0, 1, 2.0), (1, 1, 2.0), (0, 2, 2.0), (1, 2, 2.0), (0, 1, 3.0), (1, 2, 1.5)])
+    (0, 1, 2.0), (1, 1, 2.0), (0, 2, 2.0), (1, 2, 2.0), (0, 1, 3.0), (1, 2, 1.5), (0, 3, 2.0)])
 def test_single_lane_epoch_matches_serial_oracle(d1, mode, engine, gamma):
     """One lane owns every edge (chunk = all edges): the kernel then runs the
     serial algorithm in CSR order; compare with the oracle in that order."""
@@ -140,6 +140,8 @@ def d1_oracle_quality(d1):
     (SL.LAYOUT_ATOMIC, SL.LAYOUT_ENGINE_GLOBAL, 0),
     (SL.LAYOUT_ATOMIC, SL.LAYOUT_ENGINE_LDS, 0),
     (SL.LAYOUT_HOGWILD_STORE, SL.LAYOUT_ENGINE_LDS, 64),
+    (SL.LAYOUT_HOGWILD_STORE, SL.LAYOUT_ENGINE_XCD, 0),
+    (SL.LAYOUT_HOGWILD_STORE, SL.LAYOUT_ENGINE_GLOBAL, 0),
 ])
 def test_final_layout_quality_d1(d1, d1_oracle_quality, mode, engine, threads):
     with _layout(d1, k=5, epochs=50, seed=0, update_mode=mode, engine=engine,
@@ -150,6 +152,32 @@ def test_final_layout_quality_d1(d1, d1_oracle_quality, mode, engine, threads):
     q = M.quality(d1.row_ptr, d1.col, Y, d1.labels)
     assert abs(q["np"] - d1_oracle_quality["np"]) <= 0.01, (q, d1_oracle_quality)
     assert abs(q["si"] - d1_oracle_quality["si"]) <= 0.01, (q, d1_oracle_quality)
+
+
+def test_xcd_engine_choice_and_limits():
+    """Graphs whose positions fit one XCD's L2 and that are too large for LDS
+    run on the XCD-local engine by default; it runs HOGWILD_STORE only and
+    refuses graphs beyond its 3 MiB position budget."""
+    pl50k = S.chung_lu_communities(50_000, 400_000, tau=2.2, dmax=2000.0, n_comm=30, intra=0.9,
+                                   seed=6)
+    with _layout(pl50k, k=5, epochs=4, seed=1) as L:
+        info = L.info()
+        assert info["engine"] == SL.LAYOUT_ENGINE_XCD and info["update_mode"] == 0
+        Y0 = L.positions()
+        L.run()
+        Y = L.positions()
+    assert np.all(np.isfinite(Y)) and not np.array_equal(Y, Y0)
+    with pytest.raises(SL.LayoutError) as ei:
+        _layout(pl50k, k=5, epochs=4, engine=SL.LAYOUT_ENGINE_XCD, update_mode=SL.LAYOUT_ATOMIC)
+    assert ei.value.code == SL.LAYOUT_E_UNSUPPORTED
+    n = 400_000
+    rp, col = S.csr_from_pairs(np.arange(n - 1), np.arange(1, n), n)
+    with pytest.raises(SL.LayoutError) as ei:
+        SL.Layout(rp, col, n, k=5, epochs=2, engine=SL.LAYOUT_ENGINE_XCD)
+    assert ei.value.code == SL.LAYOUT_E_UNSUPPORTED
+    # the same graph as ATOMIC falls back to the all-CU global engine
+    with _layout(pl50k, k=5, epochs=2, seed=1, update_mode=SL.LAYOUT_ATOMIC) as L:
+        assert L.info()["engine"] == SL.LAYOUT_ENGINE_GLOBAL
 
 
 def test_atomic_mode_conserves_centroid(d1):

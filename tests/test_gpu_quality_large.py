@@ -1,7 +1,8 @@
 """Final-layout quality of the lock-free GPU path at the workload sizes, against
 the oracle's references (tests/golden/quality_*.json, written by
 tests/golden/make_quality_golden.py from the oracle only): NP and SI within
-0.01 absolute on the same seeded node samples."""
+0.01 absolute on the same seeded node samples, from the seeded uniform start
+and from the Pivot MDS start."""
 import json
 import os
 
@@ -20,8 +21,10 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 def _check(name, maker):
     ref = json.load(open(os.path.join(GOLDEN, f"quality_{name}.json")))
     run0 = [r for r in ref["runs"] if r["seed"] == 0][0]
-    g = S.cached(name, maker)
-    with SL.Layout(g.row_ptr, g.col, g.n, k=ref["k"], epochs=ref["epochs"], seed=0) as L:
+    g = S.cached(ref.get("graph", name), maker)
+    init = SL.LAYOUT_INIT_PMDS if ref.get("init") == "pmds" else SL.LAYOUT_INIT_UNIFORM
+    with SL.Layout(g.row_ptr, g.col, g.n, k=ref["k"], epochs=ref["epochs"], seed=0,
+                   init_mode=init) as L:
         L.run()
         Y = L.positions()
         info = L.info()
@@ -40,3 +43,13 @@ def test_quality_orkut_like_259k():
 
 def test_quality_lj_like_4m():
     _check("lj-like-4m", S.lj_like)
+
+
+def test_quality_orkut_like_259k_from_pmds():
+    """From the Pivot MDS start of Sec. 4.1 (the oracle starts from its own
+    PMDS layout, which may differ from the device's by a rotation)."""
+    _check("orkut-like-259k-pmds", S.orkut_like)
+
+
+def test_quality_lj_like_4m_from_pmds():
+    _check("lj-like-4m-pmds", S.lj_like)
