@@ -285,6 +285,8 @@ typedef struct layout_batch_info {
     int32_t bundle_edges, hub_split_edges; /* of the global group */
     int32_t grid_blocks, block_threads;    /* of the global group */
     int32_t lds_block_threads, update_mode_global, update_mode_lds, epochs_done;
+    int32_t xcd_engine;       /* 1: the global group runs on the XCD-local engine */
+    int32_t xcd_grid_blocks;  /* its launch size (kXcds x the largest bin's workgroups) */
 } layout_batch_info;
 
 /* Creates a batch of count graphs (validated like layout_create).  opts as for

@@ -7,7 +7,11 @@
 //   LDS group:    n_g * 8 B fits one workgroup's LDS; one workgroup per graph
 //                 runs every epoch (epoch_lds_kernel).
 //   global group: one launch per epoch over the chunks of all its graphs
-//                 (epoch_global_kernel with a multi-graph table).
+//                 (epoch_global_kernel with a multi-graph table), or, when
+//                 every such graph's positions fit one XCD's L2, the
+//                 XCD-local engine: the graphs are split into one bin per XCD
+//                 and each XCD runs its bin with plain loads and stores
+//                 (epoch_xcd_group_kernel).
 // Both groups' epochs are captured once in a HIP graph (two branches forked
 // from the batch stream) and replayed by layout_batch_run.
 #include <hip/hip_runtime.h>
@@ -61,6 +65,14 @@ struct layout_batch {
   std::vector<int32_t> global_ids, lds_ids;
   GlobalGroup gg;
   LdsGroup lg;
+  // XCD-local engine for the global group
+  bool xcd_mode = false;
+  XcdGroup xg;
+  GraphDesc* d_table_xcd = nullptr;
+  XcdSeg* d_segs = nullptr;
+  XcdBin* d_bins = nullptr;
+  int32_t* d_xcd_counters = nullptr;  // [epochs][segments], segments <= graphs
+  XcdBin bins[kXcds] = {};
   int64_t nodes = 0, total_nnz = 0;
 };
 
@@ -107,6 +119,10 @@ int build_global_chunks(layout_batch_t* B) {
   for (int32_t g : B->global_ids)
     if (B->nnz[g] > 0) table.push_back(B->desc[g]);
   B->gg.max_lanes = table.empty() ? 0 : fair_lanes(table, B->opts.nodes_per_lane);
+  // small lane caps get small workgroups (whole wavefronts), as on one graph
+  if (!B->opts.block_threads)
+    B->gg.block = static_cast<int>(
+        std::min<int64_t>(256, std::max<int64_t>(64, div_up(std::max<int64_t>(1, B->gg.max_lanes), 64) * 64)));
   return LAYOUT_OK;
 }
 
@@ -122,6 +138,33 @@ int upload_global_table(layout_batch_t* B, int grid) {
                                 hipMemcpyHostToDevice, B->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
   if (e != hipSuccess) return hip_fail(e, "uploading the global table");
+  return LAYOUT_OK;
+}
+
+// Bins and segments of the XCD-local engine for the current chunk tables,
+// uploaded to the device.
+int upload_xcd_table(layout_batch_t* B) {
+  std::vector<GraphDesc> graphs, table;
+  std::vector<XcdSeg> segs;
+  for (int32_t g : B->global_ids)
+    if (B->nnz[g] > 0) graphs.push_back(B->desc[g]);
+  B->xg.total_chunks = B->gg.total_chunks;
+  if (graphs.empty()) {
+    B->xg.grid = 0;
+    return LAYOUT_OK;
+  }
+  B->xg.grid = plan_xcd_bins(graphs, B->opts.nodes_per_lane, table, segs, B->bins);
+  B->xg.n_segs = static_cast<int32_t>(segs.size());
+  hipError_t e = hipMemcpyAsync(B->d_table_xcd, table.data(), sizeof(GraphDesc) * table.size(),
+                                hipMemcpyHostToDevice, B->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(B->d_segs, segs.data(), sizeof(XcdSeg) * segs.size(),
+                       hipMemcpyHostToDevice, B->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(B->d_bins, B->bins, sizeof(XcdBin) * kXcds, hipMemcpyHostToDevice,
+                       B->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
+  if (e != hipSuccess) return hip_fail(e, "uploading the XCD bins");
   return LAYOUT_OK;
 }
 
@@ -143,7 +186,7 @@ int capture(layout_batch_t* B) {
   }
   if (B->gg.total_chunks > 0) {
     GlobalGroup probe = B->gg;
-    const int rc = upload_global_table(B, global_grid(probe));
+    const int rc = B->xcd_mode ? upload_xcd_table(B) : upload_global_table(B, global_grid(probe));
     if (rc != LAYOUT_OK) return rc;
   }
   hipError_t e = hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal);
@@ -152,7 +195,15 @@ int capture(layout_batch_t* B) {
   e = hipEventRecord(B->fork, B->stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(B->side, B->fork, 0);
   if (e == hipSuccess) rc = launch_lds_epochs(B->side, B->lg, 0, B->epochs);
-  if (e == hipSuccess && rc == LAYOUT_OK) rc = launch_global_epochs(B->stream, B->gg, 0, B->epochs);
+  if (e == hipSuccess && rc == LAYOUT_OK) {
+    if (B->xcd_mode) {
+      // counters start at zero on every replay (a fill kernel: no memset node)
+      launch_fill_i32(B->stream, B->d_xcd_counters, int64_t(B->epochs) * B->count, 0);
+      rc = launch_xcd_group_epochs(B->stream, B->xg, 0, B->epochs);
+    } else {
+      rc = launch_global_epochs(B->stream, B->gg, 0, B->epochs);
+    }
+  }
   if (e == hipSuccess) e = hipEventRecord(B->join, B->side);
   if (e == hipSuccess) e = hipStreamWaitEvent(B->stream, B->join, 0);
   hipGraph_t graph = nullptr;
@@ -185,7 +236,8 @@ std::string tune_key(const layout_batch_t* B) {
   const int ld = nodes > 0 ? static_cast<int>(std::log2(std::max(1.0, double(nnz) / double(nodes))))
                            : 0;
   char key[256];
-  snprintf(key, sizeof key, "%s|k%d|m%d|e%d|d%d", prop.gcnArchName, B->k, B->mode_global, le, ld);
+  snprintf(key, sizeof key, "%s|k%d|m%d|e%d|d%d|x%d", prop.gcnArchName, B->k, B->mode_global, le,
+           ld, B->xcd_mode ? 1 : 0);
   for (char* c = key; *c; ++c)
     if (*c == ' ') *c = '_';
   return key;
@@ -239,7 +291,7 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
     return fail(LAYOUT_E_INVALID_ARG, "update_mode = %d", o.update_mode);
   if (o.neg_weights != LAYOUT_NEG_UNIFORM && o.neg_weights != LAYOUT_NEG_DEGREE)
     return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
-  if (o.engine < 0 || o.engine > 2) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
+  if (o.engine < 0 || o.engine > 3) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
   if (o.bundle_edges < 0 || o.block_threads < 0 || o.grid_blocks < 0 || o.hub_split_edges < 0 ||
       o.nodes_per_lane < 0 || o.block_threads > 1024 || (o.block_threads % 64) != 0)
     return fail(LAYOUT_E_INVALID_ARG, "bad launch option");
@@ -343,6 +395,22 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
   }
   if (!B->global_ids.empty() && o.block_threads > 256)
     return bail(fail(LAYOUT_E_UNSUPPORTED, "global engine runs at most 256-thread workgroups"));
+  {
+    bool all_fit = !B->global_ids.empty();
+    for (int32_t g : B->global_ids) all_fit = all_fit && int64_t(B->n[g]) * 8 <= kXcdMaxPositionBytes;
+    const bool store = B->mode_global == LAYOUT_HOGWILD_STORE;
+    const bool plain = !jacobi && store && o.access == LAYOUT_ACCESS_COHERENT && o.block_threads <= 256 &&
+                       o.grid_blocks == 0;
+    if (o.engine == LAYOUT_ENGINE_XCD) {
+      if (!plain || !all_fit)
+        return bail(fail(LAYOUT_E_UNSUPPORTED,
+                         "XCD-local engine: HOGWILD_STORE, coherent access and graphs of at most "
+                         "%lld B of positions", (long long)kXcdMaxPositionBytes));
+      B->xcd_mode = true;
+    } else if (o.engine == LAYOUT_ENGINE_AUTO) {
+      B->xcd_mode = plain && all_fit;
+    }
+  }
 
   // packed allocations
   int rc;
@@ -355,6 +423,13 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
       (rc = balloc(B, reinterpret_cast<void**>(&B->d_table_global), sizeof(GraphDesc) * size_t(count), "table")) ||
       (rc = balloc(B, reinterpret_cast<void**>(&B->d_table_lds), sizeof(GraphDesc) * size_t(count), "table")) ||
       (rc = balloc(B, reinterpret_cast<void**>(&B->d_lds_ids), sizeof(int32_t) * size_t(count), "ids")))
+    return bail(rc);
+  if (B->xcd_mode &&
+      ((rc = balloc(B, reinterpret_cast<void**>(&B->d_table_xcd), sizeof(GraphDesc) * size_t(count), "xcd table")) ||
+       (rc = balloc(B, reinterpret_cast<void**>(&B->d_segs), sizeof(XcdSeg) * size_t(count), "xcd segments")) ||
+       (rc = balloc(B, reinterpret_cast<void**>(&B->d_bins), sizeof(XcdBin) * kXcds, "xcd bins")) ||
+       (rc = balloc(B, reinterpret_cast<void**>(&B->d_xcd_counters),
+                    sizeof(int32_t) * size_t(epochs) * size_t(count), "xcd counters"))))
     return bail(rc);
   if (jacobi && (rc = balloc(B, reinterpret_cast<void**>(&B->d_D), sizeof(float2) * size_t(B->nodes), "delta")))
     return bail(rc);
@@ -436,6 +511,12 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
   B->gg.jacobi_Y = B->d_Y;
   B->gg.jacobi_D = B->d_D;
   B->gg.jacobi_nodes = B->nodes;
+  B->xg.d_table = B->d_table_xcd;
+  B->xg.d_segs = B->d_segs;
+  B->xg.d_bins = B->d_bins;
+  B->xg.d_counters = B->d_xcd_counters;
+  B->xg.k = k;
+  B->xg.degree = degree;
   if ((rc = build_global_chunks(B)) != LAYOUT_OK) return bail(rc);
   {
     std::vector<GraphDesc> lt;
@@ -570,6 +651,9 @@ int layout_batch_get_info(const layout_batch_t* B, layout_batch_info* info) {
   info->update_mode_global = B->mode_global;
   info->update_mode_lds = B->mode_lds;
   info->epochs_done = B->ran ? B->epochs : 0;
+  info->xcd_engine = B->xcd_mode ? 1 : 0;
+  info->xcd_grid_blocks = B->xcd_mode ? B->xg.grid : 0;
+  if (B->xcd_mode) info->grid_blocks = B->xg.grid;
   return LAYOUT_OK;
 }
 
@@ -600,6 +684,34 @@ int layout_batch_autotune(layout_batch_t* B, int32_t trial_epochs, const char* c
       B->bundle = bundles[bi];
       B->hub = kHubFactor * bundles[bi];
       if ((rc = build_global_chunks(B)) != LAYOUT_OK) break;
+      if (B->xcd_mode) {
+        // the XCD-local engine's workers follow from the lane caps: only the
+        // chunk size is searched
+        if ((rc = upload_xcd_table(B)) != LAYOUT_OK) break;
+        const int64_t nctr = int64_t(B->epochs) * B->count;
+        launch_fill_i32(B->stream, B->d_xcd_counters, nctr, 0);
+        rc = launch_xcd_group_epochs(B->stream, B->xg, 0, 1);  // warm-up
+        if (rc == LAYOUT_OK) {
+          launch_fill_i32(B->stream, B->d_xcd_counters, nctr, 0);
+          e = hipEventRecord(a, B->stream);
+        }
+        const int32_t trials = std::min(trial_epochs, B->epochs);
+        if (rc == LAYOUT_OK && e == hipSuccess) rc = launch_xcd_group_epochs(B->stream, B->xg, 0, trials);
+        if (rc == LAYOUT_OK && e == hipSuccess) e = hipEventRecord(b, B->stream);
+        if (rc == LAYOUT_OK && e == hipSuccess) e = hipEventSynchronize(b);
+        float t = 0.f;
+        if (rc == LAYOUT_OK && e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+        const float tt = t * float(trial_epochs) / float(trials);
+        if (rc == LAYOUT_OK && e == hipSuccess && (best_ms < 0 || tt < best_ms)) {
+          best_ms = tt;
+          best_b = bundles[bi];
+          best_p = 0;
+        }
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(B->d_Y, saved, sizeof(float2) * size_t(B->nodes),
+                             hipMemcpyDeviceToDevice, B->stream);
+        continue;
+      }
       for (int pi = 0; pi < 4 && e == hipSuccess && rc == LAYOUT_OK; ++pi) {
         GlobalGroup g = B->gg;
         g.grid = 0;

@@ -27,7 +27,6 @@ inline int lds_lanes_for(int32_t n, int nodes_per_lane) {
   return lanes < 64 ? 64 : (lanes > 256 ? 256 : lanes);
 }
 constexpr long long kLdsAutoMaxEdges = 400000;  // AUTO picks LDS below this many directed edges
-constexpr int kXcds = 8;                             // accelerator complex dies of the device
 constexpr long long kXcdMaxPositionBytes = 3 << 20;  // XCD-local engine: positions within 3 MiB
                                                      // of the 4 MiB L2 of one XCD
 
@@ -101,6 +100,25 @@ struct LdsGroup {
   bool degree = false;
   int block = 256;
 };
+// Global-group graphs on the XCD-local engine (see desc.hpp).
+struct XcdGroup {
+  const GraphDesc* d_table = nullptr;
+  const XcdSeg* d_segs = nullptr;
+  const XcdBin* d_bins = nullptr;
+  int32_t* d_counters = nullptr;  // [epoch][segment] chunk counters, zero before the epochs run
+  int32_t n_segs = 0;
+  int k = 5;
+  bool degree = false;
+  int grid = 0;  // kXcds x the largest bin's workers
+  int64_t total_chunks = 0;
+};
+// Bins, segments and rounds for the graphs of `graphs` (n_chunks set); fills
+// the launch table (slice/chunk_base per segment), segs and bins; returns the
+// launch grid.
+int plan_xcd_bins(const std::vector<GraphDesc>& graphs, int nodes_per_lane,
+                  std::vector<GraphDesc>& table, std::vector<XcdSeg>& segs, XcdBin* bins);
+int launch_xcd_group_epochs(hipStream_t stream, const XcdGroup& g, int32_t dt, int32_t count);
+void launch_fill_i32(hipStream_t stream, int32_t* p, int64_t n, int32_t v);
 int lds_bytes_for(int32_t n);
 // Cuts the chunks of the graphs in table (host copy, n_chunks set) into
 // rounds for a launch of `lanes` lanes: sets each entry's slice/chunk_base and

@@ -37,4 +37,26 @@ struct GraphDesc {
   SamplerConsts sc;
 };
 
+// Multi-graph launches on the XCD-local engine.  The graphs are split into
+// bins, one per XCD; a bin's graphs run in sequence segments whose positions
+// fit the XCD's L2 together, each segment with its own lane cap and chunk
+// counter.  Inside a segment the chunk positions are cut into rounds as for
+// the global engine (GraphDesc::slice, chunk_base).
+constexpr int kXcds = 8;  // accelerator complex dies of the device
+
+struct XcdSeg {
+  int64_t total_index;  // positions of the segment (rounds x round_size)
+  int64_t round_size;   // positions per round (sum of the slices of its graphs)
+  int32_t table_begin;  // first table entry of the segment
+  int32_t G;            // table entries of the segment
+  int32_t workers;      // workgroups that serve the segment (its graphs' lane cap)
+  int32_t pad0;
+};
+
+struct XcdBin {
+  int32_t seg_begin, seg_count;  // the bin's segments, run in this order
+  int32_t workers;               // the most workers any of its segments takes
+  int32_t pad0;
+};
+
 }  // namespace snap

@@ -46,6 +46,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "desc.hpp"
 #include "rng.hpp"
 
@@ -386,6 +388,56 @@ static __global__ void __launch_bounds__(256)
     if (c < n_chunks)
       process_chunk<K, kStore, DEGREE, XcdLocalMem>(g, g.Y, g.D, g.chunk_offset + c, t, eta);
   }
+}
+
+// One epoch of many graphs on the XCD-local engine.  Workgroup w of the launch
+// runs on XCD w mod kXcds (round-robin dispatch), reads which XCD it is on,
+// and walks that XCD's bin segment by segment; it serves a segment if it is
+// among the segment's first `workers` workgroups (the segment's lane cap),
+// taking 64 positions per wave at a time from the segment's counter, and
+// otherwise moves on to the next segment.
+// FIXUP: run after the main launch, one workgroup per bin (bin = workgroup
+// index mod kXcds), with device-coherent accesses; it finishes whatever
+// positions the main launch left unclaimed (none when every XCD received its
+// workgroups), so the epoch completes whatever the dispatch order.
+// counters: [epoch][segment], zero before the epoch.
+template <int K, bool DEGREE, bool FIXUP>
+static __global__ void __launch_bounds__(256)
+    epoch_xcd_group_kernel(const GraphDesc* __restrict__ table, const XcdSeg* __restrict__ segs,
+                           int32_t n_segs, const XcdBin* __restrict__ bins, int32_t* counters,
+                           int32_t dt) {
+  using Mem = typename std::conditional<FIXUP, GlobalMem, XcdLocalMem>::type;
+  const int32_t x = FIXUP ? static_cast<int32_t>(blockIdx.x % kXcds) : xcd_id();
+  if (x >= kXcds) return;
+  const XcdBin b = bins[x];
+  const int32_t worker = static_cast<int32_t>(blockIdx.x / kXcds);
+  const int lane = static_cast<int>(threadIdx.x & 63);
+  for (int32_t q = 0; q < b.seg_count; ++q) {
+    const int32_t si = b.seg_begin + q;
+    const XcdSeg sg = segs[si];
+    if (!FIXUP && worker >= sg.workers) continue;
+    int32_t* ctr = counters + static_cast<int64_t>(dt) * n_segs + si;
+    while (true) {
+      int32_t base = 0;
+      if (lane == 0) base = atomicAdd(ctr, 64);
+      base = __shfl(base, 0, 64);
+      if (base >= sg.total_index) break;
+      const int64_t c = static_cast<int64_t>(base) + lane;
+      if (c >= sg.total_index) continue;
+      const int64_t r = c / sg.round_size;
+      const int64_t w = c - r * sg.round_size;
+      const GraphDesc& g = table[sg.table_begin + find_graph(table + sg.table_begin, sg.G, w)];
+      const int64_t local = r * g.slice + (w - g.chunk_base);
+      if (local >= g.n_chunks) continue;  // past this graph's last chunk
+      const int32_t t = g.t0 + dt;
+      process_chunk<K, kStore, DEGREE, Mem>(g, g.Y, g.D, g.chunk_offset + local, t, eta_of(g, t));
+    }
+  }
+}
+
+static __global__ void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 // Whole epochs [dt, dt + count) of one small graph per workgroup, positions in

@@ -299,6 +299,9 @@ int run_round(layout_server_t* S) {
     gg.block = S->opts.block_threads && S->opts.block_threads <= 256 ? S->opts.block_threads : 256;
     gg.grid = S->opts.grid_blocks;
     gg.max_lanes = fair_lanes(gt, S->opts.nodes_per_lane);
+    if (!S->opts.block_threads)  // small lane caps get small workgroups
+      gg.block = static_cast<int>(
+          std::min<int64_t>(256, std::max<int64_t>(64, div_up(std::max<int64_t>(1, gg.max_lanes), 64) * 64)));
     plan_rounds(gt, gg, int64_t(global_grid(gg)) * gg.block);
     e = hipMemcpyAsync(S->d_table, gt.data(), sizeof(GraphDesc) * gt.size(), hipMemcpyHostToDevice,
                        S->stream);

@@ -335,6 +335,102 @@ int64_t snap::fair_lanes(const std::vector<GraphDesc>& table, int nodes_per_lane
   return best < 1.0 ? 1 : static_cast<int64_t>(best);
 }
 
+int snap::plan_xcd_bins(const std::vector<GraphDesc>& graphs, int nodes_per_lane,
+                        std::vector<GraphDesc>& table, std::vector<XcdSeg>& segs, XcdBin* bins) {
+  table.clear();
+  segs.clear();
+  std::vector<std::vector<int>> members(kXcds);
+  {
+    // longest-processing-time assignment by edges: biggest graph first, each
+    // to the least loaded bin
+    std::vector<int> order(graphs.size());
+    for (size_t q = 0; q < graphs.size(); ++q) order[q] = static_cast<int>(q);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return graphs[a].nnz > graphs[b].nnz; });
+    int64_t load[kXcds] = {0};
+    for (int q : order) {
+      int x = 0;
+      for (int y = 1; y < kXcds; ++y)
+        if (load[y] < load[x]) x = y;
+      members[x].push_back(q);
+      load[x] += graphs[q].nnz;
+    }
+  }
+  const int cus_per_xcd = std::max(1, device_props().cus / kXcds);
+  int grid = 0;
+  for (int x = 0; x < kXcds; ++x) {
+    XcdBin& b = bins[x];
+    b = XcdBin{};
+    b.seg_begin = static_cast<int32_t>(segs.size());
+    // sequence segments whose positions fit the L2 together
+    std::vector<std::vector<int>> parts;
+    int64_t bytes = 0;
+    for (int q : members[x]) {
+      const int64_t need = int64_t(graphs[q].n) * 8;
+      if (parts.empty() || bytes + need > kXcdMaxPositionBytes) {
+        parts.emplace_back();
+        bytes = 0;
+      }
+      parts.back().push_back(q);
+      bytes += need;
+    }
+    for (const auto& part : parts) {
+      // workers: the segment's lane cap, at most one workgroup per CU
+      std::vector<GraphDesc> sub;
+      for (int q : part) sub.push_back(graphs[q]);
+      const int64_t cap = fair_lanes(sub, nodes_per_lane);
+      XcdSeg sg{};
+      sg.workers = static_cast<int32_t>(
+          std::min<int64_t>(cus_per_xcd, std::max<int64_t>(1, div_up(cap, 256))));
+      sg.table_begin = static_cast<int32_t>(table.size());
+      sg.G = static_cast<int32_t>(part.size());
+      int64_t total = 0;
+      for (int q : part) total += graphs[q].n_chunks;
+      const int64_t rounds = std::max<int64_t>(1, div_up(2 * total, int64_t(sg.workers) * 256));
+      int64_t base = 0;
+      for (int q : part) {
+        GraphDesc d = graphs[q];
+        d.slice = div_up(d.n_chunks, rounds);
+        d.chunk_base = base;
+        base += d.slice;
+        table.push_back(d);
+      }
+      sg.round_size = std::max<int64_t>(1, base);
+      sg.total_index = rounds * sg.round_size;
+      segs.push_back(sg);
+      b.workers = std::max(b.workers, sg.workers);
+    }
+    b.seg_count = static_cast<int32_t>(segs.size()) - b.seg_begin;
+    grid = std::max(grid, b.workers);
+  }
+  return grid * kXcds;
+}
+
+void snap::launch_fill_i32(hipStream_t stream, int32_t* p, int64_t n, int32_t v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(div_up(n, 256)), dim3(256), 0, stream, p, n, v);
+}
+
+int snap::launch_xcd_group_epochs(hipStream_t stream, const XcdGroup& g, int32_t dt,
+                                  int32_t count) {
+  if (g.total_chunks == 0 || count <= 0 || g.grid <= 0) return LAYOUT_OK;
+  return with_k(g.k, [&](auto kc) -> int {
+    constexpr int K = decltype(kc)::value;
+    return with_degree(g.degree, [&](auto dc) -> int {
+      constexpr bool DEG = decltype(dc)::value;
+      for (int32_t ep = 0; ep < count; ++ep) {
+        hipLaunchKernelGGL((epoch_xcd_group_kernel<K, DEG, false>), dim3(g.grid), dim3(256), 0,
+                           stream, g.d_table, g.d_segs, g.n_segs, g.d_bins, g.d_counters, dt + ep);
+        hipLaunchKernelGGL((epoch_xcd_group_kernel<K, DEG, true>), dim3(kXcds), dim3(256), 0,
+                           stream, g.d_table, g.d_segs, g.n_segs, g.d_bins, g.d_counters, dt + ep);
+      }
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "epoch_xcd_group_kernel launch");
+      return LAYOUT_OK;
+    });
+  });
+}
+
 int snap::launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t dt,
                                int32_t count) {
   if (g.total_chunks == 0 || count <= 0) return LAYOUT_OK;

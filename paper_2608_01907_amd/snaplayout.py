@@ -93,6 +93,7 @@ class layout_batch_info(ctypes.Structure):
         ("grid_blocks", ctypes.c_int32), ("block_threads", ctypes.c_int32),
         ("lds_block_threads", ctypes.c_int32), ("update_mode_global", ctypes.c_int32),
         ("update_mode_lds", ctypes.c_int32), ("epochs_done", ctypes.c_int32),
+        ("xcd_engine", ctypes.c_int32), ("xcd_grid_blocks", ctypes.c_int32),
     ]
 
 

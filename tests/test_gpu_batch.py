@@ -50,6 +50,8 @@ def test_batch_groups_and_draws_bit_exact(mix):
         info = B.info()
         assert info["graphs"] == len(mix)
         assert info["lds_graphs"] >= 4 and info["global_graphs"] >= 2
+        # every non-LDS graph fits one XCD's L2, so they run on XCD bins
+        assert info["xcd_engine"] == 1 and info["xcd_grid_blocks"] % 8 == 0
         for q, g in enumerate(mix):
             if g.nnz == 0:
                 continue
@@ -72,14 +74,17 @@ def test_batch_jacobi_equals_single_graph(mix):
         assert np.abs(got[q] - alone).max() <= tol, q
 
 
-def test_batch_hogwild_quality_alone_and_in_mix(mix):
+@pytest.mark.parametrize("engine", [SL.LAYOUT_ENGINE_AUTO, SL.LAYOUT_ENGINE_GLOBAL])
+def test_batch_hogwild_quality_alone_and_in_mix(mix, engine):
     """Lock-free runs are not bit-reproducible, so each side is the mean over
-    two seeds (the same two seeds alone and in the mix)."""
+    three seeds (the same seeds alone and in the mix).  AUTO puts the larger
+    graphs on XCD bins; GLOBAL keeps them in the all-CU multi-graph launch."""
     T = 40
-    seeds = (100, 700)
+    seeds = (100, 700, 1300)
     inmix = {}
     for s0 in seeds:
-        with SL.BatchLayout(_desc(mix, s0), k=5, epochs=T) as B:
+        with SL.BatchLayout(_desc(mix, s0), k=5, epochs=T, engine=engine) as B:
+            assert B.info()["xcd_engine"] == (1 if engine == SL.LAYOUT_ENGINE_AUTO else 0)
             B.run()
             for q in range(len(mix)):
                 inmix[(q, s0)] = B.positions(q)

@@ -19,22 +19,29 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def _check(name, maker):
+    """Lock-free layouts vary from run to run, so the GPU runs every seed the
+    reference holds and the means are compared."""
     ref = json.load(open(os.path.join(GOLDEN, f"quality_{name}.json")))
-    run0 = [r for r in ref["runs"] if r["seed"] == 0][0]
     g = S.cached(ref.get("graph", name), maker)
     init = SL.LAYOUT_INIT_PMDS if ref.get("init") == "pmds" else SL.LAYOUT_INIT_UNIFORM
-    with SL.Layout(g.row_ptr, g.col, g.n, k=ref["k"], epochs=ref["epochs"], seed=0,
-                   init_mode=init) as L:
-        L.run()
-        Y = L.positions()
-        info = L.info()
-    assert np.all(np.isfinite(Y))
-    q_np = M.np_score(g.row_ptr, g.col, Y, sample=ref["np_sample"], seed=ref["metric_seed"])
-    q_si = M.si_score(Y, g.labels, sample=ref["si_sample"], seed=ref["metric_seed"])
-    print(f"{name}: gpu np {q_np:.4f} si {q_si:.4f} | oracle np {run0['np']:.4f} "
-          f"si {run0['si']:.4f} | grid {info['grid_blocks']}", flush=True)
-    assert abs(q_np - run0["np"]) <= 0.01
-    assert abs(q_si - run0["si"]) <= 0.01
+    got = []
+    for run in ref["runs"]:
+        with SL.Layout(g.row_ptr, g.col, g.n, k=ref["k"], epochs=ref["epochs"], seed=run["seed"],
+                       init_mode=init) as L:
+            L.run()
+            Y = L.positions()
+            info = L.info()
+        assert np.all(np.isfinite(Y))
+        got.append({"np": M.np_score(g.row_ptr, g.col, Y, sample=ref["np_sample"],
+                                     seed=ref["metric_seed"]),
+                    "si": M.si_score(Y, g.labels, sample=ref["si_sample"],
+                                     seed=ref["metric_seed"])})
+    for key in ("np", "si"):
+        gpu = float(np.mean([q[key] for q in got]))
+        orc = float(np.mean([r[key] for r in ref["runs"]]))
+        print(f"{name}: {key} gpu {gpu:.4f} oracle {orc:.4f} ({len(got)} seeds, engine "
+              f"{info['engine']}, grid {info['grid_blocks']})", flush=True)
+        assert abs(gpu - orc) <= 0.01, (key, got, ref["runs"])
 
 
 def test_quality_orkut_like_259k():
