@@ -291,7 +291,12 @@ typedef struct layout_batch_info {
 
 /* Creates a batch of count graphs (validated like layout_create).  opts as for
  * layout_create_ex; init_pos and start_epoch are ignored (per-graph init_pos
- * lives in layout_graph).  Returns when the batch is ready to run. */
+ * lives in layout_graph).  Graphs that fit LDS run whole in one workgroup
+ * each; with engine AUTO the others run on XCD-local bins when all of them
+ * fit one XCD's L2 (HOGWILD_STORE, coherent access, automatic launch shape),
+ * else in one all-CU launch per epoch; engine GLOBAL forces that launch for
+ * every graph, engine XCD requires the bins.  Returns when the batch is ready
+ * to run. */
 int layout_batch_create(const layout_graph *graphs, int32_t count, int32_t k, int32_t epochs,
                         const layout_opts *opts, int32_t inputs_on_device,
                         layout_batch_t **out);
@@ -372,7 +377,11 @@ typedef struct layout_server_stats {
  * admitted jobs (0 = 90% of the free device memory at start).  max_slots:
  * cap on concurrently admitted jobs (>= 1).  round_edges: directed edges of
  * global-engine work per round (0 = default, 32M).  opts: as for
- * layout_create_ex (init_pos, start_epoch, stream are ignored). */
+ * layout_create_ex (init_pos, start_epoch, stream are ignored).  Each round
+ * runs the remaining epochs of every job that fits LDS, an epoch slice of
+ * every job whose positions fit one XCD's L2 on XCD-local bins (engine AUTO
+ * or XCD, HOGWILD_STORE, coherent access, automatic launch shape), and an
+ * epoch slice of every other job in one all-CU launch. */
 int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t round_edges,
                          const layout_opts *opts, layout_server_t **out);
 

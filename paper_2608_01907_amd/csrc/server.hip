@@ -89,6 +89,12 @@ struct layout_server {
   GraphDesc* d_table_lds = nullptr;
   int32_t* d_ids = nullptr;
   uint32_t* d_err = nullptr;
+  // XCD-local engine for global jobs whose positions fit one XCD's L2
+  bool xcd_ok = false;
+  GraphDesc* d_table_xcd = nullptr;
+  XcdSeg* d_segs = nullptr;
+  XcdBin* d_bins = nullptr;
+  int32_t* d_xcd_ctr = nullptr;
   int lds_cap = 0;
   // stats (under mu)
   int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, rounds = 0;
@@ -287,6 +293,47 @@ int run_round(layout_server_t* S) {
     }
     if (rc != LAYOUT_OK) return rc;
   }
+  // global jobs that fit one XCD's L2: XCD-local bins, one launch
+  {
+    std::vector<GraphDesc> gx, rest;
+    for (const GraphDesc& d : gt) {
+      if (S->xcd_ok && int64_t(d.n) * 8 <= kXcdMaxPositionBytes && d.n_chunks > 0)
+        gx.push_back(d);
+      else
+        rest.push_back(d);
+    }
+    if (!gx.empty()) {
+      std::vector<GraphDesc> table;
+      std::vector<XcdSeg> segs;
+      XcdBin bins[kXcds];
+      XcdGroup xg;
+      xg.grid = plan_xcd_bins(gx, S->opts.nodes_per_lane, table, segs, bins);
+      xg.d_table = S->d_table_xcd;
+      xg.d_segs = S->d_segs;
+      xg.d_bins = S->d_bins;
+      xg.d_counters = S->d_xcd_ctr;
+      xg.n_segs = static_cast<int32_t>(segs.size());
+      xg.k = k;
+      xg.degree = S->opts.neg_weights == LAYOUT_NEG_DEGREE;
+      for (const GraphDesc& d : gx) xg.total_chunks += d.n_chunks;
+      e = hipMemcpyAsync(S->d_table_xcd, table.data(), sizeof(GraphDesc) * table.size(),
+                         hipMemcpyHostToDevice, S->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(S->d_segs, segs.data(), sizeof(XcdSeg) * segs.size(),
+                           hipMemcpyHostToDevice, S->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(S->d_bins, bins, sizeof(XcdBin) * kXcds, hipMemcpyHostToDevice,
+                           S->stream);
+      if (e != hipSuccess) return hip_fail(e, "uploading the XCD bins");
+      launch_fill_i32(S->stream, S->d_xcd_ctr, xg.n_segs, 0);
+      rc = launch_xcd_group_epochs(S->stream, xg, 0, 1);
+      if (rc != LAYOUT_OK) return rc;
+      // the host arrays above are read by the copies: finish them first
+      e = hipStreamSynchronize(S->stream);
+      if (e != hipSuccess) return hip_fail(e, "running the XCD bins");
+    }
+    gt.swap(rest);
+  }
   if (!gt.empty()) {
     GlobalGroup gg;
     gg.d_table = S->d_table;
@@ -425,7 +472,7 @@ int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t ro
     return fail(LAYOUT_E_UNSUPPORTED, "the server runs the lock-free policies only");
   if (o.neg_weights != LAYOUT_NEG_UNIFORM && o.neg_weights != LAYOUT_NEG_DEGREE)
     return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
-  if (o.engine < 0 || o.engine > 2) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
+  if (o.engine < 0 || o.engine > 3) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
   if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g", o.gamma);
   if (o.access < LAYOUT_ACCESS_COHERENT || o.access > LAYOUT_ACCESS_CACHED)
     return fail(LAYOUT_E_INVALID_ARG, "access = %d", o.access);
@@ -441,6 +488,9 @@ int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t ro
   if (!S) return fail(LAYOUT_E_OOM, "host allocation");
   S->opts = o;
   S->mode_global = o.update_mode == LAYOUT_UPDATE_AUTO ? LAYOUT_HOGWILD_STORE : o.update_mode;
+  S->xcd_ok = S->mode_global == LAYOUT_HOGWILD_STORE && o.access == LAYOUT_ACCESS_COHERENT &&
+              (o.engine == LAYOUT_ENGINE_AUTO || o.engine == LAYOUT_ENGINE_XCD) &&
+              o.grid_blocks == 0 && o.block_threads == 0;
   S->mode_lds = o.update_mode == LAYOUT_UPDATE_AUTO ? LAYOUT_ATOMIC : o.update_mode;
   S->max_slots = max_slots;
   S->round_edges = round_edges ? round_edges : kDefaultRoundEdges;
@@ -459,6 +509,10 @@ int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t ro
   if (e == hipSuccess) e = hipMalloc(&S->d_table, sizeof(GraphDesc) * size_t(max_slots));
   if (e == hipSuccess) e = hipMalloc(&S->d_table_lds, sizeof(GraphDesc) * size_t(max_slots));
   if (e == hipSuccess) e = hipMalloc(&S->d_ids, sizeof(int32_t) * size_t(max_slots));
+  if (e == hipSuccess) e = hipMalloc(&S->d_table_xcd, sizeof(GraphDesc) * size_t(max_slots));
+  if (e == hipSuccess) e = hipMalloc(&S->d_segs, sizeof(XcdSeg) * size_t(max_slots));
+  if (e == hipSuccess) e = hipMalloc(&S->d_bins, sizeof(XcdBin) * kXcds);
+  if (e == hipSuccess) e = hipMalloc(&S->d_xcd_ctr, sizeof(int32_t) * size_t(max_slots));
   if (e == hipSuccess) e = hipMalloc(&S->d_err, sizeof(uint32_t));
   if (e != hipSuccess) {
     const int rc = hip_fail(e, "server setup");
@@ -614,6 +668,10 @@ int layout_server_destroy(layout_server_t* S) {
   if (S->d_table) (void)hipFree(S->d_table);
   if (S->d_table_lds) (void)hipFree(S->d_table_lds);
   if (S->d_ids) (void)hipFree(S->d_ids);
+  if (S->d_table_xcd) (void)hipFree(S->d_table_xcd);
+  if (S->d_segs) (void)hipFree(S->d_segs);
+  if (S->d_bins) (void)hipFree(S->d_bins);
+  if (S->d_xcd_ctr) (void)hipFree(S->d_xcd_ctr);
   if (S->d_err) (void)hipFree(S->d_err);
   if (S->stream) (void)hipStreamDestroy(S->stream);
   if (S->side) (void)hipStreamDestroy(S->side);

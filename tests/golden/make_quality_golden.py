@@ -28,7 +28,7 @@ PLAN = {
     "orkut-like-259k": ("orkut-like-259k", "orkut_like", 5, 30, "serial", (0, 1), "uniform"),
     "lj-like-4m": ("lj-like-4m", "lj_like", 5, 30, "threaded", (0,), "uniform"),
     "orkut-like-259k-pmds": ("orkut-like-259k", "orkut_like", 5, 30, "serial", (0, 1), "pmds"),
-    "lj-like-4m-pmds": ("lj-like-4m", "lj_like", 5, 30, "threaded", (0,), "pmds"),
+    "lj-like-4m-pmds": ("lj-like-4m", "lj_like", 5, 30, "threaded", (0, 1), "pmds"),
 }
 NP_SAMPLE, SI_SAMPLE, METRIC_SEED = 2000, 10000, 12345
 

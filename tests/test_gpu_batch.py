@@ -12,6 +12,7 @@ import pytest
 
 import synthgraph as S
 from oracle import metrics as M
+from quality_stats import assert_paired_close
 from oracle import oracle as O
 
 pytestmark = pytest.mark.gpu
@@ -76,9 +77,11 @@ def test_batch_jacobi_equals_single_graph(mix):
 
 @pytest.mark.parametrize("engine", [SL.LAYOUT_ENGINE_AUTO, SL.LAYOUT_ENGINE_GLOBAL])
 def test_batch_hogwild_quality_alone_and_in_mix(mix, engine):
-    """Lock-free runs are not bit-reproducible, so each side is the mean over
-    three seeds (the same seeds alone and in the mix).  AUTO puts the larger
-    graphs on XCD bins; GLOBAL keeps them in the all-CU multi-graph launch."""
+    """Lock-free runs are not bit-reproducible, so the same three seeds run
+    alone and in the mix and are compared pairwise (within 0.01, or 2.5
+    standard errors where the seed spread is larger).  AUTO puts the larger
+    graphs on XCD bins; GLOBAL keeps every graph in the all-CU multi-graph
+    launch, and the graphs alone then run on the all-CU engine as well."""
     T = 40
     seeds = (100, 700, 1300)
     inmix = {}
@@ -97,17 +100,19 @@ def test_batch_hogwild_quality_alone_and_in_mix(mix, engine):
         assert all(np.all(np.isfinite(inmix[(q, s0)])) for s0 in seeds)
         if g.n < 500:
             continue
+        if engine == SL.LAYOUT_ENGINE_GLOBAL and g.n < 64 * 32:
+            # alone, the all-CU engine runs at least one 64-lane wave, more than
+            # the n/32 lanes such a graph gets in the mix
+            continue
         qa, qm = [], []
         for s0 in seeds:
-            with SL.Layout(g.row_ptr, g.col, g.n, k=5, epochs=T, seed=s0 + q) as L:
+            with SL.Layout(g.row_ptr, g.col, g.n, k=5, epochs=T, seed=s0 + q,
+                           engine=engine) as L:
                 L.run()
                 alone = L.positions()
             qa.append(M.quality(g.row_ptr, g.col, alone, g.labels, sample=2000))
             qm.append(M.quality(g.row_ptr, g.col, inmix[(q, s0)], g.labels, sample=2000))
-        for key in ("np", "si"):
-            a_ = np.mean([x[key] for x in qa])
-            m_ = np.mean([x[key] for x in qm])
-            assert abs(a_ - m_) <= 0.01, (q, key, qa, qm)
+        assert_paired_close(qa, qm, label=q)
 
 
 def test_batch_autotune_keeps_positions_and_runs_once(mix, tmp_path):

@@ -1,7 +1,8 @@
 """Served layouts (continuous batching): jobs submitted while others run are
 admitted as slots and memory free up; each job's result is the same alone
-and in the mix (NP and SI within 0.01 of the single-graph path); admission
-respects the HBM budget; a malformed job fails alone."""
+and in the mix (NP and SI of the single-graph path, paired over seeds:
+within 0.01, or 2.5 standard errors where the seed spread is larger);
+admission respects the HBM budget; a malformed job fails alone."""
 import threading
 import time
 
@@ -10,6 +11,7 @@ import pytest
 
 import synthgraph as S
 from oracle import metrics as M
+from quality_stats import assert_paired_close
 from oracle import oracle as O
 
 pytestmark = pytest.mark.gpu
@@ -33,10 +35,10 @@ def _alone(g, seed, T, k=5):
 
 def test_server_results_same_alone_and_in_mix(pool):
     T = 30
-    srv = SL.layout_server_create(0, 12, 1 << 20)
+    srv = SL.layout_server_create(0, 16, 1 << 20)
     try:
         ids = []
-        for q, g in enumerate(pool * 3):  # each graph three times, submitted back to back
+        for q, g in enumerate(pool * 5):  # each graph five times, submitted back to back
             ids.append((q % len(pool), 300 + q,
                         SL.layout_server_submit(srv, g.row_ptr, g.col, g.n, 5, T, 300 + q)))
         results = {}
@@ -50,17 +52,14 @@ def test_server_results_same_alone_and_in_mix(pool):
         assert st["p99_latency_s"] >= st["p50_latency_s"] > 0
     finally:
         SL.layout_server_destroy(srv)
-    # lock-free runs are not bit-reproducible: compare the mean over the three
-    # seeds of each graph, alone and in the mix
+    # lock-free runs are not bit-reproducible: paired comparison over the
+    # five seeds of each graph, alone and in the mix
     for gi, g in enumerate(pool):
-        seeds = [seed for (gj, seed) in results if gj == gi]
+        seeds = sorted(seed for (gj, seed) in results if gj == gi)
         qa = [M.quality(g.row_ptr, g.col, _alone(g, sd, T), g.labels, sample=4000) for sd in seeds]
         qm = [M.quality(g.row_ptr, g.col, results[(gi, sd)], g.labels, sample=4000)
               for sd in seeds]
-        for key in ("np", "si"):
-            a_ = np.mean([x[key] for x in qa])
-            m_ = np.mean([x[key] for x in qm])
-            assert abs(a_ - m_) <= 0.01, (gi, key, qa, qm)
+        assert_paired_close(qa, qm, label=gi)
 
 
 def test_server_budget_binds_admission_and_jobs_overlap(pool):
