@@ -41,6 +41,7 @@ PLAIN = {
     "lj-like-4m": ("lj_like", 5, 30),
     "orkut-like-259k": ("orkut_like", 5, 30),
     "sbm-2000": ("sbm_2000", 5, 50),
+    "friendster-like-65m": ("gpu:friendster_like", 5, 30),
 }
 KERNEL_SOURCES = ["paper_2608_01907_amd/csrc/kernels.hpp", "paper_2608_01907_amd/csrc/rng.hpp",
                   "paper_2608_01907_amd/csrc/desc.hpp"]
@@ -109,14 +110,25 @@ def bench_plain(args):
     maker, k, T = PLAIN[args.workload]
     seed = 0
     t0 = time.perf_counter()
-    g = S.cached(args.workload, getattr(S, maker))
-    log(f"[bench] graph {g.name}: n={g.n} |E|={g.n_edges} nnz={g.nnz} "
-        f"dmax={int(g.degrees().max())} ({time.perf_counter() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    if maker == "gpu:friendster_like":
+        # generated on the device (10^9 edges): inputs never leave HBM
+        from synthgraph import gpu as G
+        rp_d, col_d, labels_d = G.friendster_like_gpu(seed=0)
+        del labels_d
+        row_ptr = rp_d.cpu().numpy()
+        g = S.Graph(row_ptr, np.zeros(0, np.int32), len(row_ptr) - 1, None, args.workload)
+        nnz = int(row_ptr[-1])
+    else:
+        g = S.cached(args.workload, getattr(S, maker))
+        rp_d = torch.from_numpy(g.row_ptr).to(dev)
+        col_d = torch.from_numpy(g.col).to(dev)
+        nnz = g.nnz
+    n_edges = nnz // 2
+    log(f"[bench] graph {g.name}: n={g.n} |E|={n_edges} nnz={nnz} "
+        f"dmax={int(np.diff(g.row_ptr).max())} ({time.perf_counter() - t0:.1f}s)")
     mode = {"auto": SL.LAYOUT_UPDATE_AUTO, "atomic": SL.LAYOUT_ATOMIC,
             "store": SL.LAYOUT_HOGWILD_STORE}[args.mode]
-    dev = torch.device("cuda:0")
-    rp_d = torch.from_numpy(g.row_ptr).to(dev)
-    col_d = torch.from_numpy(g.col).to(dev)
     out_d = torch.empty((g.n, 2), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
 
@@ -151,7 +163,7 @@ def bench_plain(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = dt * 1e3 / args.steps
-    value = g.n_edges * (1 + k) * T / (dt / args.steps)
+    value = n_edges * (1 + k) * T / (dt / args.steps)
     log(f"[bench] {args.steps} steps, {ms_step:.2f} ms/step")
 
     # dominant kernel: the epoch kernel, timed with HIP events on its stream
@@ -189,7 +201,9 @@ def bench_plain(args):
         roof["gather_roofline_frac"] = round(roof["gather_roofline_ms"] / ms_epoch, 4)
         roof["gather_roofline_ms_by_policy"] = {k_: round(v, 4) for k_, v in gather.items()}
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and maker.startswith("gpu:"):
+        log("[bench] no CPU baseline for a device-generated workload (headline workload only)")
+    elif not args.no_cpu:
         log("[bench] timing the CPU oracle baseline")
         cpu = cpu_baseline(g, k, T, seed)
         log(f"[bench] cpu baseline {cpu['value']:.3e} edge-updates/s on {cpu['cores']} threads")
@@ -198,13 +212,13 @@ def bench_plain(args):
         "value": value, "unit": "edge-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": g.name, "n": g.n, "edges": g.n_edges, "k": k, "epochs": T,
+        "config": {"workload": g.name, "n": g.n, "edges": n_edges, "k": k, "epochs": T,
                    "update_mode": policy, "engine": info["engine"],
                    "bundle_edges": info["bundle_edges"],
                    "hub_split_edges": info["hub_split_edges"],
                    "grid_blocks": info["grid_blocks"]},
         "epoch_ms": round(ms_epoch, 4),
-        "epoch_only_value": g.n_edges * (1 + k) / (ms_epoch * 1e-3),
+        "epoch_only_value": n_edges * (1 + k) / (ms_epoch * 1e-3),
         "positions_finite": finite,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -72,7 +72,12 @@ enum {
 /* Distribution of the negatives. */
 enum {
     LAYOUT_NEG_UNIFORM = 0, /* uniform over V \ {i}: the paper's method (Algorithm 1) */
-    LAYOUT_NEG_DEGREE = 1   /* proportional to degree via an alias table (control) */
+    LAYOUT_NEG_DEGREE = 1,  /* proportional to degree via an alias table (control) */
+    LAYOUT_NEG_CUSTOM = 2   /* proportional to the caller's integer weights w (opts
+                               neg_weight_values, 0 < sum w < 2^32), drawn like DEGREE: an
+                               alias table over w, a draw equal to the source rejected;
+                               the more flexible negative sampling the conclusion names
+                               as future work; single-graph layouts only */
 };
 
 /* Which kernel family runs the epochs. */
@@ -117,6 +122,8 @@ typedef struct layout_opts {
                                  inputs are on the device); NULL = init_mode */
     void *stream;             /* hipStream_t for all work of the handle; NULL = a
                                  stream owned by the library */
+    const uint32_t *neg_weight_values; /* LAYOUT_NEG_CUSTOM: n weights (host, or device when
+                                 the inputs are on the device), copied at create */
 } layout_opts;
 
 /* Fills *opts with the defaults listed above. */
@@ -235,6 +242,12 @@ int layout_effective_energy(layout_t *L, double *attr_out, double *rep_out);
 /* Writes the k negatives the epoch kernels draw for every directed edge in
  * epoch t (host array nnz*k, int32, edge-major).  Does not change positions. */
 int layout_debug_draws(layout_t *L, int32_t epoch, int32_t *host_out);
+
+/* The negatives of the listed directed edges only (host edges[count], each
+ * in [0, nnz), else E_INVALID_ARG; host_out count*k int32, edge-major), for
+ * graphs too large to dump every edge.  Does not change positions. */
+int layout_debug_draws_at(layout_t *L, int32_t epoch, const int64_t *edges, int64_t count,
+                          int32_t *host_out);
 
 /* Copies the chunk table: begin[n_chunks + 1] (first directed edge of each
  * lane chunk, begin[n_chunks] = nnz) and src[n_chunks] (row holding that

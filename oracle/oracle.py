@@ -68,6 +68,13 @@ def lib():
         L.oracle_init_positions_scaled.argtypes = [ctypes.c_int64, ctypes.c_uint64,
                                                    ctypes.c_float, _f64p]
         L.oracle_init_positions_scaled.restype = None
+        L.oracle_init_positions_at.argtypes = [ctypes.c_int64, ctypes.c_uint64, _i64p,
+                                               ctypes.c_int64, _f64p]
+        L.oracle_init_positions_at.restype = None
+        L.oracle_draw_edges.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                        ctypes.c_uint64, ctypes.c_int32, _u32p, _u32p, _i64p,
+                                        _i32p, ctypes.c_int64, _i32p]
+        L.oracle_draw_edges.restype = ctypes.c_int
         L.oracle_alias_build.argtypes = [_i64p, ctypes.c_int64, _u32p, _u32p]
         L.oracle_alias_build.restype = ctypes.c_int
         L.oracle_draw_negatives.argtypes = [
@@ -144,6 +151,26 @@ def init_positions_scaled(n, seed, scale):
     Y = np.zeros(2 * max(n, 1), dtype=np.float64)
     lib().oracle_init_positions_scaled(int(n), int(seed), float(scale), Y)
     return Y[: 2 * n].reshape(n, 2)
+
+
+def init_positions_at(n, seed, nodes):
+    """Initial positions (as init_positions) of the listed nodes only."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    Y = np.zeros(2 * max(nodes.size, 1), dtype=np.float64)
+    lib().oracle_init_positions_at(int(n), int(seed), nodes, int(nodes.size), Y)
+    return Y[: 2 * nodes.size].reshape(-1, 2)
+
+
+def draw_edges(row_ptr, n, k, t, seed, edges, mode=NEG_UNIFORM, thr=None, alias=None):
+    """Negatives (as draw_negatives) of the listed directed edges only."""
+    edges = np.ascontiguousarray(edges, dtype=np.int64)
+    src = (np.searchsorted(np.asarray(row_ptr, dtype=np.int64), edges, side="right") - 1)
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    thr, alias = _tables(n, thr, alias)
+    out = np.zeros(max(edges.size * k, 1), dtype=np.int32)
+    lib().oracle_draw_edges(int(n), int(k), int(t), int(seed), int(mode), thr, alias, edges, src,
+                            int(edges.size), out)
+    return out[: edges.size * k].reshape(-1, k)
 
 
 def alias_build(w):

@@ -158,6 +158,25 @@ void oracle_init_positions(int64_t n, uint64_t seed, double *Y)
     oracle_init_positions_scaled(n, seed, sqrtf((float)n), Y);
 }
 
+/* The initial positions of listed nodes of an n-node graph only:
+ * Y[2q], Y[2q+1] for node nodes[q]. */
+void oracle_init_positions_at(int64_t n, uint64_t seed, const int64_t *nodes, int64_t count,
+                              double *Y)
+{
+    float s = sqrtf((float)n);
+    uint64_t key[2] = {seed, KEY_DOMAIN};
+    for (int64_t q = 0; q < count; ++q) {
+        uint64_t ctr[4] = {(uint64_t)nodes[q], 0, 0, TAG_INIT};
+        uint64_t x[4];
+        oracle_philox4x64(ctr, key, x);
+        for (int c = 0; c < 2; ++c) {
+            int32_t v = (int32_t)(x[c] >> 40) - (1 << 23);
+            float unit = (float)v * 0x1p-23f; /* exact */
+            Y[2 * q + c] = (double)(unit * s);
+        }
+    }
+}
+
 /* -------------------------------------------------------------- alias table */
 /* Integer alias table for weights w[0..n) (Walker/Vose), built by a
  * deterministic sequential sweep.  Item s has mass M_s = w_s * n against a bin
@@ -262,6 +281,19 @@ int oracle_draw_negatives(const int32_t *row_ptr, const int32_t *col, int32_t n,
     for (int32_t i = 0; i < n; ++i)
         for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
             draw_negatives(&sp, seed, e, t, i, k, out + e * k);
+    return 0;
+}
+
+/* The negatives of listed directed edges only: edge edges[q] with source
+ * src[q] (the row holding it), out[q*k .. q*k+k).  For graphs too large to
+ * draw every edge on the host. */
+int oracle_draw_edges(int32_t n, int32_t k, int64_t t, uint64_t seed, int32_t mode,
+                      const uint32_t *thr, const uint32_t *alias, const int64_t *edges,
+                      const int32_t *src, int64_t count, int32_t *out)
+{
+    sampler sp = {n, mode, thr, alias};
+    for (int64_t q = 0; q < count; ++q)
+        draw_negatives(&sp, seed, edges[q], t, src[q], k, out + q * k);
     return 0;
 }
 

@@ -40,15 +40,22 @@ __device__ __forceinline__ AliasScanItem operator+(const AliasScanItem& a,
   return AliasScanItem{a.excess + b.excess, a.deficit + b.deficit, a.heavy + b.heavy, 0};
 }
 
-// Item s of the scan: heavy/light classification of M_s = degree(s) * n
-// against W.
+// Weight of item s: weights[s] when given, else the degree of s.
+__device__ __forceinline__ int64_t alias_weight(const int32_t* __restrict__ row_ptr,
+                                                const uint32_t* __restrict__ weights, int64_t s) {
+  return weights ? static_cast<int64_t>(weights[s])
+                 : static_cast<int64_t>(row_ptr[s + 1] - row_ptr[s]);
+}
+
+// Item s of the scan: heavy/light classification of M_s = w_s * n against W.
 struct AliasLoad {
   const int32_t* row_ptr;
+  const uint32_t* weights;  // nullable: degrees
   int64_t n, W;
   __device__ AliasScanItem operator()(int64_t s) const {
     AliasScanItem it{0, 0, 0, 0};
     if (s < n) {
-      const int64_t M = static_cast<int64_t>(row_ptr[s + 1] - row_ptr[s]) * n;
+      const int64_t M = alias_weight(row_ptr, weights, s) * n;
       if (M >= W) {
         it.excess = M - W;
         it.heavy = 1;
@@ -113,7 +120,8 @@ __device__ __forceinline__ uint32_t alias_threshold(int64_t own, int64_t W) {
 }
 
 // Phase 4: one thread per item writes thr/alias.
-static __global__ void alias_fill_kernel(const int32_t* __restrict__ row_ptr, int64_t n, int64_t W,
+static __global__ void alias_fill_kernel(const int32_t* __restrict__ row_ptr,
+                                  const uint32_t* __restrict__ weights, int64_t n, int64_t W,
                                   const AliasScanItem* __restrict__ grand,
                                   const int32_t* __restrict__ heavy_item,
                                   const int64_t* __restrict__ heavy_inc,
@@ -127,7 +135,7 @@ static __global__ void alias_fill_kernel(const int32_t* __restrict__ row_ptr, in
   if (r < nl) {
     // light of rank r
     const int32_t s = light_item[r];
-    const int64_t M = static_cast<int64_t>(row_ptr[s + 1] - row_ptr[s]) * n;
+    const int64_t M = alias_weight(row_ptr, weights, s) * n;
     const int64_t x = light_inc[r] - (W - M);  // exclusive deficit prefix
     const int64_t h = lower_bound64(heavy_inc, nh, x);
     thr[s] = alias_threshold(M, W);

@@ -289,6 +289,8 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
     layout_opts_init(&o);
   if (o.update_mode < 0 || o.update_mode > 3)
     return fail(LAYOUT_E_INVALID_ARG, "update_mode = %d", o.update_mode);
+  if (o.neg_weights == LAYOUT_NEG_CUSTOM)
+    return fail(LAYOUT_E_UNSUPPORTED, "per-node negative weights: single-graph layouts only");
   if (o.neg_weights != LAYOUT_NEG_UNIFORM && o.neg_weights != LAYOUT_NEG_DEGREE)
     return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
   if (o.engine < 0 || o.engine > 3) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
@@ -485,7 +487,7 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
     if (degree && B->nnz[g] > 0) {
       d.thr = B->d_thr + B->node_off[g];
       d.alias = B->d_alias + B->node_off[g];
-      if ((rc = build_alias_table(B->stream, row, gr.n, B->nnz[g], const_cast<uint32_t*>(d.thr),
+      if ((rc = build_alias_table(B->stream, row, nullptr, gr.n, B->nnz[g], const_cast<uint32_t*>(d.thr),
                                   const_cast<uint32_t*>(d.alias))) != LAYOUT_OK)
         return bail(rc);
     }

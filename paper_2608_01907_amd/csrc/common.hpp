@@ -55,8 +55,10 @@ inline int64_t chunk_bound(int64_t nnz, int32_t bundle, int32_t hub) {
 int build_chunk_table(hipStream_t stream, const int32_t* d_row, int32_t n, int64_t nnz,
                       int32_t bundle, int32_t hub, int32_t* d_chunk_begin, int32_t* d_chunk_src,
                       int64_t* n_chunks);
-int build_alias_table(hipStream_t stream, const int32_t* d_row, int32_t n, int64_t W,
-                      uint32_t* d_thr, uint32_t* d_alias);
+// Integer alias table for the weights d_weights[0..n) (nullable: degrees from
+// d_row), W = their sum, 0 < W < 2^32.
+int build_alias_table(hipStream_t stream, const int32_t* d_row, const uint32_t* d_weights,
+                      int32_t n, int64_t W, uint32_t* d_thr, uint32_t* d_alias);
 // Device validation of one CSR (LAYOUT_E_BAD_GRAPH with a message on failure);
 // err is a device word of scratch.
 int validate_csr(hipStream_t stream, const int32_t* d_row, const int32_t* d_col, int32_t n,

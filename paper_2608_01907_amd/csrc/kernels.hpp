@@ -585,6 +585,21 @@ static __global__ void dump_draws_kernel(GraphDesc g, int32_t t, int32_t* __rest
   for (int m = 0; m < K; ++m) out[e * K + m] = static_cast<int32_t>(s[m]);
 }
 
+// Debug: the negatives of listed edges only (edges already checked < nnz).
+template <int K, bool DEGREE>
+static __global__ void dump_draws_at_kernel(GraphDesc g, int32_t t,
+                                            const int64_t* __restrict__ edges, int64_t count,
+                                            int32_t* __restrict__ out) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  const int64_t e = edges[q];
+  const int32_t i = row_of(g.row_ptr, g.n, e);
+  uint32_t s[K > 0 ? K : 1];
+  draw_k<K, DEGREE>(g, e, static_cast<uint32_t>(t), static_cast<uint32_t>(i), s);
+#pragma unroll
+  for (int m = 0; m < K; ++m) out[q * K + m] = static_cast<int32_t>(s[m]);
+}
+
 // ----------------------------------------------------------- microbenchmarks
 // Plain streaming copy (HBM roofline and counter calibration).
 static __global__ void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n4) {

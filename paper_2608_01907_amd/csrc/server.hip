@@ -161,7 +161,7 @@ int setup_job(layout_server_t* S, Job& j) {
   if (S->opts.neg_weights == LAYOUT_NEG_DEGREE && j.nnz > 0) {
     if ((rc = jalloc(j, reinterpret_cast<void**>(&thr), 4 * size_t(j.n), "alias thr")) ||
         (rc = jalloc(j, reinterpret_cast<void**>(&alias), 4 * size_t(j.n), "alias")) ||
-        (rc = build_alias_table(S->stream, row, j.n, j.nnz, thr, alias)))
+        (rc = build_alias_table(S->stream, row, nullptr, j.n, j.nnz, thr, alias)))
       return rc;
   }
   launch_init_positions(S->stream, Y, j.n, j.seed);
@@ -470,6 +470,8 @@ int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t ro
     return fail(LAYOUT_E_INVALID_ARG, "update_mode = %d", o.update_mode);
   if (o.update_mode == LAYOUT_JACOBI)
     return fail(LAYOUT_E_UNSUPPORTED, "the server runs the lock-free policies only");
+  if (o.neg_weights == LAYOUT_NEG_CUSTOM)
+    return fail(LAYOUT_E_UNSUPPORTED, "per-node negative weights: single-graph layouts only");
   if (o.neg_weights != LAYOUT_NEG_UNIFORM && o.neg_weights != LAYOUT_NEG_DEGREE)
     return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
   if (o.engine < 0 || o.engine > 3) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);

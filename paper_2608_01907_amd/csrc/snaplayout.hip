@@ -13,6 +13,7 @@
 #include <string>
 #include <type_traits>
 #include <utility>
+#include <vector>
 
 #include "alias.hpp"
 #include "chunks.hpp"
@@ -148,7 +149,7 @@ GlobalGroup global_group_of(const layout_t* L) {
   g.total_chunks = L->n_chunks;
   g.k = L->k;
   g.mode = L->mode;
-  g.degree = L->opts.neg_weights == LAYOUT_NEG_DEGREE;
+  g.degree = L->opts.neg_weights != LAYOUT_NEG_UNIFORM;
   g.access = L->access;
   g.block = L->block;
   g.grid = L->opts.grid_blocks;
@@ -167,7 +168,7 @@ LdsGroup lds_group_of(const layout_t* L) {
   g.lds_bytes = lds_bytes_for(L->n);
   g.k = L->k;
   g.mode = L->mode;
-  g.degree = L->opts.neg_weights == LAYOUT_NEG_DEGREE;
+  g.degree = L->opts.neg_weights != LAYOUT_NEG_UNIFORM;
   g.block = L->block;
   return g;
 }
@@ -190,7 +191,7 @@ int launch_xcd_epochs(layout_t* L, int32_t count) {
   const int grid = xcd_workers(L) * xcds;
   return with_k(L->k, [&](auto kc) -> int {
     constexpr int K = decltype(kc)::value;
-    return with_degree(L->opts.neg_weights == LAYOUT_NEG_DEGREE, [&](auto dc) -> int {
+    return with_degree(L->opts.neg_weights != LAYOUT_NEG_UNIFORM, [&](auto dc) -> int {
       constexpr bool DEG = decltype(dc)::value;
       for (int32_t ep = 0; ep < count; ++ep) {
         const int32_t t = L->t + ep;
@@ -251,8 +252,8 @@ int snap::build_chunk_table(hipStream_t stream, const int32_t* d_row, int32_t n,
 
 // Alias table for weights w_s = degree(s), W = sum w = nnz, built on the
 // device (temporary buffers freed before returning).
-int snap::build_alias_table(hipStream_t stream, const int32_t* d_row, int32_t n, int64_t W,
-                            uint32_t* d_thr, uint32_t* d_alias) {
+int snap::build_alias_table(hipStream_t stream, const int32_t* d_row, const uint32_t* d_weights,
+                            int32_t n, int64_t W, uint32_t* d_thr, uint32_t* d_alias) {
   const int64_t tiles = std::max<int64_t>(1, scan_tiles(n));
   void* tmp = nullptr;
   const size_t b_sums = sizeof(AliasScanItem) * size_t(tiles + 1);
@@ -268,11 +269,11 @@ int snap::build_alias_table(hipStream_t stream, const int32_t* d_row, int32_t n,
   auto* light_inc = heavy_inc + n;
   auto* heavy_item = reinterpret_cast<int32_t*>(light_inc + n);
   auto* light_item = heavy_item + n;
-  device_exclusive_scan<AliasScanItem>(stream, n, AliasLoad{d_row, n, W},
+  device_exclusive_scan<AliasScanItem>(stream, n, AliasLoad{d_row, d_weights, n, W},
                                        AliasCompact{heavy_item, heavy_inc, light_item, light_inc},
                                        sums);
   hipLaunchKernelGGL(alias_fill_kernel, dim3(div_up(n, 256)), dim3(256), 0, stream, d_row,
-                     int64_t(n), W, grand, heavy_item, heavy_inc, light_item, light_inc, d_thr,
+                     d_weights, int64_t(n), W, grand, heavy_item, heavy_inc, light_item, light_inc, d_thr,
                      d_alias);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -593,7 +594,7 @@ int launch_sampled_energy(layout_t* L, int32_t t, bool with_rep) {
   const int k = with_rep ? L->k : 0;
   return with_k(k, [&](auto kc) -> int {
     constexpr int K = decltype(kc)::value;
-    return with_degree(L->opts.neg_weights == LAYOUT_NEG_DEGREE, [&](auto dc) -> int {
+    return with_degree(L->opts.neg_weights != LAYOUT_NEG_UNIFORM, [&](auto dc) -> int {
       constexpr bool DEG = decltype(dc)::value;
       hipLaunchKernelGGL((sampled_energy_kernel<K, DEG>), dim3(grid), dim3(256), 0, L->stream,
                          L->d_table, L->n_chunks, t, L->d_energy);
@@ -656,8 +657,11 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
     layout_opts_init(&o);
   if (o.update_mode < 0 || o.update_mode > 3)
     return fail(LAYOUT_E_INVALID_ARG, "update_mode = %d", o.update_mode);
-  if (o.neg_weights != LAYOUT_NEG_UNIFORM && o.neg_weights != LAYOUT_NEG_DEGREE)
+  if (o.neg_weights != LAYOUT_NEG_UNIFORM && o.neg_weights != LAYOUT_NEG_DEGREE &&
+      o.neg_weights != LAYOUT_NEG_CUSTOM)
     return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
+  if (o.neg_weights == LAYOUT_NEG_CUSTOM && n > 0 && !o.neg_weight_values)
+    return fail(LAYOUT_E_INVALID_ARG, "LAYOUT_NEG_CUSTOM needs neg_weight_values");
   if (o.start_epoch < 0 || o.start_epoch > epochs)
     return fail(LAYOUT_E_INVALID_ARG, "start_epoch = %d", o.start_epoch);
   if (o.engine < 0 || o.engine > 3) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
@@ -806,14 +810,37 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
       return bail(rc);
   }
 
-  // alias table of the degree-weighted negatives (weights = degrees, W = nnz)
+  // alias table of weighted negatives: degrees (W = nnz) or the caller's
+  // weights (0 < W < 2^32, summed on the host)
   uint32_t* d_thr = nullptr;
   uint32_t* d_alias = nullptr;
-  if (o.neg_weights == LAYOUT_NEG_DEGREE && L->nnz > 0) {
+  if (o.neg_weights != LAYOUT_NEG_UNIFORM && L->nnz > 0) {
     if ((rc = alloc(L, reinterpret_cast<void**>(&d_thr), sizeof(uint32_t) * size_t(n), "alias thr")) ||
         (rc = alloc(L, reinterpret_cast<void**>(&d_alias), sizeof(uint32_t) * size_t(n), "alias")))
       return bail(rc);
-    if ((rc = build_alias_table(L->stream, d_row, n, L->nnz, d_thr, d_alias)) != LAYOUT_OK)
+    int64_t W = L->nnz;
+    uint32_t* d_w = nullptr;
+    if (o.neg_weight_values) {
+      std::vector<uint32_t> w(static_cast<size_t>(n));
+      if (inputs_on_device)
+        e = hipMemcpy(w.data(), o.neg_weight_values, sizeof(uint32_t) * size_t(n),
+                      hipMemcpyDeviceToHost);
+      else
+        std::memcpy(w.data(), o.neg_weight_values, sizeof(uint32_t) * size_t(n));
+      if (e != hipSuccess) return bail(hip_fail(e, "reading neg_weight_values"));
+      W = 0;
+      for (uint32_t x : w) W += x;
+      if (W <= 0 || W >= (int64_t(1) << 32))
+        return bail(fail(LAYOUT_E_INVALID_ARG, "negative weights sum to %lld (need 0 < W < 2^32)",
+                         (long long)W));
+      if ((rc = alloc(L, reinterpret_cast<void**>(&d_w), sizeof(uint32_t) * size_t(n), "weights")))
+        return bail(rc);
+      e = hipMemcpyAsync(d_w, w.data(), sizeof(uint32_t) * size_t(n), hipMemcpyHostToDevice,
+                         L->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+      if (e != hipSuccess) return bail(hip_fail(e, "copying neg_weight_values"));
+    }
+    if ((rc = build_alias_table(L->stream, d_row, d_w, n, W, d_thr, d_alias)) != LAYOUT_OK)
       return bail(rc);
   }
 
@@ -1061,7 +1088,7 @@ int layout_debug_draws(layout_t* L, int32_t epoch, int32_t* host_out) {
   int32_t* d_out = nullptr;
   hipError_t e = hipMalloc(&d_out, bytes);
   if (e != hipSuccess) return hip_fail(e, "debug draws buffer");
-  int rc = launch_dump_draws(L->stream, L->k, L->opts.neg_weights == LAYOUT_NEG_DEGREE,
+  int rc = launch_dump_draws(L->stream, L->k, L->opts.neg_weights != LAYOUT_NEG_UNIFORM,
                              L->host_desc, epoch, d_out);
   if (rc == LAYOUT_OK) {
     e = hipMemcpyAsync(host_out, d_out, bytes, hipMemcpyDeviceToHost, L->stream);
@@ -1070,6 +1097,47 @@ int layout_debug_draws(layout_t* L, int32_t epoch, int32_t* host_out) {
   }
   (void)hipFree(d_out);
   return rc;
+}
+
+int layout_debug_draws_at(layout_t* L, int32_t epoch, const int64_t* edges, int64_t count,
+                          int32_t* host_out) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (count < 0 || (count > 0 && (!edges || !host_out)))
+    return fail(LAYOUT_E_INVALID_ARG, "NULL edges/host_out or count < 0");
+  if (count == 0 || L->k == 0) return LAYOUT_OK;
+  for (int64_t q = 0; q < count; ++q)
+    if (edges[q] < 0 || edges[q] >= L->nnz)
+      return fail(LAYOUT_E_INVALID_ARG, "edge %lld out of range [0, %lld)",
+                  (long long)edges[q], (long long)L->nnz);
+  int64_t* d_e = nullptr;
+  int32_t* d_out = nullptr;
+  hipError_t e = hipMalloc(&d_e, sizeof(int64_t) * size_t(count));
+  if (e == hipSuccess) e = hipMalloc(&d_out, sizeof(int32_t) * size_t(count) * size_t(L->k));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_e, edges, sizeof(int64_t) * size_t(count), hipMemcpyHostToDevice,
+                       L->stream);
+  int rc = LAYOUT_OK;
+  if (e == hipSuccess) {
+    rc = with_k(L->k, [&](auto kc) -> int {
+      constexpr int K = decltype(kc)::value;
+      return with_degree(L->opts.neg_weights != LAYOUT_NEG_UNIFORM, [&](auto dc) -> int {
+        constexpr bool DEG = decltype(dc)::value;
+        hipLaunchKernelGGL((dump_draws_at_kernel<K, DEG>), dim3(div_up(count, 256)), dim3(256), 0,
+                           L->stream, L->host_desc, epoch, d_e, count, d_out);
+        return LAYOUT_OK;
+      });
+    });
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && rc == LAYOUT_OK)
+    e = hipMemcpyAsync(host_out, d_out, sizeof(int32_t) * size_t(count) * size_t(L->k),
+                       hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (d_e) (void)hipFree(d_e);
+  if (d_out) (void)hipFree(d_out);
+  if (rc != LAYOUT_OK) return rc;
+  if (e != hipSuccess) return hip_fail(e, "debug draws of listed edges");
+  return LAYOUT_OK;
 }
 
 int layout_debug_chunks(const layout_t* L, int32_t* begin_out, int32_t* src_out) {

@@ -32,6 +32,7 @@ LAYOUT_INIT_UNIFORM = 0
 LAYOUT_INIT_PMDS = 1
 LAYOUT_NEG_UNIFORM = 0
 LAYOUT_NEG_DEGREE = 1
+LAYOUT_NEG_CUSTOM = 2
 LAYOUT_ENGINE_AUTO = 0
 LAYOUT_ENGINE_GLOBAL = 1
 LAYOUT_ENGINE_LDS = 2
@@ -61,6 +62,7 @@ class layout_opts(ctypes.Structure):
         ("hub_split_edges", ctypes.c_int32), ("nodes_per_lane", ctypes.c_int32),
         ("init_mode", ctypes.c_int32), ("pmds_pivots", ctypes.c_int32),
         ("init_pos", ctypes.c_void_p), ("stream", ctypes.c_void_p),
+        ("neg_weight_values", ctypes.c_void_p),
     ]
 
 
@@ -144,6 +146,7 @@ _SIGNATURES = {
     "layout_effective_energy": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
                                                ctypes.POINTER(ctypes.c_double)]),
     "layout_debug_alias": (ctypes.c_int, [_vp, _vp, _vp]),
+    "layout_debug_draws_at": (ctypes.c_int, [_vp, _i32, _vp, _i64, _vp]),
     "layout_debug_chunks": (ctypes.c_int, [_vp, _vp, _vp]),
     "layout_bench_gather": (ctypes.c_int, [_vp, _i32, _i32, _i32, _f32p]),
     "layout_bench_copy": (ctypes.c_int, [_i64, _i32, _f32p]),
@@ -329,6 +332,14 @@ def layout_effective_energy(h):
     return a.value, r.value
 
 
+def layout_debug_draws_at(h, epoch, edges, k):
+    """Negatives of the listed directed edges (len(edges) x k)."""
+    e = np.ascontiguousarray(edges, dtype=np.int64)
+    out = np.zeros((max(e.size, 1), max(k, 1)), dtype=np.int32)
+    _check(lib().layout_debug_draws_at(h, epoch, e.ctypes.data, int(e.size), out.ctypes.data))
+    return out[: e.size, :k]
+
+
 def layout_debug_chunks(h):
     n_chunks = layout_get_info(h)["n_chunks"]
     begin = np.zeros(n_chunks + 1, dtype=np.int32)
@@ -491,9 +502,16 @@ class Layout:
                  alpha=0.1, beta=8.0, gamma=2.0, init_pos=None, bundle_edges=0,
                  block_threads=0, grid_blocks=0, start_epoch=0, stream=None,
                  hub_split_edges=0, nodes_per_lane=0, init_mode=LAYOUT_INIT_UNIFORM,
-                 pmds_pivots=0):
+                 pmds_pivots=0, neg_weight_values=None):
         o = layout_opts_init()
         o.init_mode, o.pmds_pivots = init_mode, pmds_pivots
+        w_keep = None
+        if neg_weight_values is not None:
+            if hasattr(neg_weight_values, "data_ptr"):
+                o.neg_weight_values = neg_weight_values.data_ptr()
+            else:
+                w_keep = np.ascontiguousarray(neg_weight_values, dtype=np.uint32)
+                o.neg_weight_values = w_keep.ctypes.data
         o.alpha, o.beta, o.gamma, o.eta0 = alpha, beta, gamma, eta0
         o.update_mode, o.neg_weights, o.engine = update_mode, neg_weights, engine
         o.access = access
@@ -515,7 +533,7 @@ class Layout:
         self.nnz = int(row_ptr[-1]) if not on_device else int(row_ptr[-1].item())
         self.h = layout_create_ex(row_ptr, col_idx, self.n, 2, self.k, self.epochs, seed, o,
                                   int(on_device))
-        del init_keep
+        del init_keep, w_keep
 
     def run(self, count=None):
         layout_epoch(self.h, self.epochs if count is None else count)

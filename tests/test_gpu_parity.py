@@ -297,6 +297,46 @@ def test_alias_table_skewed_weights():
     assert np.array_equal(thr, thr_o) and np.array_equal(alias, alias_o)
 
 
+@pytest.mark.parametrize("kind", ["random", "zeros_and_one_heavy", "near_2_32"])
+def test_custom_negative_weights_bit_exact(d1, kind):
+    """Caller-given integer weights (the flexible negative sampling named as
+    future work in the conclusion): alias table and draws bit-exact with the
+    oracle's sweep over the same weights, including zero weights, one
+    dominant weight (most draws hit it, and its own source rejects) and a
+    total just under 2^32."""
+    rng = np.random.default_rng(5)
+    if kind == "random":
+        w = rng.integers(1, 1000, d1.n).astype(np.uint32)
+        w[::7] = 0
+    elif kind == "zeros_and_one_heavy":
+        w = np.zeros(d1.n, np.uint32)
+        w[:10] = 1
+        w[3] = 100_000
+    else:
+        w = np.full(d1.n, (2**32 - 1) // d1.n, np.uint32)
+    thr_o, alias_o = O.alias_build(w.astype(np.int64))
+    with _layout(d1, k=4, epochs=6, seed=3, neg_weights=SL.LAYOUT_NEG_CUSTOM,
+                 neg_weight_values=w) as L:
+        thr, alias = SL.layout_debug_alias(L.h, d1.n)
+        assert np.array_equal(thr, thr_o) and np.array_equal(alias, alias_o)
+        for t in (0, 5):
+            ref = O.draw_negatives(d1.row_ptr, d1.col, d1.n, 4, t, 3, mode=O.NEG_DEGREE,
+                                   thr=thr_o, alias=alias_o)
+            assert np.array_equal(L.draws(t), ref)
+        L.run()
+        assert np.all(np.isfinite(L.positions()))
+
+
+def test_custom_negative_weights_rejected(d1):
+    for w in (np.zeros(d1.n, np.uint32), np.full(d1.n, 2**31, np.uint32)):
+        with pytest.raises(SL.LayoutError) as ei:
+            _layout(d1, k=4, epochs=2, neg_weights=SL.LAYOUT_NEG_CUSTOM, neg_weight_values=w)
+        assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
+    with pytest.raises(SL.LayoutError) as ei:
+        _layout(d1, k=4, epochs=2, neg_weights=SL.LAYOUT_NEG_CUSTOM)
+    assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
+
+
 def test_jacobi_epoch_degree_weighted(d1):
     thr_o, alias_o = O.alias_build(d1.degrees())
     Y0 = O.init_positions(d1.n, 6).astype(np.float32)

@@ -449,3 +449,21 @@ def test_threaded_single_thread_is_deterministic_and_clusters():
     q1 = M.quality(g.row_ptr, g.col, Y1, g.labels)
     q4 = M.quality(g.row_ptr, g.col, Y4, g.labels)
     assert abs(q1["si"] - q4["si"]) < 0.02 and abs(q1["np"] - q4["np"]) < 0.02
+
+
+def test_sampled_draws_and_init_match_full_ones():
+    """The per-edge and per-node oracle functions used at sizes where the full
+    ones cannot run agree with the full ones (same definitions, listed items)."""
+    g = S.chung_lu_communities(3000, 12000, tau=2.2, dmax=200.0, n_comm=8, intra=0.9, seed=9)
+    rng = np.random.default_rng(1)
+    edges = np.concatenate([[0, g.nnz - 1], rng.integers(0, g.nnz, 500)])
+    for t in (0, 17):
+        full = O.draw_negatives(g.row_ptr, g.col, g.n, 6, t, 21)
+        assert np.array_equal(O.draw_edges(g.row_ptr, g.n, 6, t, 21, edges), full[edges])
+    thr, alias = O.alias_build(g.degrees())
+    full = O.draw_negatives(g.row_ptr, g.col, g.n, 3, 2, 8, mode=O.NEG_DEGREE, thr=thr,
+                            alias=alias)
+    got = O.draw_edges(g.row_ptr, g.n, 3, 2, 8, edges, mode=O.NEG_DEGREE, thr=thr, alias=alias)
+    assert np.array_equal(got, full[edges])
+    nodes = np.concatenate([[0, g.n - 1], rng.integers(0, g.n, 300)])
+    assert np.array_equal(O.init_positions_at(g.n, 5, nodes), O.init_positions(g.n, 5)[nodes])
