@@ -3,7 +3,8 @@
 Calls only the oracle (and the seeded input generators): the serial FP64
 Algorithm 1 for the 259k-node graph, the FP64 threaded bundle scheme of
 Sec. 3.4 for the 4M-node graph (a serial run takes too long; the paper reports
-the parallel and serial variants within a few percent of each other, Sec. 4.3).
+the parallel and serial variants within a few percent of each other, Sec. 4.3),
+and both for the 259k-node graph (the "-lockfree" entries).
 The "-pmds" entries start from the oracle's Pivot MDS layout (the initial
 layout of Sec. 4.1, oracle/pmds.py, 50 pivots) instead of the seeded uniform
 draws.  NP and SI are measured on seeded node samples; the GPU tests use the
@@ -29,6 +30,12 @@ PLAN = {
     "lj-like-4m": ("lj-like-4m", "lj_like", 5, 30, "threaded", (0,), "uniform"),
     "orkut-like-259k-pmds": ("orkut-like-259k", "orkut_like", 5, 30, "serial", (0, 1), "pmds"),
     "lj-like-4m-pmds": ("lj-like-4m", "lj_like", 5, 30, "threaded", (0, 1), "pmds"),
+    # the paper's lock-free scheme (Sec. 3.4) on the 259k-node graph: the
+    # reference for lock-free layouts, next to serial Algorithm 1 above
+    "orkut-like-259k-lockfree": ("orkut-like-259k", "orkut_like", 5, 30, "threaded", (0, 1, 2),
+                                 "uniform"),
+    "orkut-like-259k-pmds-lockfree": ("orkut-like-259k", "orkut_like", 5, 30, "threaded",
+                                      (0, 1, 2), "pmds"),
 }
 NP_SAMPLE, SI_SAMPLE, METRIC_SEED = 2000, 10000, 12345
 

