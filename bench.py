@@ -323,7 +323,7 @@ def bench_served(args):
     picks = rng.integers(0, len(pool), args.jobs)
 
     def run_plain(order):
-        lat, t_busy = [], 0.0
+        lat = []
         for q in order:
             g = pool[q]
             t0 = time.perf_counter()
@@ -332,10 +332,12 @@ def bench_served(args):
             SL.layout_get_positions(h, g.n)
             SL.layout_destroy(h)
             lat.append(time.perf_counter() - t0)
+            if len(lat) % 50 == 0:
+                log(f"[bench] plain path: {len(lat)}/{len(order)} jobs")
         return np.array(lat)
 
-    # plain service time (FIFO, one job at a time) on a sample of the stream
-    svc = run_plain(picks[: min(len(picks), 24)])
+    # plain service times (one job at a time) on the first jobs of the stream
+    svc = run_plain(picks[: min(len(picks), 200)])
     mean_svc = float(svc.mean())
     log(f"[bench] plain mean service time {mean_svc * 1e3:.1f} ms")
     results = {}
@@ -350,6 +352,9 @@ def bench_served(args):
                 time.sleep(min(0.0005, ta - (time.perf_counter() - t_start)))
             g = pool[q]
             ids.append((SL.layout_server_submit(srv, g.row_ptr, g.col, g.n, k, T, int(q)), g.n))
+            if len(ids) % 100 == 0:
+                log(f"[bench] rho {rho}: {len(ids)}/{args.jobs} jobs submitted, "
+                    f"{time.perf_counter() - t_start:.1f}s")
         log(f"[bench] rho {rho}: {len(ids)} jobs submitted")
         for q, (jid, n) in enumerate(ids):
             SL.layout_server_wait(srv, jid, 600.0)
@@ -375,6 +380,29 @@ def bench_served(args):
                            "p99_s": float(np.percentile(lat, 99))},
         }
         log(f"[bench] rho {rho}: {results[str(rho)]}")
+    # capacity: the jobs whose plain service times were measured, submitted
+    # at once; makespan against their summed plain service times
+    sat_jobs = picks[: len(svc)]
+    srv = SL.layout_server_create(args.budget, args.slots, 0)
+    t_start = time.perf_counter()
+    ids = [(SL.layout_server_submit(srv, pool[q].row_ptr, pool[q].col, pool[q].n, k, T, int(q)),
+            pool[q].n) for q in sat_jobs]
+    log(f"[bench] saturation: {len(ids)} jobs submitted")
+    for q, (jid, n) in enumerate(ids):
+        SL.layout_server_wait(srv, jid, 1200.0)
+        SL.layout_server_take(srv, jid, n)
+        if (q + 1) % 50 == 0:
+            log(f"[bench] saturation: {q + 1}/{len(ids)} jobs done")
+    makespan = time.perf_counter() - t_start
+    st = SL.layout_server_get_stats(srv)
+    SL.layout_server_destroy(srv)
+    plain_total = float(svc.sum())
+    saturation = {"jobs": len(ids), "makespan_s": makespan,
+                  "edge_updates_per_s": st["edge_updates"] / makespan,
+                  "plain_sequential_s": plain_total,
+                  "plain_edge_updates_per_s": st["edge_updates"] / plain_total,
+                  "speedup_vs_plain": plain_total / makespan}
+    log(f"[bench] saturation: {saturation}")
     main_rho = str(args.rho[-1])
     return {
         "metric": "edge-updates/sec (|E|(1+k)/epoch time) + p50/p99 job latency, served vs plain",
@@ -386,6 +414,7 @@ def bench_served(args):
                    "epochs": T, "slots": args.slots, "budget_bytes": args.budget},
         "plain_mean_service_s": mean_svc,
         "by_load": results,
+        "saturation": saturation,
     }
 
 

@@ -52,16 +52,9 @@ enum {
     LAYOUT_HOGWILD_STORE = 0, /* device-scope plain stores; racing updates may be lost */
     LAYOUT_ATOMIC = 1,        /* device-scope float atomic adds; no update lost */
     LAYOUT_JACOBI = 2,        /* test mode: all pair forces from epoch-start positions */
-    LAYOUT_UPDATE_AUTO = 3    /* ATOMIC on the LDS engine, HOGWILD_STORE on the global one */
+    LAYOUT_UPDATE_AUTO = 3    /* ATOMIC on the LDS engine, HOGWILD_STORE on the others */
 };
 
-/* How the global engine reaches positions in device memory. */
-enum {
-    LAYOUT_ACCESS_COHERENT = 0, /* device-scope loads/stores: every lane sees the value last
-                                   written anywhere on the device */
-    LAYOUT_ACCESS_CACHED = 1    /* plain loads/stores through the per-XCD L2 (HOGWILD_STORE
-                                   only); writes of other XCDs show up after eviction */
-};
 
 /* Initial layout when no positions are given. */
 enum {
@@ -105,7 +98,6 @@ typedef struct layout_opts {
     int32_t block_threads;    /* threads per workgroup; 0 = automatic (see nodes_per_lane) */
     int32_t grid_blocks;      /* workgroups of the epoch kernel; 0 = automatic: at most one
                                  256-lane workgroup per CU and n / nodes_per_lane lanes */
-    int32_t access;           /* LAYOUT_ACCESS_COHERENT (default) / LAYOUT_ACCESS_CACHED */
     int32_t hub_split_edges;  /* rows with more edges are split into segments of this many
                                  edges, one lane each; 0 = default (4 * bundle_edges on the
                                  global engine, never on the LDS engine) */
@@ -210,7 +202,7 @@ typedef struct layout_info {
     int64_t nnz;
     int32_t n, k;
     int32_t epochs, update_mode; /* the resolved policy (never AUTO) */
-    int32_t access, hub_split_edges;
+    int32_t hub_split_edges;
 } layout_info;
 
 int layout_get_info(const layout_t *L, layout_info *info);
@@ -260,10 +252,10 @@ int layout_debug_alias(const layout_t *L, uint32_t *thr_out, uint32_t *alias_out
 /* Random-gather roofline of the handle's graph: the memory pattern of one
  * epoch (stream col, one read-modify-write at col[e] and k at hashed uniform
  * nodes per directed edge) without force arithmetic or generator.  mode:
- * LAYOUT_HOGWILD_STORE or LAYOUT_ATOMIC; access: LAYOUT_ACCESS_* (CACHED only
- * with HOGWILD_STORE).  Runs reps launches, reports the mean launch time in
- * *ms.  Perturbs the positions slightly (use on a scratch job). */
-int layout_bench_gather(layout_t *L, int32_t mode, int32_t access, int32_t reps, float *ms);
+ * LAYOUT_HOGWILD_STORE or LAYOUT_ATOMIC.  Runs reps launches, reports the
+ * mean launch time in *ms.  Perturbs the positions slightly (use on a scratch
+ * job).  Global-engine layouts only (E_UNSUPPORTED otherwise). */
+int layout_bench_gather(layout_t *L, int32_t mode, int32_t reps, float *ms);
 
 /* Streaming copy of bytes bytes between two device buffers allocated by the
  * library; mean time of reps launches in *ms (HBM roofline and counter
@@ -306,7 +298,7 @@ typedef struct layout_batch_info {
  * layout_create_ex; init_pos and start_epoch are ignored (per-graph init_pos
  * lives in layout_graph).  Graphs that fit LDS run whole in one workgroup
  * each; with engine AUTO the others run on XCD-local bins when all of them
- * fit one XCD's L2 (HOGWILD_STORE, coherent access, automatic launch shape),
+ * fit one XCD's L2 (HOGWILD_STORE, automatic launch shape),
  * else in one all-CU launch per epoch; engine GLOBAL forces that launch for
  * every graph, engine XCD requires the bins.  Returns when the batch is ready
  * to run. */
@@ -393,7 +385,7 @@ typedef struct layout_server_stats {
  * layout_create_ex (init_pos, start_epoch, stream are ignored).  Each round
  * runs the remaining epochs of every job that fits LDS, an epoch slice of
  * every job whose positions fit one XCD's L2 on XCD-local bins (engine AUTO
- * or XCD, HOGWILD_STORE, coherent access, automatic launch shape), and an
+ * or XCD, HOGWILD_STORE, automatic launch shape), and an
  * epoch slice of every other job in one all-CU launch. */
 int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t round_edges,
                          const layout_opts *opts, layout_server_t **out);

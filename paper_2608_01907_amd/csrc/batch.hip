@@ -298,8 +298,6 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
       o.nodes_per_lane < 0 || o.block_threads > 1024 || (o.block_threads % 64) != 0)
     return fail(LAYOUT_E_INVALID_ARG, "bad launch option");
   if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g (must be > 1)", o.gamma);
-  if (o.access < LAYOUT_ACCESS_COHERENT || o.access > LAYOUT_ACCESS_CACHED)
-    return fail(LAYOUT_E_INVALID_ARG, "access = %d", o.access);
   if (o.init_mode != LAYOUT_INIT_UNIFORM)
     return fail(LAYOUT_E_UNSUPPORTED, "init_mode = %d (only the seeded uniform init here)", o.init_mode);
 
@@ -316,8 +314,6 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
   const bool jacobi = o.update_mode == LAYOUT_JACOBI;
   B->mode_global = o.update_mode == LAYOUT_UPDATE_AUTO ? LAYOUT_HOGWILD_STORE : o.update_mode;
   B->mode_lds = o.update_mode == LAYOUT_UPDATE_AUTO ? LAYOUT_ATOMIC : o.update_mode;
-  if (B->mode_global != LAYOUT_HOGWILD_STORE && o.access != LAYOUT_ACCESS_COHERENT)
-    return bail(fail(LAYOUT_E_UNSUPPORTED, "cached access needs HOGWILD_STORE"));
   B->bundle = o.bundle_edges ? o.bundle_edges : kDefaultBundle;
   B->hub = o.hub_split_edges ? o.hub_split_edges : kHubFactor * B->bundle;
 
@@ -401,12 +397,12 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
     bool all_fit = !B->global_ids.empty();
     for (int32_t g : B->global_ids) all_fit = all_fit && int64_t(B->n[g]) * 8 <= kXcdMaxPositionBytes;
     const bool store = B->mode_global == LAYOUT_HOGWILD_STORE;
-    const bool plain = !jacobi && store && o.access == LAYOUT_ACCESS_COHERENT && o.block_threads <= 256 &&
+    const bool plain = !jacobi && store && o.block_threads <= 256 &&
                        o.grid_blocks == 0;
     if (o.engine == LAYOUT_ENGINE_XCD) {
       if (!plain || !all_fit)
         return bail(fail(LAYOUT_E_UNSUPPORTED,
-                         "XCD-local engine: HOGWILD_STORE, coherent access and graphs of at most "
+                         "XCD-local engine: HOGWILD_STORE, automatic launch shape and graphs of at most "
                          "%lld B of positions", (long long)kXcdMaxPositionBytes));
       B->xcd_mode = true;
     } else if (o.engine == LAYOUT_ENGINE_AUTO) {
@@ -508,7 +504,6 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
   B->gg.k = k;
   B->gg.mode = B->mode_global;
   B->gg.degree = degree;
-  B->gg.access = o.access;
   B->gg.block = o.block_threads ? o.block_threads : 256;
   B->gg.jacobi_Y = B->d_Y;
   B->gg.jacobi_D = B->d_D;

@@ -84,7 +84,6 @@ struct GlobalGroup {
   int64_t total_index = 0;   // G > 1: rounds * round_size
   int k = 5, mode = kStore;
   bool degree = false;
-  int access = 0;  // LAYOUT_ACCESS_*
   int block = 256;
   int grid = 0;    // 0 = fill the device, capped by max_lanes
   int64_t max_lanes = 0;  // 0 = no cap

@@ -73,13 +73,6 @@ struct GlobalMem {
   }
 };
 
-// Global positions through the caches with plain accesses: an XCD's L2 may
-// serve a line that another XCD has since written (STORE policy only).
-struct GlobalCachedMem {
-  static __device__ __forceinline__ float2 load(const float2* p) { return *p; }
-  static __device__ __forceinline__ void store(float2* p, float2 v) { *p = v; }
-};
-
 // Positions touched by the CUs of one XCD only (the XCD-local engine): plain
 // loads and stores are coherent through that XCD's L2, and hit there when the
 // positions fit it.  A per-CU L1 line may lag another CU's store by the

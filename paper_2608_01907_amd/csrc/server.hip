@@ -342,7 +342,6 @@ int run_round(layout_server_t* S) {
     gg.k = k;
     gg.mode = S->mode_global;
     gg.degree = S->opts.neg_weights == LAYOUT_NEG_DEGREE;
-    gg.access = S->opts.access;
     gg.block = S->opts.block_threads && S->opts.block_threads <= 256 ? S->opts.block_threads : 256;
     gg.grid = S->opts.grid_blocks;
     gg.max_lanes = fair_lanes(gt, S->opts.nodes_per_lane);
@@ -476,13 +475,8 @@ int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t ro
     return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
   if (o.engine < 0 || o.engine > 3) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
   if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g", o.gamma);
-  if (o.access < LAYOUT_ACCESS_COHERENT || o.access > LAYOUT_ACCESS_CACHED)
-    return fail(LAYOUT_E_INVALID_ARG, "access = %d", o.access);
   if (o.init_mode != LAYOUT_INIT_UNIFORM)
     return fail(LAYOUT_E_UNSUPPORTED, "init_mode = %d (only the seeded uniform init here)", o.init_mode);
-  if (o.access != LAYOUT_ACCESS_COHERENT && o.update_mode != LAYOUT_UPDATE_AUTO &&
-      o.update_mode != LAYOUT_HOGWILD_STORE)
-    return fail(LAYOUT_E_UNSUPPORTED, "cached access needs HOGWILD_STORE");
   if (o.block_threads < 0 || o.block_threads > 1024 || (o.block_threads % 64) != 0 ||
       o.bundle_edges < 0 || o.hub_split_edges < 0 || o.grid_blocks < 0 || o.nodes_per_lane < 0)
     return fail(LAYOUT_E_INVALID_ARG, "bad launch option");
@@ -490,7 +484,7 @@ int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t ro
   if (!S) return fail(LAYOUT_E_OOM, "host allocation");
   S->opts = o;
   S->mode_global = o.update_mode == LAYOUT_UPDATE_AUTO ? LAYOUT_HOGWILD_STORE : o.update_mode;
-  S->xcd_ok = S->mode_global == LAYOUT_HOGWILD_STORE && o.access == LAYOUT_ACCESS_COHERENT &&
+  S->xcd_ok = S->mode_global == LAYOUT_HOGWILD_STORE &&
               (o.engine == LAYOUT_ENGINE_AUTO || o.engine == LAYOUT_ENGINE_XCD) &&
               o.grid_blocks == 0 && o.block_threads == 0;
   S->mode_lds = o.update_mode == LAYOUT_UPDATE_AUTO ? LAYOUT_ATOMIC : o.update_mode;

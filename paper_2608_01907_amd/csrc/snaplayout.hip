@@ -114,7 +114,6 @@ struct layout {
   layout_opts opts{};
   int32_t engine = LAYOUT_ENGINE_GLOBAL;
   int32_t mode = LAYOUT_ATOMIC;  // resolved update policy
-  int32_t access = LAYOUT_ACCESS_COHERENT;
   int32_t bundle = 16;
   int32_t hub = 64;
   int32_t block = 256;
@@ -150,7 +149,6 @@ GlobalGroup global_group_of(const layout_t* L) {
   g.k = L->k;
   g.mode = L->mode;
   g.degree = L->opts.neg_weights != LAYOUT_NEG_UNIFORM;
-  g.access = L->access;
   g.block = L->block;
   g.grid = L->opts.grid_blocks;
   g.max_lanes = L->n / (L->opts.nodes_per_lane > 0 ? L->opts.nodes_per_lane : kNodesPerLane);
@@ -444,14 +442,6 @@ int snap::launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t
         constexpr int MODE = decltype(mc)::value;
         for (int32_t ep = 0; ep < count; ++ep) {
           const int64_t index = g.G > 1 ? g.total_index : g.total_chunks;
-          if constexpr (MODE == kStore) {
-            if (g.access == LAYOUT_ACCESS_CACHED) {
-              hipLaunchKernelGGL((epoch_global_kernel<K, MODE, DEG, GlobalCachedMem>), dim3(grid),
-                                 dim3(g.block), 0, stream, g.d_table, g.G, index, g.round_size,
-                                 dt + ep);
-              continue;
-            }
-          }
           hipLaunchKernelGGL((epoch_global_kernel<K, MODE, DEG>), dim3(grid), dim3(g.block), 0,
                              stream, g.d_table, g.G, index, g.round_size, dt + ep);
           if constexpr (MODE == kJacobi) {
@@ -626,7 +616,6 @@ void layout_opts_init(layout_opts* o) {
   o->gamma = 2.0f;
   o->eta0 = 1.0f;
   o->update_mode = LAYOUT_UPDATE_AUTO;
-  o->access = LAYOUT_ACCESS_COHERENT;
   o->neg_weights = LAYOUT_NEG_UNIFORM;
   o->engine = LAYOUT_ENGINE_AUTO;
 }
@@ -665,8 +654,6 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
   if (o.start_epoch < 0 || o.start_epoch > epochs)
     return fail(LAYOUT_E_INVALID_ARG, "start_epoch = %d", o.start_epoch);
   if (o.engine < 0 || o.engine > 3) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
-  if (o.access < LAYOUT_ACCESS_COHERENT || o.access > LAYOUT_ACCESS_CACHED)
-    return fail(LAYOUT_E_INVALID_ARG, "access = %d", o.access);
   if (o.init_mode != LAYOUT_INIT_UNIFORM && o.init_mode != LAYOUT_INIT_PMDS)
     return fail(LAYOUT_E_INVALID_ARG, "init_mode = %d", o.init_mode);
   if (o.pmds_pivots < 0 || o.pmds_pivots > 64)
@@ -737,8 +724,7 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
     const bool store_ok = o.update_mode == LAYOUT_UPDATE_AUTO || o.update_mode == LAYOUT_HOGWILD_STORE;
     if (lds_fits && L->nnz <= kLdsAutoMaxEdges && o.update_mode != LAYOUT_JACOBI)
       L->engine = LAYOUT_ENGINE_LDS;
-    else if (store_ok && int64_t(n) * 8 <= kXcdMaxPositionBytes &&
-             o.access == LAYOUT_ACCESS_COHERENT)
+    else if (store_ok && int64_t(n) * 8 <= kXcdMaxPositionBytes)
       L->engine = LAYOUT_ENGINE_XCD;
     else
       L->engine = LAYOUT_ENGINE_GLOBAL;
@@ -763,15 +749,8 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
   L->mode = o.update_mode != LAYOUT_UPDATE_AUTO
                 ? o.update_mode
                 : (L->engine == LAYOUT_ENGINE_LDS ? LAYOUT_ATOMIC : LAYOUT_HOGWILD_STORE);
-  L->access = o.access;
-  if (L->access != LAYOUT_ACCESS_COHERENT &&
-      (L->mode != LAYOUT_HOGWILD_STORE || L->engine != LAYOUT_ENGINE_GLOBAL))
-    return bail(fail(LAYOUT_E_UNSUPPORTED,
-                     "cached access is only defined for HOGWILD_STORE on the global engine"));
   if ((L->engine == LAYOUT_ENGINE_GLOBAL || L->engine == LAYOUT_ENGINE_XCD) && L->block > 256)
     return bail(fail(LAYOUT_E_UNSUPPORTED, "global engines run at most 256-thread workgroups"));
-  if (L->engine == LAYOUT_ENGINE_XCD && L->access != LAYOUT_ACCESS_COHERENT)
-    return bail(fail(LAYOUT_E_UNSUPPORTED, "the XCD-local engine has its own access rule"));
   const int64_t chunk_cap = L->nnz > 0 ? chunk_bound(L->nnz, L->bundle, L->hub) : 0;
 
   // device buffers
@@ -1075,7 +1054,6 @@ int layout_get_info(const layout_t* L, layout_info* info) {
   info->k = L->k;
   info->epochs = L->epochs;
   info->update_mode = L->mode;
-  info->access = L->access;
   info->hub_split_edges = L->hub;
   return LAYOUT_OK;
 }
@@ -1169,14 +1147,10 @@ int layout_debug_alias(const layout_t* L, uint32_t* thr_out, uint32_t* alias_out
   return LAYOUT_OK;
 }
 
-int layout_bench_gather(layout_t* L, int32_t mode, int32_t access, int32_t reps, float* ms) {
+int layout_bench_gather(layout_t* L, int32_t mode, int32_t reps, float* ms) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (!ms || reps < 1) return fail(LAYOUT_E_INVALID_ARG, "ms NULL or reps < 1");
   if (mode != kStore && mode != kAtomic) return fail(LAYOUT_E_INVALID_ARG, "mode %d", mode);
-  if (access < LAYOUT_ACCESS_COHERENT || access > LAYOUT_ACCESS_CACHED)
-    return fail(LAYOUT_E_INVALID_ARG, "access %d", access);
-  if (access != LAYOUT_ACCESS_COHERENT && mode != kStore)
-    return fail(LAYOUT_E_UNSUPPORTED, "cached access only with the store policy");
   if (L->nnz == 0) {
     *ms = 0.f;
     return LAYOUT_OK;
@@ -1199,14 +1173,8 @@ int layout_bench_gather(layout_t* L, int32_t mode, int32_t access, int32_t reps,
         const int grid = global_grid(gg);
         hipError_t ee = hipEventRecord(a, L->stream);
         for (int r = 0; r < reps && ee == hipSuccess; ++r) {
-          if (access == LAYOUT_ACCESS_CACHED) {
-            if constexpr (MODE == kStore)
-              hipLaunchKernelGGL((gather_rmw_kernel<K, MODE, GlobalCachedMem>), dim3(grid),
-                                 dim3(256), 0, L->stream, L->d_table, L->n_chunks);
-          } else {
-            hipLaunchKernelGGL((gather_rmw_kernel<K, MODE, GlobalMem>), dim3(grid), dim3(256), 0,
-                               L->stream, L->d_table, L->n_chunks);
-          }
+          hipLaunchKernelGGL((gather_rmw_kernel<K, MODE, GlobalMem>), dim3(grid), dim3(gg.block),
+                             0, L->stream, L->d_table, L->n_chunks);
         }
         if (ee == hipSuccess) ee = hipEventRecord(b, L->stream);
         if (ee == hipSuccess) ee = hipEventSynchronize(b);

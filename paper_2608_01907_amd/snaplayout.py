@@ -26,8 +26,6 @@ LAYOUT_HOGWILD_STORE = 0
 LAYOUT_ATOMIC = 1
 LAYOUT_JACOBI = 2
 LAYOUT_UPDATE_AUTO = 3
-LAYOUT_ACCESS_COHERENT = 0
-LAYOUT_ACCESS_CACHED = 1
 LAYOUT_INIT_UNIFORM = 0
 LAYOUT_INIT_PMDS = 1
 LAYOUT_NEG_UNIFORM = 0
@@ -58,7 +56,7 @@ class layout_opts(ctypes.Structure):
         ("update_mode", ctypes.c_int32), ("neg_weights", ctypes.c_int32),
         ("engine", ctypes.c_int32), ("start_epoch", ctypes.c_int32),
         ("bundle_edges", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-        ("grid_blocks", ctypes.c_int32), ("access", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32),
         ("hub_split_edges", ctypes.c_int32), ("nodes_per_lane", ctypes.c_int32),
         ("init_mode", ctypes.c_int32), ("pmds_pivots", ctypes.c_int32),
         ("init_pos", ctypes.c_void_p), ("stream", ctypes.c_void_p),
@@ -73,7 +71,7 @@ class layout_info(ctypes.Structure):
         ("n_chunks", ctypes.c_int64), ("nnz", ctypes.c_int64),
         ("n", ctypes.c_int32), ("k", ctypes.c_int32),
         ("epochs", ctypes.c_int32), ("update_mode", ctypes.c_int32),
-        ("access", ctypes.c_int32), ("hub_split_edges", ctypes.c_int32),
+        ("hub_split_edges", ctypes.c_int32),
     ]
 
 
@@ -148,7 +146,7 @@ _SIGNATURES = {
     "layout_debug_alias": (ctypes.c_int, [_vp, _vp, _vp]),
     "layout_debug_draws_at": (ctypes.c_int, [_vp, _i32, _vp, _i64, _vp]),
     "layout_debug_chunks": (ctypes.c_int, [_vp, _vp, _vp]),
-    "layout_bench_gather": (ctypes.c_int, [_vp, _i32, _i32, _i32, _f32p]),
+    "layout_bench_gather": (ctypes.c_int, [_vp, _i32, _i32, _f32p]),
     "layout_bench_copy": (ctypes.c_int, [_i64, _i32, _f32p]),
     "layout_batch_create": (ctypes.c_int, [ctypes.POINTER(layout_graph), _i32, _i32, _i32,
                                            ctypes.POINTER(layout_opts), _i32,
@@ -355,9 +353,9 @@ def layout_debug_alias(h, n):
     return thr[:n], alias[:n]
 
 
-def layout_bench_gather(h, mode, reps, access=LAYOUT_ACCESS_COHERENT):
+def layout_bench_gather(h, mode, reps):
     ms = ctypes.c_float()
-    _check(lib().layout_bench_gather(h, mode, access, reps, ctypes.byref(ms)))
+    _check(lib().layout_bench_gather(h, mode, reps, ctypes.byref(ms)))
     return ms.value
 
 
@@ -497,7 +495,7 @@ class Layout:
     """One layout job: owns a handle; positions come back as numpy arrays."""
 
     def __init__(self, row_ptr, col_idx, n, k=5, epochs=50, seed=0, *,
-                 update_mode=LAYOUT_UPDATE_AUTO, access=LAYOUT_ACCESS_COHERENT,
+                 update_mode=LAYOUT_UPDATE_AUTO,
                  neg_weights=LAYOUT_NEG_UNIFORM, engine=LAYOUT_ENGINE_AUTO, eta0=1.0,
                  alpha=0.1, beta=8.0, gamma=2.0, init_pos=None, bundle_edges=0,
                  block_threads=0, grid_blocks=0, start_epoch=0, stream=None,
@@ -514,7 +512,6 @@ class Layout:
                 o.neg_weight_values = w_keep.ctypes.data
         o.alpha, o.beta, o.gamma, o.eta0 = alpha, beta, gamma, eta0
         o.update_mode, o.neg_weights, o.engine = update_mode, neg_weights, engine
-        o.access = access
         o.bundle_edges, o.block_threads, o.grid_blocks = bundle_edges, block_threads, grid_blocks
         o.start_epoch = start_epoch
         o.hub_split_edges = hub_split_edges
