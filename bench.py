@@ -349,7 +349,7 @@ def bench_served(args):
         ids = []
         for q, ta in zip(picks, arrivals):
             while time.perf_counter() - t_start < ta:
-                time.sleep(min(0.0005, ta - (time.perf_counter() - t_start)))
+                time.sleep(max(0.0, min(0.0005, ta - (time.perf_counter() - t_start))))
             g = pool[q]
             ids.append((SL.layout_server_submit(srv, g.row_ptr, g.col, g.n, k, T, int(q)), g.n))
             if len(ids) % 100 == 0:

@@ -231,6 +231,16 @@ int layout_sampled_energy(layout_t *L, int32_t epoch, double *attr_out, double *
  * epochs at fixed positions tends to this value.  Errors as above. */
 int layout_effective_energy(layout_t *L, double *attr_out, double *rep_out);
 
+/* Silhouette index of the current positions for the clusters given by
+ * labels (host int32[n], any values; at least 2 distinct, else
+ * E_INVALID_ARG): the mean over all nodes of (b_i - a_i) / max(a_i, b_i),
+ * a_i the mean distance to the other members of i's cluster, b_i the
+ * smallest mean distance to another cluster, 0 for a node alone in its
+ * cluster (the SI metric of Sec. 4.1, exact over all pairs rather than on a
+ * node sample).  O(n^2) on the device: about 15 ms for 259k nodes.
+ * Allocates and frees temporary device memory. */
+int layout_silhouette(layout_t *L, const int32_t *labels, double *si_out);
+
 /* Writes the k negatives the epoch kernels draw for every directed edge in
  * epoch t (host array nnz*k, int32, edge-major).  Does not change positions. */
 int layout_debug_draws(layout_t *L, int32_t epoch, int32_t *host_out);

@@ -11,7 +11,8 @@
 //   * the degree-weighted objective that the sampling realises in expectation:
 //     the same attraction plus k/(n-1) * sum_{i<j} (d_i + d_j) U_r(q_ij).
 // The first is a stream over the edges with random gathers; the second is a
-// dense all-pairs sweep bound by the vector ALUs.
+// dense all-pairs sweep bound by the vector ALUs.  The exact silhouette index
+// of a layout (a quality metric of Sec. 4.1) is the same kind of sweep.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -151,6 +152,83 @@ static __global__ void __launch_bounds__(256)
     if (live) acc += double(part);
   }
   block_add2<256>(0.0, acc, out);
+}
+
+// out[q] = Y[order[q]]
+static __global__ void gather_positions_kernel(const float2* __restrict__ Y,
+                                               const int32_t* __restrict__ order, int32_t n,
+                                               float2* __restrict__ out) {
+  const int32_t q = int32_t(blockIdx.x) * blockDim.x + int32_t(threadIdx.x);
+  if (q < n) out[q] = Y[order[q]];
+}
+
+// Silhouette index (the SI metric of Sec. 4.1) of all nodes for given
+// clusters, exactly: s(i) = (b_i - a_i) / max(a_i, b_i) with a_i the mean
+// distance from i to the other members of its cluster and b_i the smallest
+// mean distance to another cluster (s = 0 for a node alone in its cluster).
+// Positions arrive sorted by cluster (Ys, cs; cluster c spans
+// [cstart[c], cstart[c+1])).  One lane per node i; every lane sweeps all
+// nodes in 256-node LDS tiles, so a cluster boundary inside a tile is the
+// same for all lanes (uniform branch).  Distances are summed in FP32 within a
+// tile and in FP64 across tiles.  out[0] += sum over the block of s(i).
+static __global__ void __launch_bounds__(256)
+    silhouette_kernel(const float2* __restrict__ Ys, const int32_t* __restrict__ cs,
+                      const int32_t* __restrict__ cstart, int32_t n, double* __restrict__ out) {
+  __shared__ float2 ty[256];
+  __shared__ int32_t tc[256];
+  const int32_t i = int32_t(blockIdx.x) * 256 + int32_t(threadIdx.x);
+  const bool live = i < n;
+  const float2 yi = live ? Ys[i] : make_float2(0.f, 0.f);
+  const int32_t ci = live ? cs[i] : -1;
+  double a = 0.0, b = 1.0e300, acc = 0.0;
+  int32_t cur = -1;
+  float part = 0.f;
+  const int32_t tiles = (n + 255) / 256;
+  for (int32_t t = 0; t < tiles; ++t) {
+    const int32_t jb = t * 256;
+    const int32_t jl = jb + int32_t(threadIdx.x);
+    __syncthreads();
+    if (jl < n) {
+      ty[threadIdx.x] = Ys[jl];
+      tc[threadIdx.x] = cs[jl];
+    }
+    __syncthreads();
+    const int32_t cnt = min(256, n - jb);
+    for (int32_t q = 0; q < cnt; ++q) {
+      const int32_t c = tc[q];
+      if (c != cur) {  // the same for every lane of the block
+        if (cur >= 0) {
+          acc += double(part);
+          const int32_t size = cstart[cur + 1] - cstart[cur];
+          if (cur == ci)
+            a = size > 1 ? acc / double(size - 1) : 0.0;
+          else
+            b = fmin(b, acc / double(size));
+        }
+        cur = c;
+        acc = 0.0;
+        part = 0.f;
+      }
+      const float dx = yi.x - ty[q].x, dy = yi.y - ty[q].y;
+      part += sqrtf(dx * dx + dy * dy);
+    }
+    acc += double(part);
+    part = 0.f;
+  }
+  if (cur >= 0) {
+    const int32_t size = cstart[cur + 1] - cstart[cur];
+    if (cur == ci)
+      a = size > 1 ? acc / double(size - 1) : 0.0;
+    else
+      b = fmin(b, acc / double(size));
+  }
+  double si = 0.0;
+  if (live) {
+    const int32_t own = cstart[ci + 1] - cstart[ci];
+    const double m = fmax(a, b);
+    si = (own > 1 && m > 0.0) ? (b - a) / m : 0.0;
+  }
+  block_add2<256>(si, 0.0, out);
 }
 
 }  // namespace snap

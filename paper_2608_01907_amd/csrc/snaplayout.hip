@@ -1034,6 +1034,71 @@ int layout_effective_energy(layout_t* L, double* attr_out, double* rep_out) {
   return LAYOUT_OK;
 }
 
+int layout_silhouette(layout_t* L, const int32_t* labels, double* si_out) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (!labels || !si_out) return fail(LAYOUT_E_INVALID_ARG, "NULL labels or si_out");
+  const int32_t n = L->n;
+  if (n < 2) return fail(LAYOUT_E_INVALID_ARG, "silhouette needs at least 2 nodes");
+  // clusters 0..C-1 in order of label value; nodes counting-sorted by cluster
+  std::vector<int32_t> lv(labels, labels + n);
+  std::vector<int32_t> uniq(lv);
+  std::sort(uniq.begin(), uniq.end());
+  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+  const int32_t C = static_cast<int32_t>(uniq.size());
+  if (C < 2) return fail(LAYOUT_E_INVALID_ARG, "silhouette needs at least 2 clusters");
+  std::vector<int32_t> cid(n), cstart(size_t(C) + 1, 0), order(n), cs(n);
+  for (int32_t v = 0; v < n; ++v) {
+    cid[v] = static_cast<int32_t>(std::lower_bound(uniq.begin(), uniq.end(), lv[v]) - uniq.begin());
+    ++cstart[size_t(cid[v]) + 1];
+  }
+  for (int32_t c = 0; c < C; ++c) cstart[size_t(c) + 1] += cstart[c];
+  {
+    std::vector<int32_t> fill(cstart.begin(), cstart.end() - 1);
+    for (int32_t v = 0; v < n; ++v) {
+      const int32_t q = fill[cid[v]]++;
+      order[q] = v;
+      cs[q] = cid[v];
+    }
+  }
+  int rc = energy_buffer(L);
+  if (rc != LAYOUT_OK) return rc;
+  int32_t *d_order = nullptr, *d_cs = nullptr, *d_cstart = nullptr;
+  float2* d_Ys = nullptr;
+  hipError_t e = hipMalloc(&d_order, sizeof(int32_t) * size_t(n));
+  if (e == hipSuccess) e = hipMalloc(&d_cs, sizeof(int32_t) * size_t(n));
+  if (e == hipSuccess) e = hipMalloc(&d_cstart, sizeof(int32_t) * (size_t(C) + 1));
+  if (e == hipSuccess) e = hipMalloc(&d_Ys, sizeof(float2) * size_t(n));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_order, order.data(), sizeof(int32_t) * size_t(n), hipMemcpyHostToDevice,
+                       L->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_cs, cs.data(), sizeof(int32_t) * size_t(n), hipMemcpyHostToDevice,
+                       L->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_cstart, cstart.data(), sizeof(int32_t) * (size_t(C) + 1),
+                       hipMemcpyHostToDevice, L->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(L->d_energy, 0, 2 * sizeof(double), L->stream);
+  if (e == hipSuccess) {
+    const int grid = static_cast<int>(div_up(n, 256));
+    hipLaunchKernelGGL(gather_positions_kernel, dim3(grid), dim3(256), 0, L->stream,
+                       L->host_desc.Y, d_order, n, d_Ys);
+    hipLaunchKernelGGL(silhouette_kernel, dim3(grid), dim3(256), 0, L->stream, d_Ys, d_cs,
+                       d_cstart, n, L->d_energy);
+    e = hipGetLastError();
+  }
+  double out[2] = {0.0, 0.0};
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, L->d_energy, 2 * sizeof(double), hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (d_order) (void)hipFree(d_order);
+  if (d_cs) (void)hipFree(d_cs);
+  if (d_cstart) (void)hipFree(d_cstart);
+  if (d_Ys) (void)hipFree(d_Ys);
+  if (e != hipSuccess) return hip_fail(e, "silhouette");
+  *si_out = out[0] / double(n);
+  return LAYOUT_OK;
+}
+
 int layout_get_info(const layout_t* L, layout_info* info) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (!info) return fail(LAYOUT_E_INVALID_ARG, "info is NULL");

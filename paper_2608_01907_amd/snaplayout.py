@@ -137,6 +137,7 @@ _SIGNATURES = {
     "layout_last_error": (ctypes.c_char_p, []),
     "layout_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(layout_info)]),
     "layout_debug_draws": (ctypes.c_int, [_vp, _i32, _vp]),
+    "layout_silhouette": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double)]),
     "layout_pmds": (ctypes.c_int, [_vp, _vp, _i32, _i32, _u64, _i32, _vp, _vp, _vp,
                                    ctypes.POINTER(_i32)]),
     "layout_sampled_energy": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_double),
@@ -314,6 +315,14 @@ def layout_pmds(row_ptr, col_idx, n, pivots=0, seed=0, want_detail=False):
         return Y
     u = used.value
     return Y, piv[:u].copy(), dist[:u, :n].copy()
+
+
+def layout_silhouette(h, labels):
+    """Exact silhouette index of the current positions for the given labels."""
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    out = ctypes.c_double()
+    _check(lib().layout_silhouette(h, lab.ctypes.data, ctypes.byref(out)))
+    return out.value
 
 
 def layout_sampled_energy(h, epoch):
@@ -553,6 +562,9 @@ class Layout:
 
     def sampled_energy(self, epoch):
         return layout_sampled_energy(self.h, epoch)
+
+    def silhouette(self, labels):
+        return layout_silhouette(self.h, labels)
 
     def effective_energy(self):
         return layout_effective_energy(self.h)

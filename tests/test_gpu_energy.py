@@ -8,7 +8,9 @@
   relative error within 2e-5;
 * the expectation identity of Sec. 3.3 at a size the O(n^2) oracle cannot
   reach: the mean sampled repulsion over many epochs' draws at fixed positions
-  equals the GPU's effective repulsion within 5 standard errors.
+  equals the GPU's effective repulsion within 5 standard errors;
+* the exact silhouette index (the SI metric of Sec. 4.1, all pairs) against
+  sklearn's within 1e-5, and its per-epoch trace on the 259k-node graph.
 """
 import numpy as np
 import pytest
@@ -121,3 +123,55 @@ def test_energy_edge_cases():
         with pytest.raises(SL.LayoutError) as ei:
             L.sampled_energy(-1)
         assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
+
+
+# ---------------------------------------------------------------- silhouette
+def _sk_silhouette(Y, labels):
+    from sklearn.metrics import silhouette_score
+    return float(silhouette_score(np.asarray(Y, dtype=np.float64), labels))
+
+
+@pytest.mark.parametrize("which,epochs_run", [("d1", 0), ("d1", 20), ("pl20k", 5)])
+def test_silhouette_matches_sklearn(which, epochs_run, d1, pl20k):
+    """Exact SI over all pairs against sklearn's (FP64); FP32 distances summed
+    in FP64 per 256-node tile: within 1e-5."""
+    g = {"d1": d1, "pl20k": pl20k}[which]
+    with SL.Layout(g.row_ptr, g.col, g.n, k=5, epochs=30, seed=4) as L:
+        if epochs_run:
+            L.run(epochs_run)
+        Y = L.positions()
+        got = L.silhouette(g.labels)
+    ref = _sk_silhouette(Y, g.labels)
+    assert abs(got - ref) <= 1e-5, (got, ref)
+
+
+def test_silhouette_labels_singletons_and_errors(d1):
+    lab = (d1.labels.astype(np.int64) * 7 - 3).astype(np.int32)  # arbitrary values
+    lab[5] = 1000  # a cluster of one node: s = 0 there
+    with SL.Layout(d1.row_ptr, d1.col, d1.n, k=5, epochs=10, seed=1) as L:
+        L.run()
+        Y = L.positions()
+        got = L.silhouette(lab)
+        with pytest.raises(SL.LayoutError) as ei:
+            L.silhouette(np.zeros(d1.n, np.int32))
+        assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
+    assert abs(got - _sk_silhouette(Y, lab)) <= 1e-5
+
+
+def test_silhouette_trace_rises_on_the_259k_graph():
+    """SI of every node, per epoch, on the device (the convergence view of
+    the paper's evaluation): it rises from the random start, and the final
+    value agrees with the sampled CPU metric within its sampling error."""
+    from oracle import metrics as M
+    g = S.cached("orkut-like-259k", S.orkut_like)
+    trace = []
+    with SL.Layout(g.row_ptr, g.col, g.n, k=5, epochs=30, seed=0) as L:
+        trace.append(L.silhouette(g.labels))
+        for _ in range(3):
+            L.run(10)
+            trace.append(L.silhouette(g.labels))
+        Y = L.positions()
+    print("SI trace", [round(x, 4) for x in trace], flush=True)
+    assert trace[0] < 0.05 and trace[-1] > trace[1] > trace[0]
+    sampled = M.si_score(Y, g.labels, sample=10000, seed=12345)
+    assert abs(trace[-1] - sampled) <= 0.02, (trace[-1], sampled)
