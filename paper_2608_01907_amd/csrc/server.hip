@@ -235,14 +235,18 @@ int run_round(layout_server_t* S) {
     lt.push_back(d);
     max_lds = std::max(max_lds, lds_bytes_for(j->n));
   }
-  // global jobs: a slice of the current epoch each
+  // global jobs: a slice of the current epoch each, the round's edges shared
+  // in proportion to the jobs' sizes so that every job advances the same
+  // fraction of an epoch per round (large jobs are not starved by many small
+  // ones)
   std::vector<GraphDesc> gt;
   std::vector<int64_t> slice(glob_jobs.size());
-  const int64_t share =
-      glob_jobs.empty() ? 0
-                        : std::max<int64_t>(kMinSliceEdges, S->round_edges / int64_t(glob_jobs.size()));
+  double total_nnz = 0.0;
+  for (Job* j : glob_jobs) total_nnz += double(j->nnz);
   for (size_t q = 0; q < glob_jobs.size(); ++q) {
     Job* j = glob_jobs[q];
+    const int64_t share = std::max<int64_t>(
+        kMinSliceEdges, int64_t(double(S->round_edges) * double(j->nnz) / std::max(1.0, total_nnz)));
     const double edges_per_chunk = double(j->nnz) / double(std::max<int64_t>(1, j->n_chunks));
     const int64_t want = std::max<int64_t>(1, int64_t(double(share) / edges_per_chunk));
     slice[q] = std::min(want, j->n_chunks - j->chunk_pos);
