@@ -1,0 +1,94 @@
+"""Pins of the layout-quality metrics (NP, SI, CQ of Sec. 4.1), which every
+quality comparison applies to oracle and device layouts alike (CPU only).
+
+* r-rings against breadth-first distances from scipy's shortest paths, and
+  the two ring implementations against each other;
+* NP against its definition written out by brute force (all pairwise layout
+  distances, ties by index), and NP = 1 exactly for a path laid on a line
+  (the 2-ring of every node is its set of nearest layout neighbours);
+* SI against a brute-force silhouette;
+* CQ = 1 for labels that are well-separated blobs, and about 0 for noise.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import shortest_path
+
+import synthgraph as S
+from oracle import metrics as M
+
+
+@pytest.fixture(scope="module")
+def small():
+    return S.chung_lu_communities(300, 900, tau=2.3, dmax=40.0, n_comm=4, intra=0.85, seed=6)
+
+
+def test_rings_match_bfs_distances(small):
+    g = small
+    A = sp.csr_matrix((np.ones(g.nnz), g.col, g.row_ptr), shape=(g.n, g.n))
+    D = shortest_path(A, method="D", unweighted=True)
+    for i in (0, 5, 77, int(np.argmax(g.degrees()))):
+        ref = np.flatnonzero((D[i] >= 1) & (D[i] <= 2))
+        assert np.array_equal(M.ring(g.row_ptr, g.col, i, 2), ref)
+        assert np.array_equal(M._ring_fast(g.row_ptr, g.col, i, 2), ref)
+
+
+def _np_brute(row_ptr, col, Y):
+    n = Y.shape[0]
+    A = sp.csr_matrix((np.ones(row_ptr[-1]), col, row_ptr), shape=(n, n))
+    D = shortest_path(A, method="D", unweighted=True)
+    dist = np.linalg.norm(Y[:, None, :] - Y[None, :, :], axis=2)
+    vals = []
+    for i in range(n):
+        ring = set(np.flatnonzero((D[i] >= 1) & (D[i] <= 2)).tolist())
+        k = len(ring)
+        if k == 0:
+            continue
+        order = sorted((j for j in range(n) if j != i), key=lambda j: (dist[i, j], j))
+        knn = set(order[:k])
+        vals.append(len(ring & knn) / len(ring | knn))
+    return float(np.mean(vals))
+
+
+def test_np_matches_brute_force(small):
+    rng = np.random.default_rng(2)
+    Y = rng.standard_normal((small.n, 2))
+    assert abs(M.np_score(small.row_ptr, small.col, Y) - _np_brute(small.row_ptr, small.col, Y)) \
+        <= 1e-12
+
+
+def test_np_is_one_for_a_path_on_a_line():
+    n = 50
+    rp, col = S.csr_from_pairs(np.arange(n - 1), np.arange(1, n), n)
+    Y = np.stack([np.arange(n, dtype=np.float64), np.zeros(n)], axis=1)
+    assert M.np_score(rp, col, Y) == 1.0
+
+
+def _si_brute(Y, labels):
+    n = Y.shape[0]
+    dist = np.linalg.norm(Y[:, None, :] - Y[None, :, :], axis=2)
+    s = np.zeros(n)
+    for i in range(n):
+        own = labels == labels[i]
+        if own.sum() <= 1:
+            continue
+        a = dist[i, own].sum() / (own.sum() - 1)
+        b = min(dist[i, labels == c].mean() for c in np.unique(labels) if c != labels[i])
+        s[i] = (b - a) / max(a, b)
+    return float(s.mean())
+
+
+def test_si_matches_brute_force(small):
+    rng = np.random.default_rng(3)
+    Y = rng.standard_normal((small.n, 2)) + 3.0 * small.labels[:, None]
+    assert abs(M.si_score(Y, small.labels) - _si_brute(Y, small.labels)) <= 1e-12
+
+
+def test_cq_extremes():
+    rng = np.random.default_rng(4)
+    labels = np.repeat(np.arange(4), 100)
+    centres = np.array([[0, 0], [50, 0], [0, 50], [50, 50]], dtype=np.float64)
+    Y = centres[labels] + rng.standard_normal((400, 2))
+    assert M.cq_score(Y, labels) == pytest.approx(1.0)
+    noise = rng.standard_normal((400, 2))
+    assert abs(M.cq_score(noise, labels)) < 0.05
