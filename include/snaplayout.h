@@ -241,6 +241,23 @@ int layout_effective_energy(layout_t *L, double *attr_out, double *rep_out);
  * Allocates and frees temporary device memory. */
 int layout_silhouette(layout_t *L, const int32_t *labels, double *si_out);
 
+/* Neighbourhood preservation of the current positions at the listed query
+ * nodes (the NP metric of Sec. 4.1, exact for each query rather than through
+ * a spatial index).  For query i: R_i = the nodes at hop distance 1..radius
+ * from i (i excluded; radius 1 or 2, else E_INVALID_ARG), k_i = |R_i|, and
+ * K_i = the k_i nodes nearest to y_i (i excluded), ranked by the FP32
+ * squared distance fl(fl(dx*dx) + fl(dy*dy)), dx = fl(y_l.x - y_i.x), ties
+ * by node index.  nodes: host int32[count], each in [0, n), else
+ * E_INVALID_ARG (repeats allowed).  k_out, inter_out: host int32[count],
+ * receive k_i and |R_i ∩ K_i|.  np_out (nullable): the mean over the queries
+ * with k_i > 0 of |R_i ∩ K_i| / |R_i ∪ K_i| (0 if there are none).  count = 0
+ * is a no-op.  Cost per query: O(n) for the selection (about four passes over
+ * the positions) plus O(sum of the ring's degrees); queries run in batches
+ * whose bitmaps take at most 256 MiB of temporary device memory, allocated
+ * and freed by the call.  Synchronises the handle's stream. */
+int layout_neighbourhood(layout_t *L, const int32_t *nodes, int32_t count, int32_t radius,
+                         int32_t *k_out, int32_t *inter_out, double *np_out);
+
 /* Writes the k negatives the epoch kernels draw for every directed edge in
  * epoch t (host array nnz*k, int32, edge-major).  Does not change positions. */
 int layout_debug_draws(layout_t *L, int32_t epoch, int32_t *host_out);

@@ -112,6 +112,39 @@ def np_score(row_ptr, col, Y, r: int = 2, sample: int | None = None, seed: int =
     return float(np.mean(scores)) if scores else 0.0
 
 
+def np_counts_f32(row_ptr, col, Y, nodes, r: int = 2):
+    """k_i = |N_G(i, r)| and |N_G(i, r) ∩ K_i| per query node, K_i the k_i
+    nearest layout neighbours of y_i ranked by the FP32 squared distance
+    fl(fl(dx*dx) + fl(dy*dy)) with dx = fl(y_l.x - y_i.x), ties by node index
+    (the NP metric of Sec. 4.1 with that ranking decided in single precision,
+    as a device implementation decides it).  Brute force over all nodes."""
+    Y = np.asarray(Y, dtype=np.float32)
+    n = Y.shape[0]
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    ks, inters = [], []
+    for i in np.asarray(nodes, dtype=np.int64):
+        ng = _ring_fast(row_ptr, col, int(i), r)
+        k = ng.size
+        if k == 0:
+            ks.append(0)
+            inters.append(0)
+            continue
+        dx = Y[:, 0] - Y[i, 0]
+        dy = Y[:, 1] - Y[i, 1]
+        q = dx * dx + dy * dy  # float32 throughout, no fused multiply-add
+        q[i] = np.inf
+        others = np.delete(np.arange(n), i)
+        qo = q[others]
+        qk = np.partition(qo, k - 1)[k - 1]
+        near = others[qo < qk]
+        ties = others[qo == qk]  # ascending node ids
+        near = np.concatenate([near, ties[:k - near.size]])
+        ks.append(k)
+        inters.append(np.intersect1d(ng, near).size)
+    return np.array(ks, dtype=np.int64), np.array(inters, dtype=np.int64)
+
+
 def si_score(Y, labels, sample: int | None = None, seed: int = 12345) -> float:
     """Silhouette index (Sec. 4.1) with the planted labels as clusters."""
     from sklearn.metrics import silhouette_score

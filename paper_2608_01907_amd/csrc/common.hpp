@@ -73,6 +73,11 @@ int pmds_positions(hipStream_t stream, const int32_t* d_row, const int32_t* d_co
                    int32_t pivots, uint64_t seed, float2* d_Y, int32_t* d_pivots_out,
                    int32_t* d_dist_out, int32_t* pivots_used);
 void launch_fill_zero(hipStream_t stream, float2* d_p, int64_t n);
+// k_i and |R_i ∩ K_i| of the NP metric for host query nodes (neighbours.hip;
+// host outputs, count entries).  Synchronises the stream.
+int neighbourhood_counts(hipStream_t stream, const int32_t* d_row, const int32_t* d_col,
+                         const float2* d_Y, int32_t n, const int32_t* nodes, int32_t count,
+                         int32_t radius, int32_t* k_out, int32_t* inter_out);
 
 // Graphs whose epochs run on the global engine, one launch per epoch for all
 // of them (table entries carry chunk_base prefixes over the group).

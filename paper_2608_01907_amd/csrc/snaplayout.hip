@@ -1099,6 +1099,33 @@ int layout_silhouette(layout_t* L, const int32_t* labels, double* si_out) {
   return LAYOUT_OK;
 }
 
+int layout_neighbourhood(layout_t* L, const int32_t* nodes, int32_t count, int32_t radius,
+                         int32_t* k_out, int32_t* inter_out, double* np_out) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (count < 0) return fail(LAYOUT_E_INVALID_ARG, "count < 0");
+  if (radius != 1 && radius != 2) return fail(LAYOUT_E_INVALID_ARG, "radius must be 1 or 2");
+  if (count > 0 && (!nodes || !k_out || !inter_out))
+    return fail(LAYOUT_E_INVALID_ARG, "NULL nodes, k_out or inter_out");
+  for (int32_t a = 0; a < count; ++a)
+    if (nodes[a] < 0 || nodes[a] >= L->n)
+      return fail(LAYOUT_E_INVALID_ARG, "query node %d out of range [0, %d)", nodes[a], L->n);
+  const int rc = neighbourhood_counts(L->stream, L->host_desc.row_ptr, L->host_desc.col,
+                                      L->host_desc.Y, L->n, nodes, count, radius, k_out,
+                                      inter_out);
+  if (rc != LAYOUT_OK) return rc;
+  if (np_out) {
+    double sum = 0.0;
+    int64_t used = 0;
+    for (int32_t a = 0; a < count; ++a) {
+      if (k_out[a] == 0) continue;
+      sum += double(inter_out[a]) / double(2 * int64_t(k_out[a]) - inter_out[a]);
+      ++used;
+    }
+    *np_out = used ? sum / double(used) : 0.0;
+  }
+  return LAYOUT_OK;
+}
+
 int layout_get_info(const layout_t* L, layout_info* info) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (!info) return fail(LAYOUT_E_INVALID_ARG, "info is NULL");

@@ -138,6 +138,8 @@ _SIGNATURES = {
     "layout_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(layout_info)]),
     "layout_debug_draws": (ctypes.c_int, [_vp, _i32, _vp]),
     "layout_silhouette": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "layout_neighbourhood": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp,
+                                            ctypes.POINTER(ctypes.c_double)]),
     "layout_pmds": (ctypes.c_int, [_vp, _vp, _i32, _i32, _u64, _i32, _vp, _vp, _vp,
                                    ctypes.POINTER(_i32)]),
     "layout_sampled_energy": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_double),
@@ -323,6 +325,17 @@ def layout_silhouette(h, labels):
     out = ctypes.c_double()
     _check(lib().layout_silhouette(h, lab.ctypes.data, ctypes.byref(out)))
     return out.value
+
+
+def layout_neighbourhood(h, nodes, radius=2):
+    """(NP mean, k_i, |R_i ∩ K_i|) at the query nodes (exact, FP32 ranking)."""
+    q = np.ascontiguousarray(nodes, dtype=np.int32)
+    k = np.zeros(max(q.size, 1), dtype=np.int32)
+    inter = np.zeros(max(q.size, 1), dtype=np.int32)
+    out = ctypes.c_double()
+    _check(lib().layout_neighbourhood(h, q.ctypes.data, int(q.size), int(radius), k.ctypes.data,
+                                      inter.ctypes.data, ctypes.byref(out)))
+    return out.value, k[:q.size], inter[:q.size]
 
 
 def layout_sampled_energy(h, epoch):
@@ -568,6 +581,9 @@ class Layout:
 
     def effective_energy(self):
         return layout_effective_energy(self.h)
+
+    def neighbourhood(self, nodes, radius=2):
+        return layout_neighbourhood(self.h, nodes, radius)
 
     def status(self):
         return layout_status(self.h)

@@ -92,3 +92,39 @@ def test_cq_extremes():
     assert M.cq_score(Y, labels) == pytest.approx(1.0)
     noise = rng.standard_normal((400, 2))
     assert abs(M.cq_score(noise, labels)) < 0.05
+
+
+# ------------------------------------------------- NP ranked in single precision
+def test_np_counts_f32_line_and_coincident_positions():
+    # a path laid on a line: every 2-ring is exactly the nearest set
+    n = 40
+    rp, col = S.csr_from_pairs(np.arange(n - 1), np.arange(1, n), n)
+    Y = np.stack([np.arange(n, dtype=np.float32), np.zeros(n, np.float32)], axis=1)
+    k, inter = M.np_counts_f32(rp, col, Y, np.arange(n))
+    assert np.array_equal(k, inter)
+    assert k[0] == 2 and k[1] == 3 and np.all(k[2:n - 2] == 4)
+    # all nodes at one point: every distance ties, so K_i is the k_i smallest
+    # ids other than i
+    g = S.chung_lu_communities(200, 600, tau=2.3, dmax=30.0, n_comm=3, intra=0.8, seed=1)
+    Y0 = np.zeros((g.n, 2), np.float32)
+    nodes = np.arange(0, g.n, 7)
+    k, inter = M.np_counts_f32(g.row_ptr, g.col, Y0, nodes)
+    for i, ki, ii in zip(nodes, k, inter):
+        ring = M.ring(g.row_ptr, g.col, int(i), 2)
+        assert ki == ring.size
+        smallest = np.delete(np.arange(g.n), i)[:ki]
+        assert ii == np.intersect1d(ring, smallest).size
+
+
+def test_np_counts_f32_agree_with_the_fp64_metric(small):
+    rng = np.random.default_rng(5)
+    Y = rng.standard_normal((small.n, 2)).astype(np.float32)
+    k, inter = M.np_counts_f32(small.row_ptr, small.col, Y, np.arange(small.n))
+    used = k > 0
+    mean = float(np.mean(inter[used] / (2 * k[used] - inter[used])))
+    assert abs(mean - M.np_score(small.row_ptr, small.col, Y.astype(np.float64))) <= 1e-12
+    # radius 1 against the brute force of the definition with 1-rings
+    k1, i1 = M.np_counts_f32(small.row_ptr, small.col, Y, np.arange(small.n), r=1)
+    assert np.array_equal(k1, np.diff(small.row_ptr))
+    assert abs(float(np.mean(i1[k1 > 0] / (2 * k1[k1 > 0] - i1[k1 > 0])))
+               - M.np_score(small.row_ptr, small.col, Y.astype(np.float64), r=1)) <= 1e-12
