@@ -68,6 +68,9 @@ def lib():
         L.oracle_init_positions_scaled.argtypes = [ctypes.c_int64, ctypes.c_uint64,
                                                    ctypes.c_float, _f64p]
         L.oracle_init_positions_scaled.restype = None
+        L.oracle_init_positions_dim.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_float,
+                                                ctypes.c_int32, _f64p]
+        L.oracle_init_positions_dim.restype = None
         L.oracle_init_positions_at.argtypes = [ctypes.c_int64, ctypes.c_uint64, _i64p,
                                                ctypes.c_int64, _f64p]
         L.oracle_init_positions_at.restype = None
@@ -87,13 +90,13 @@ def lib():
         L.oracle_serial_run.argtypes = [
             _i32p, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
             ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-            ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _u32p, _u32p, _f64p]
+            ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _u32p, _u32p, ctypes.c_int32, _f64p]
         L.oracle_serial_run.restype = ctypes.c_int
         L.oracle_jacobi_epoch.argtypes = [
             _i32p, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
             ctypes.c_uint64, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-            ctypes.c_int32, _u32p, _u32p, ctypes.c_int32, ctypes.c_int32, _f64p, _f64p,
-            ctypes.c_void_p]
+            ctypes.c_int32, _u32p, _u32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _f64p,
+            _f64p, ctypes.c_void_p]
         L.oracle_jacobi_epoch.restype = ctypes.c_int
         L.oracle_sampled_energy.argtypes = [
             _i32p, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
@@ -139,11 +142,15 @@ def philox_bulk(key, ctr, count):
     return out.reshape(count, 4)
 
 
-def init_positions(n, seed):
-    """Seeded uniform init in [-sqrt(n), sqrt(n)]^2 (FP32 values, widened)."""
-    Y = np.zeros(2 * max(n, 1), dtype=np.float64)
-    lib().oracle_init_positions(int(n), int(seed), Y)
-    return Y[: 2 * n].reshape(n, 2)
+def init_positions(n, seed, dim=2):
+    """Seeded uniform init in [-sqrt(n), sqrt(n)]^dim (FP32 values, widened)."""
+    Y = np.zeros(dim * max(n, 1), dtype=np.float64)
+    if dim == 2:
+        lib().oracle_init_positions(int(n), int(seed), Y)
+    else:
+        lib().oracle_init_positions_dim(int(n), int(seed), float(np.sqrt(np.float32(n))),
+                                        int(dim), Y)
+    return Y[: dim * n].reshape(n, dim)
 
 
 def init_positions_scaled(n, seed, scale):
@@ -205,37 +212,43 @@ def force_magnitudes(dist, alpha=ALPHA, beta=BETA, gamma=GAMMA):
 
 def serial_run(row_ptr, col, n, k, T, seed, Y0=None, t_begin=0, t_end=None,
                order=ORDER_SHUFFLED, mode=NEG_UNIFORM, thr=None, alias=None,
-               alpha=ALPHA, beta=BETA, gamma=GAMMA, eta0=ETA0):
-    """Serial Algorithm 1 in FP64 over epochs [t_begin, t_end) of a T-epoch run."""
+               alpha=ALPHA, beta=BETA, gamma=GAMMA, eta0=ETA0, dim=None):
+    """Serial Algorithm 1 in FP64 over epochs [t_begin, t_end) of a T-epoch run;
+    dim (2 or 3) defaults to the width of Y0, else 2."""
     rp, c = _csr(row_ptr, col)
     thr, alias = _tables(n, thr, alias)
     if t_end is None:
         t_end = T
-    Y = init_positions(n, seed) if Y0 is None else np.array(Y0, dtype=np.float64)
+    if dim is None:
+        dim = 2 if Y0 is None else int(np.asarray(Y0).reshape(n, -1).shape[1]) if n else 2
+    Y = init_positions(n, seed, dim) if Y0 is None else np.array(Y0, dtype=np.float64)
     Y = np.ascontiguousarray(Y.reshape(-1))
     if Y.size == 0:
-        Y = np.zeros(2, dtype=np.float64)
+        Y = np.zeros(dim, dtype=np.float64)
     lib().oracle_serial_run(rp, c, int(n), int(k), int(t_begin), int(t_end), int(T), int(seed),
-                            alpha, beta, gamma, eta0, int(order), int(mode), thr, alias, Y)
-    return Y[: 2 * n].reshape(n, 2)
+                            alpha, beta, gamma, eta0, int(order), int(mode), thr, alias, int(dim),
+                            Y)
+    return Y[: dim * n].reshape(n, dim)
 
 
 def jacobi_epoch(row_ptr, col, n, k, t, T, seed, Y, mode=NEG_UNIFORM, thr=None, alias=None,
                  use_attr=True, use_rep=True, alpha=ALPHA, beta=BETA, gamma=GAMMA, eta0=ETA0,
                  want_abs=False):
-    """One synchronous epoch from Y; returns Y_out (and the |contribution| sums)."""
+    """One synchronous epoch from Y (n x 2 or n x 3); returns Y_out (and the
+    |contribution| sums)."""
     rp, c = _csr(row_ptr, col)
     thr, alias = _tables(n, thr, alias)
+    dim = int(np.asarray(Y).reshape(n, -1).shape[1]) if n else 2
     Yin = np.ascontiguousarray(np.asarray(Y, dtype=np.float64).reshape(-1))
     Yout = np.zeros_like(Yin)
     absd = np.zeros_like(Yin) if want_abs else None
     lib().oracle_jacobi_epoch(rp, c, int(n), int(k), int(t), int(T), int(seed), alpha, beta,
                               gamma, eta0, int(mode), thr, alias, int(bool(use_attr)),
-                              int(bool(use_rep)), Yin, Yout,
+                              int(bool(use_rep)), dim, Yin, Yout,
                               absd.ctypes.data if want_abs else None)
     if want_abs:
-        return Yout.reshape(n, 2), absd.reshape(n, 2)
-    return Yout.reshape(n, 2)
+        return Yout.reshape(n, dim), absd.reshape(n, dim)
+    return Yout.reshape(n, dim)
 
 
 def sampled_energy(row_ptr, col, n, k, t, seed, Y, mode=NEG_UNIFORM, thr=None, alias=None,

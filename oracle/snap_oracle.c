@@ -30,7 +30,7 @@
  *   counter = (a, b, c, tag)    tag: 1 init, 2 negatives, 3 edge shuffle
  *   one Philox block gives four u64 x0..x3 = eight u32 words
  *       w[2q] = lo32(x_q), w[2q+1] = hi32(x_q)
- *   init of node i:     counter (i, 0, 0, 1); coordinate c from x_c:
+ *   init of node i:     counter (i, 0, 0, 1); coordinate c (< dim) from x_c:
  *                       v = (int)(x_c >> 40) - 2^23, y = (float)v * 2^-23 * s,
  *                       s = sqrtf((float)n) (FP32, one rounding)
  *   negatives of edge e in epoch t: word stream of blocks (e, t, b, 2), b=0,1,..
@@ -134,22 +134,28 @@ static uint32_t ws_word(word_stream *ws)
 }
 
 /* ------------------------------------------------------------ init layout */
-/* Uniform positions in [-scale, scale]^2 for nodes [0, n), produced in FP32
- * (one rounding) and widened exactly to FP64. */
-void oracle_init_positions_scaled(int64_t n, uint64_t seed, float s, double *Y)
+/* Uniform positions in [-scale, scale]^dim (dim 2 or 3) for nodes [0, n),
+ * produced in FP32 (one rounding) and widened exactly to FP64; Y is n*dim. */
+void oracle_init_positions_dim(int64_t n, uint64_t seed, float s, int32_t dim, double *Y)
 {
     uint64_t key[2] = {seed, KEY_DOMAIN};
     for (int64_t i = 0; i < n; ++i) {
         uint64_t ctr[4] = {(uint64_t)i, 0, 0, TAG_INIT};
         uint64_t x[4];
         oracle_philox4x64(ctr, key, x);
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < dim; ++c) {
             int32_t v = (int32_t)(x[c] >> 40) - (1 << 23);
             float unit = (float)v * 0x1p-23f; /* exact: 24-bit integer times 2^-23 */
             float coord = unit * s;           /* the only rounding */
-            Y[2 * i + c] = (double)coord;
+            Y[dim * i + c] = (double)coord;
         }
     }
+}
+
+/* Uniform positions in [-scale, scale]^2. */
+void oracle_init_positions_scaled(int64_t n, uint64_t seed, float s, double *Y)
+{
+    oracle_init_positions_dim(n, seed, s, 2, Y);
 }
 
 /* The initial layout: uniform in [-sqrt(n), sqrt(n)]^2. */
@@ -351,21 +357,34 @@ static int32_t *sources_of(const int32_t *row_ptr, int32_t n)
     return src;
 }
 
-/* One stochastic pair step on two points of Y (in place). */
-static void attract_pair(const force_params *fp, double eta, double *yi, double *yj)
+/* One stochastic pair step on two points of Y (in place), dim coordinates
+ * each; q sums the squared differences over all coordinates. */
+static void attract_pair(const force_params *fp, double eta, int dim, double *yi, double *yj)
 {
-    double dx = yi[0] - yj[0], dy = yi[1] - yj[1];
-    double c = eta * attr_coef(fp, dx * dx + dy * dy);
-    yi[0] -= c * dx; yi[1] -= c * dy;
-    yj[0] += c * dx; yj[1] += c * dy;
+    double d[3], q = 0.0;
+    for (int c = 0; c < dim; ++c) {
+        d[c] = yi[c] - yj[c];
+        q += d[c] * d[c];
+    }
+    double coef = eta * attr_coef(fp, q);
+    for (int c = 0; c < dim; ++c) {
+        yi[c] -= coef * d[c];
+        yj[c] += coef * d[c];
+    }
 }
 
-static void repel_pair(const force_params *fp, double eta, double *yi, double *ys)
+static void repel_pair(const force_params *fp, double eta, int dim, double *yi, double *ys)
 {
-    double dx = yi[0] - ys[0], dy = yi[1] - ys[1];
-    double c = eta * rep_coef(fp, dx * dx + dy * dy);
-    yi[0] += c * dx; yi[1] += c * dy;
-    ys[0] -= c * dx; ys[1] -= c * dy;
+    double d[3], q = 0.0;
+    for (int c = 0; c < dim; ++c) {
+        d[c] = yi[c] - ys[c];
+        q += d[c] * d[c];
+    }
+    double coef = eta * rep_coef(fp, q);
+    for (int c = 0; c < dim; ++c) {
+        yi[c] += coef * d[c];
+        ys[c] -= coef * d[c];
+    }
 }
 
 /* Serial Algorithm 1 in FP64 over epochs [t_begin, t_end) of a T-epoch
@@ -373,11 +392,11 @@ static void repel_pair(const force_params *fp, double eta, double *yi, double *y
  * (Algorithm 1, first step) by a seeded permutation; ORDER_CSR: rows in index
  * order, each row in CSR order (the visiting order of one bundle-serial
  * worker).  Positions are updated immediately after every pair force
- * (Sec. 3.3, "immediate updates").  Y is n*2, updated in place. */
+ * (Sec. 3.3, "immediate updates").  Y is n*dim (dim 2 or 3), updated in place. */
 int oracle_serial_run(const int32_t *row_ptr, const int32_t *col, int32_t n, int32_t k,
                       int64_t t_begin, int64_t t_end, int64_t T, uint64_t seed, double alpha,
                       double beta, double gamma, double eta0, int32_t order, int32_t mode,
-                      const uint32_t *thr, const uint32_t *alias, double *Y)
+                      const uint32_t *thr, const uint32_t *alias, int32_t dim, double *Y)
 {
     int64_t nnz = row_ptr[n];
     force_params fp = {alpha, beta, gamma, eta0};
@@ -405,9 +424,10 @@ int oracle_serial_run(const int32_t *row_ptr, const int32_t *col, int32_t n, int
         for (int64_t p = 0; p < nnz; ++p) {
             int64_t e = perm[p];
             int32_t i = src[e], j = col[e];
-            attract_pair(&fp, eta, Y + 2 * i, Y + 2 * j);
+            attract_pair(&fp, eta, dim, Y + (int64_t)dim * i, Y + (int64_t)dim * j);
             draw_negatives(&sp, seed, e, t, i, k, neg);
-            for (int32_t m = 0; m < k; ++m) repel_pair(&fp, eta, Y + 2 * i, Y + 2 * neg[m]);
+            for (int32_t m = 0; m < k; ++m)
+                repel_pair(&fp, eta, dim, Y + (int64_t)dim * i, Y + (int64_t)dim * neg[m]);
         }
     }
     free(neg);
@@ -422,49 +442,64 @@ int oracle_serial_run(const int32_t *row_ptr, const int32_t *col, int32_t n, int
  * the contributions are summed into D before Y_out = Y + D.  use_attr /
  * use_rep switch the two force families (for the expectation pins).  When
  * abs_out is non-NULL it receives, per node and coordinate, the sum of the
- * absolute values of the contributions (a rounding-error scale). */
+ * absolute values of the contributions (a rounding-error scale).  Y, Y_out and
+ * abs_out are n*dim (dim 2 or 3). */
+static void jacobi_pair(double coef, int dim, const double *d, int64_t a, int64_t b, double *D,
+                        double *abs_out)
+{
+    /* D[a] += coef * d, D[b] -= coef * d */
+    for (int c = 0; c < dim; ++c) {
+        D[a + c] += coef * d[c];
+        D[b + c] -= coef * d[c];
+        if (abs_out) {
+            abs_out[a + c] += fabs(coef * d[c]);
+            abs_out[b + c] += fabs(coef * d[c]);
+        }
+    }
+}
+
 int oracle_jacobi_epoch(const int32_t *row_ptr, const int32_t *col, int32_t n, int32_t k,
                         int64_t t, int64_t T, uint64_t seed, double alpha, double beta,
                         double gamma, double eta0, int32_t mode, const uint32_t *thr,
-                        const uint32_t *alias, int32_t use_attr, int32_t use_rep,
+                        const uint32_t *alias, int32_t use_attr, int32_t use_rep, int32_t dim,
                         const double *Y, double *Y_out, double *abs_out)
 {
     force_params fp = {alpha, beta, gamma, eta0};
     sampler sp = {n, mode, thr, alias};
     double eta = eta_at(&fp, t, T);
-    double *D = (double *)calloc((size_t)n * 2 + 2, sizeof(double));
+    double *D = (double *)calloc((size_t)n * (size_t)dim + 3, sizeof(double));
     int32_t *neg = (int32_t *)malloc(sizeof(int32_t) * (size_t)(k > 0 ? k : 1));
-    if (abs_out) memset(abs_out, 0, sizeof(double) * (size_t)n * 2);
+    if (abs_out) memset(abs_out, 0, sizeof(double) * (size_t)n * (size_t)dim);
     for (int32_t i = 0; i < n; ++i) {
+        const int64_t yi = (int64_t)dim * i;
         for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-            int32_t j = col[e];
+            const int64_t yj = (int64_t)dim * col[e];
+            double d[3], q;
             if (use_attr) {
-                double dx = Y[2 * i] - Y[2 * j], dy = Y[2 * i + 1] - Y[2 * j + 1];
-                double c = eta * attr_coef(&fp, dx * dx + dy * dy);
-                D[2 * i] -= c * dx; D[2 * i + 1] -= c * dy;
-                D[2 * j] += c * dx; D[2 * j + 1] += c * dy;
-                if (abs_out) {
-                    abs_out[2 * i] += fabs(c * dx); abs_out[2 * i + 1] += fabs(c * dy);
-                    abs_out[2 * j] += fabs(c * dx); abs_out[2 * j + 1] += fabs(c * dy);
+                q = 0.0;
+                for (int c = 0; c < dim; ++c) {
+                    d[c] = Y[yi + c] - Y[yj + c];
+                    q += d[c] * d[c];
                 }
+                /* attraction: y_i -= eta*A(d), y_j += eta*A(d) */
+                jacobi_pair(-eta * attr_coef(&fp, q), dim, d, yi, yj, D, abs_out);
             }
             if (use_rep && k > 0) {
                 draw_negatives(&sp, seed, e, t, i, k, neg);
                 for (int32_t m = 0; m < k; ++m) {
-                    int32_t s = neg[m];
-                    double dx = Y[2 * i] - Y[2 * s], dy = Y[2 * i + 1] - Y[2 * s + 1];
-                    double c = eta * rep_coef(&fp, dx * dx + dy * dy);
-                    D[2 * i] += c * dx; D[2 * i + 1] += c * dy;
-                    D[2 * s] -= c * dx; D[2 * s + 1] -= c * dy;
-                    if (abs_out) {
-                        abs_out[2 * i] += fabs(c * dx); abs_out[2 * i + 1] += fabs(c * dy);
-                        abs_out[2 * s] += fabs(c * dx); abs_out[2 * s + 1] += fabs(c * dy);
+                    const int64_t ys = (int64_t)dim * neg[m];
+                    q = 0.0;
+                    for (int c = 0; c < dim; ++c) {
+                        d[c] = Y[yi + c] - Y[ys + c];
+                        q += d[c] * d[c];
                     }
+                    /* repulsion: y_i += eta*R(d), y_s -= eta*R(d) */
+                    jacobi_pair(eta * rep_coef(&fp, q), dim, d, yi, ys, D, abs_out);
                 }
             }
         }
     }
-    for (int64_t v = 0; v < (int64_t)n * 2; ++v) Y_out[v] = Y[v] + D[v];
+    for (int64_t v = 0; v < (int64_t)n * dim; ++v) Y_out[v] = Y[v] + D[v];
     free(neg);
     free(D);
     return 0;
@@ -606,7 +641,7 @@ static void *thread_main(void *arg)
                 int32_t j = job->col[e];
                 double yi[2] = {ld(Y + 2 * i), ld(Y + 2 * i + 1)};
                 double yj[2] = {ld(Y + 2 * j), ld(Y + 2 * j + 1)};
-                attract_pair(&job->fp, eta, yi, yj);
+                attract_pair(&job->fp, eta, 2, yi, yj);
                 st(Y + 2 * i, yi[0]); st(Y + 2 * i + 1, yi[1]);
                 st(Y + 2 * j, yj[0]); st(Y + 2 * j + 1, yj[1]);
                 draw_negatives(&job->sp, job->seed, e, t, i, job->k, neg);
@@ -614,7 +649,7 @@ static void *thread_main(void *arg)
                     int32_t s = neg[m];
                     double ys[2] = {ld(Y + 2 * s), ld(Y + 2 * s + 1)};
                     yi[0] = ld(Y + 2 * i); yi[1] = ld(Y + 2 * i + 1);
-                    repel_pair(&job->fp, eta, yi, ys);
+                    repel_pair(&job->fp, eta, 2, yi, ys);
                     st(Y + 2 * i, yi[0]); st(Y + 2 * i + 1, yi[1]);
                     st(Y + 2 * s, ys[0]); st(Y + 2 * s + 1, ys[1]);
                 }

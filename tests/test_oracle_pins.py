@@ -467,3 +467,77 @@ def test_sampled_draws_and_init_match_full_ones():
     assert np.array_equal(got, full[edges])
     nodes = np.concatenate([[0, g.n - 1], rng.integers(0, g.n, 300)])
     assert np.array_equal(O.init_positions_at(g.n, 5, nodes), O.init_positions(g.n, 5)[nodes])
+
+
+# ------------------------------------------------------------ 3D positions
+def test_init_positions_3d_match_library_generator():
+    """3D init: coordinate c from word x_c of the same block (c = 0, 1, 2); the
+    first two coordinates are the 2D init."""
+    n, seed = 501, 6
+    Y3 = O.init_positions(n, seed, dim=3)
+    assert np.array_equal(Y3[:, :2], O.init_positions(n, seed))
+    s = np.sqrt(np.float32(n))
+    for i in range(0, n, 41):
+        x = _numpy_block(seed, i, 0, 0, 1)
+        v = np.int64(int(x[2]) >> 40) - (1 << 23)
+        assert Y3[i, 2] == float(np.float32(np.float32(np.float32(v) * np.float32(2.0**-23)) * s))
+
+
+@pytest.mark.parametrize("order", [O.ORDER_CSR, O.ORDER_SHUFFLED])
+def test_two_node_trajectory_closed_form_3d(order):
+    """The scalar recursion of the two-node graph holds for a 3D separation."""
+    rp, col = S.csr_from_pairs(np.array([0]), np.array([1]), 2)
+    k, T = 2, 30
+    Y0 = np.array([[1.0, -2.0, 2.5], [0.5, 1.0, -1.0]])
+    Y = O.serial_run(rp, col, 2, k, T, 5, Y0=Y0, order=order)
+    d = Y0[0] - Y0[1]
+    for t in range(T):
+        eta = 1.0 * (1 - t / T)
+        for _ in range(2):
+            d = d * (1 - 2 * eta * ALPHA * (1 + BETA / (1 + d @ d)))
+            for _ in range(k):
+                d = d * (1 + 2 * eta / (1 + d @ d) ** 2)
+    assert np.allclose(Y[0] - Y[1], d, rtol=1e-10, atol=1e-12)
+    assert np.allclose(Y.sum(0), Y0.sum(0), atol=1e-12)
+
+
+def test_3d_run_in_the_plane_is_the_2d_run():
+    """With every z = 0, a 3D run never leaves the plane and equals the 2D run
+    bit for bit (q gains +0, each z update is 0)."""
+    g = S.small_sbm(200, 2, 6.0, 3)
+    Y2 = O.init_positions(g.n, 2)
+    Y3 = np.concatenate([Y2, np.zeros((g.n, 1))], axis=1)
+    a = O.serial_run(g.row_ptr, g.col, g.n, 5, 8, 2, Y0=Y2)
+    b = O.serial_run(g.row_ptr, g.col, g.n, 5, 8, 2, Y0=Y3)
+    assert np.array_equal(b[:, :2], a) and np.all(b[:, 2] == 0.0)
+    ja = O.jacobi_epoch(g.row_ptr, g.col, g.n, 5, 1, 8, 2, Y2)
+    jb = O.jacobi_epoch(g.row_ptr, g.col, g.n, 5, 1, 8, 2, Y3)
+    assert np.array_equal(jb[:, :2], ja) and np.all(jb[:, 2] == 0.0)
+
+
+def test_3d_rotation_equivariance():
+    """Rotating the start rotates the result (forces depend on |d| only and act
+    along d), which a dropped or misplaced z term would break."""
+    g = S.small_sbm(150, 3, 5.0, 9)
+    Y0 = O.init_positions(g.n, 1, dim=3)
+    Q, _ = np.linalg.qr(np.random.default_rng(2).standard_normal((3, 3)))
+    a = O.serial_run(g.row_ptr, g.col, g.n, 4, 6, 1, Y0=Y0)
+    b = O.serial_run(g.row_ptr, g.col, g.n, 4, 6, 1, Y0=Y0 @ Q.T)
+    scale = 1 + np.abs(a).max()
+    assert np.allclose(b, a @ Q.T, atol=1e-9 * scale)
+    ja = O.jacobi_epoch(g.row_ptr, g.col, g.n, 4, 2, 6, 1, Y0)
+    jb = O.jacobi_epoch(g.row_ptr, g.col, g.n, 4, 2, 6, 1, Y0 @ Q.T)
+    assert np.allclose(jb, ja @ Q.T, atol=1e-9 * scale)
+
+
+def test_jacobi_attraction_is_exact_double_sum_3d():
+    rp, col, n = _hub_graph()
+    Y = O.init_positions(n, 8, dim=3)
+    Yo = O.jacobi_epoch(rp, col, n, 5, 3, 10, 1, Y, use_rep=False)
+    eta = 1.0 * (1 - 3 / 10)
+    src = np.repeat(np.arange(n), np.diff(rp))
+    D = Y[src] - Y[col]
+    A = ALPHA * (1 + BETA / (1 + (D ** 2).sum(1)))[:, None] * D
+    ref = np.zeros_like(Y)
+    np.add.at(ref, src, -2 * eta * A)
+    assert np.allclose(Yo - Y, ref, rtol=1e-12, atol=1e-12)
