@@ -110,7 +110,7 @@ typedef struct layout_opts {
     int32_t init_mode;        /* LAYOUT_INIT_UNIFORM (default) / LAYOUT_INIT_PMDS; ignored
                                  when init_pos is given */
     int32_t pmds_pivots;      /* pivots of LAYOUT_INIT_PMDS, 1..64; 0 = default 50 */
-    const float *init_pos;    /* n*2 initial positions (host, or device when the
+    const float *init_pos;    /* n*dim initial positions (host, or device when the
                                  inputs are on the device); NULL = init_mode */
     void *stream;             /* hipStream_t for all work of the handle; NULL = a
                                  stream owned by the library */
@@ -149,8 +149,14 @@ int layout_pmds(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32
 
 /* Creates a layout job with default options.  Validates the CSR on the device,
  * builds the chunk table, initialises positions.  Returns when the job is
- * ready.  row_ptr/col_idx: host arrays (copied).  dim must be 2.  k in [0, 8].
- * epochs >= 1.  seed keys every random draw (init and negatives). */
+ * ready.  row_ptr/col_idx: host arrays (copied).  dim: 2 (the paper's
+ * layouts), or 3 (the same force law with q = |y_i - y_j|^2 over three
+ * coordinates; positions are held as 16-byte (x, y, z, unused) entries on the
+ * device and exchanged as n*3 floats); other values E_UNSUPPORTED.  A 3D job
+ * has no Pivot MDS start and no 2D monitors (energies, silhouette, NP, gather
+ * roofline: E_UNSUPPORTED).  k in [0, 8].  epochs >= 1.  seed keys every
+ * random draw (init and negatives); the 3D init draws the third coordinate
+ * from the third word of the node's init block. */
 int layout_create(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t dim,
                   int32_t k, int32_t epochs, uint64_t seed, layout_t **out);
 
@@ -169,14 +175,15 @@ int layout_epoch(layout_t *L, int32_t count);
  * epoch kernels (HIP events on the handle's stream) in *ms. */
 int layout_epoch_timed(layout_t *L, int32_t count, float *ms);
 
-/* Copies the n*2 positions to host memory; waits for the handle's stream. */
+/* Copies the n*dim positions (row-major FP32) to host memory; waits for the
+ * handle's stream. */
 int layout_get_positions(const layout_t *L, float *host_out);
 
-/* Copies the n*2 positions to a device buffer, ordered after the handle's
+/* Copies the n*dim positions to a device buffer, ordered after the handle's
  * work; stream = NULL uses the handle's stream.  Does not wait. */
 int layout_get_positions_device(const layout_t *L, float *dev_out, void *stream);
 
-/* Overwrites the positions from host memory (n*2 floats); waits. */
+/* Overwrites the positions from host memory (n*dim floats); waits. */
 int layout_set_positions(layout_t *L, const float *host_in);
 
 /* Epochs run so far and device bytes held by the handle (either may be NULL). */

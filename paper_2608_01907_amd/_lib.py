@@ -25,6 +25,13 @@ def load(signatures: dict | None = None):
             raise LibraryMissing(
                 f"{LIB_PATH} is not built; run paper_2608_01907_amd/build.py "
                 "(or __graft_entry__.build()) first")
+        # PyTorch ships its own HIP runtime.  Loading torch first makes this
+        # library bind to that same runtime, so that one process never holds
+        # two (torch then finds no device when it starts after this library).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         _handle = ctypes.CDLL(LIB_PATH)
     if signatures:
         for name, (res, args) in signatures.items():

@@ -63,7 +63,10 @@ int build_alias_table(hipStream_t stream, const int32_t* d_row, const uint32_t* 
 // err is a device word of scratch.
 int validate_csr(hipStream_t stream, const int32_t* d_row, const int32_t* d_col, int32_t n,
                  int64_t nnz, uint32_t* d_err);
-void launch_init_positions(hipStream_t stream, float2* d_Y, int32_t n, uint64_t seed);
+// Seeded uniform initial positions; dim 3 writes float4 positions through the
+// float2 pointer (n float4 = 2n float2 of storage).
+void launch_init_positions(hipStream_t stream, float2* d_Y, int32_t n, uint64_t seed,
+                           int dim = 2);
 // Pivot MDS positions of a validated CSR (pmds.hip).  d_pivots_out (nullable,
 // device, [pivots]) receives the pivots, d_dist_out (nullable, device,
 // pivots x n) the hop distances; *pivots_used the pivots taken.  Synchronises
@@ -92,6 +95,7 @@ struct GlobalGroup {
   int block = 256;
   int grid = 0;    // 0 = fill the device, capped by max_lanes
   int64_t max_lanes = 0;  // 0 = no cap
+  int dim = 2;            // positions: float2 (2) or float4 (3)
   float2* jacobi_Y = nullptr;  // JACOBI: Y and D of every graph, contiguous
   float2* jacobi_D = nullptr;
   int64_t jacobi_nodes = 0;
@@ -105,6 +109,7 @@ struct LdsGroup {
   int k = 5, mode = kAtomic;
   bool degree = false;
   int block = 256;
+  int dim = 2;
 };
 // Global-group graphs on the XCD-local engine (see desc.hpp).
 struct XcdGroup {
@@ -125,7 +130,7 @@ int plan_xcd_bins(const std::vector<GraphDesc>& graphs, int nodes_per_lane,
                   std::vector<GraphDesc>& table, std::vector<XcdSeg>& segs, XcdBin* bins);
 int launch_xcd_group_epochs(hipStream_t stream, const XcdGroup& g, int32_t dt, int32_t count);
 void launch_fill_i32(hipStream_t stream, int32_t* p, int64_t n, int32_t v);
-int lds_bytes_for(int32_t n);
+int lds_bytes_for(int32_t n, int dim = 2);  // LDS of one graph's positions
 // Cuts the chunks of the graphs in table (host copy, n_chunks set) into
 // rounds for a launch of `lanes` lanes: sets each entry's slice/chunk_base and
 // the group's round_size/total_index/total_chunks.
@@ -136,7 +141,7 @@ int64_t fair_lanes(const std::vector<GraphDesc>& table, int nodes_per_lane);
 int global_grid(const GlobalGroup& g);  // resolved grid size
 int launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t dt, int32_t count);
 int launch_lds_epochs(hipStream_t stream, const LdsGroup& g, int32_t dt, int32_t count);
-int allow_lds(int k, int bytes);  // raise the dynamic LDS limit of the LDS kernels
+int allow_lds(int k, int bytes, int dim = 2);  // raise the dynamic LDS limit of the LDS kernels
 // negatives of every edge of one graph in epoch t (device out[nnz*k])
 int launch_dump_draws(hipStream_t stream, int k, bool degree, const GraphDesc& g, int32_t t,
                       int32_t* d_out);

@@ -8,7 +8,9 @@
 //     attraction: y_i -= eta*alpha*(1 + beta/(1+q)) d,   y_j += the same
 //     repulsion:  y_i += eta*d/(1+q)^gamma,              y_s -= the same
 // (signs read physically: edges pull, all pairs push, Sec. 3.1).  Positions are
-// updated immediately after each pair (Sec. 3.3), lock-free (Sec. 3.4).
+// updated immediately after each pair (Sec. 3.3), lock-free (Sec. 3.4).  A
+// position is 2D (float2) or 3D (float4 holding x, y, z; w unused), the same
+// force law with q over all coordinates.
 //
 // Work decomposition.  One lane owns one chunk of the row-aligned chunk table
 // (chunks.hpp): a run of whole rows of about B directed edges -- the paper's
@@ -53,6 +55,8 @@
 
 namespace snap {
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 // --------------------------------------------------------------- memory ops
 // Global positions: device-scope relaxed accesses, so that every lane reads
 // the value last committed at device level (no stale per-CU L1 copy), 64-bit
@@ -71,6 +75,22 @@ struct GlobalMem {
     __hip_atomic_fetch_add(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_fetch_add(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  // 3D: one 16-byte access with system-scope cache bits (coherent across
+  // XCDs like the 8-byte accesses above; a random 16-byte access costs the
+  // memory system the same request as an 8-byte one, while splitting it into
+  // 8 + 4 bytes would take two)
+  static __device__ __forceinline__ float4 load(const float4* p) {
+    const v4f v = *reinterpret_cast<const volatile v4f*>(p);
+    return make_float4(v.x, v.y, v.z, v.w);
+  }
+  static __device__ __forceinline__ void store(float4* p, float4 v) {
+    *reinterpret_cast<volatile v4f*>(p) = v4f{v.x, v.y, v.z, v.w};
+  }
+  static __device__ __forceinline__ void add(float4* p, float4 v) {
+    __hip_atomic_fetch_add(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&p->z, v.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 };
 
 // Positions touched by the CUs of one XCD only (the XCD-local engine): plain
@@ -82,6 +102,9 @@ struct XcdLocalMem {
   static __device__ __forceinline__ float2 load(const float2* p) { return *p; }
   static __device__ __forceinline__ void store(float2* p, float2 v) { *p = v; }
   static __device__ __forceinline__ void add(float2* p, float2 v) { GlobalMem::add(p, v); }
+  static __device__ __forceinline__ float4 load(const float4* p) { return *p; }
+  static __device__ __forceinline__ void store(float4* p, float4 v) { *p = v; }
+  static __device__ __forceinline__ void add(float4* p, float4 v) { GlobalMem::add(p, v); }
 };
 
 // LDS-resident positions (one workgroup owns the whole graph).
@@ -99,7 +122,71 @@ struct LdsMem {
     __hip_atomic_fetch_add(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __hip_atomic_fetch_add(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
+  static __device__ __forceinline__ float4 load(const float4* p) {
+    const v4f v = *reinterpret_cast<const volatile v4f*>(p);
+    return make_float4(v.x, v.y, v.z, v.w);
+  }
+  static __device__ __forceinline__ void store(float4* p, float4 v) {
+    *reinterpret_cast<volatile v4f*>(p) = v4f{v.x, v.y, v.z, v.w};
+  }
+  static __device__ __forceinline__ void add(float4* p, float4 v) {
+    __hip_atomic_fetch_add(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&p->z, v.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
 };
+
+// ---------------------------------------------------------------- positions
+// A 2D position is a float2; a 3D one a float4 holding (x, y, z), w unused,
+// 16-byte aligned so that one access moves the whole position.  The vector
+// helpers below act on the used coordinates only.
+template <int DIM> struct PosOf { using type = float2; };
+template <> struct PosOf<3> { using type = float4; };
+template <int DIM> using Pos = typename PosOf<DIM>::type;
+
+__device__ __forceinline__ float2 vsub(float2 a, float2 b) {
+  return make_float2(a.x - b.x, a.y - b.y);
+}
+__device__ __forceinline__ float4 vsub(float4 a, float4 b) {
+  return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, 0.f);
+}
+__device__ __forceinline__ float2 vadd(float2 a, float2 b) {
+  return make_float2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ float4 vadd(float4 a, float4 b) {
+  return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w);
+}
+__device__ __forceinline__ float vnorm2(float2 d) { return d.x * d.x + d.y * d.y; }
+__device__ __forceinline__ float vnorm2(float4 d) { return d.x * d.x + d.y * d.y + d.z * d.z; }
+// y + c * d
+__device__ __forceinline__ float2 vaxpy(float2 y, float c, float2 d) {
+  return make_float2(y.x + c * d.x, y.y + c * d.y);
+}
+__device__ __forceinline__ float4 vaxpy(float4 y, float c, float4 d) {
+  return make_float4(y.x + c * d.x, y.y + c * d.y, y.z + c * d.z, y.w);
+}
+__device__ __forceinline__ float2 vscale(float c, float2 d) { return make_float2(c * d.x, c * d.y); }
+__device__ __forceinline__ float4 vscale(float c, float4 d) {
+  return make_float4(c * d.x, c * d.y, c * d.z, 0.f);
+}
+// per-coordinate select (keeps array indices compile-time constants)
+__device__ __forceinline__ float2 vpick(bool c, float2 a, float2 b) {
+  return make_float2(c ? a.x : b.x, c ? a.y : b.y);
+}
+__device__ __forceinline__ float4 vpick(bool c, float4 a, float4 b) {
+  return make_float4(c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z, c ? a.w : b.w);
+}
+__device__ __forceinline__ bool same_bits(float2 a, float2 b) {
+  return __builtin_bit_cast(uint64_t, a) == __builtin_bit_cast(uint64_t, b);
+}
+__device__ __forceinline__ bool same_bits(float4 a, float4 b) {
+  return __float_as_uint(a.x) == __float_as_uint(b.x) &&
+         __float_as_uint(a.y) == __float_as_uint(b.y) &&
+         __float_as_uint(a.z) == __float_as_uint(b.z);
+}
+template <class P> __device__ __forceinline__ P vzero();
+template <> __device__ __forceinline__ float2 vzero<float2>() { return make_float2(0.f, 0.f); }
+template <> __device__ __forceinline__ float4 vzero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
 
 // ------------------------------------------------------------------- forces
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -137,10 +224,6 @@ __device__ __forceinline__ void draw_k(const GraphDesc& g, int64_t e, uint32_t t
   }
 }
 
-__device__ __forceinline__ bool same_bits(float2 a, float2 b) {
-  return __builtin_bit_cast(uint64_t, a) == __builtin_bit_cast(uint64_t, b);
-}
-
 // Commit of the source at the end of its run inside a chunk.  A whole row
 // (the lane owns every out-edge of i) commits the change since the run
 // started, so that updates other lanes made to y_i meanwhile (i as a
@@ -152,23 +235,22 @@ __device__ __forceinline__ bool same_bits(float2 a, float2 b) {
 //   STORE : y_i <- the lane's own value (last segment to finish wins)
 //   ATOMIC: y_i += change / segments      (the mean of the segments' moves)
 // JACOBI sums contributions into D, which is exact in every case.
-template <int MODE, class Mem>
-__device__ __forceinline__ void commit_source(float2* __restrict__ Y, float2* __restrict__ D,
-                                              int32_t i, float2 yi, float2 yi_start, float2 acc,
-                                              int32_t segments) {
+template <int MODE, class Mem, class P>
+__device__ __forceinline__ void commit_source(P* __restrict__ Y, P* __restrict__ D, int32_t i,
+                                              P yi, P yi_start, P acc, int32_t segments) {
   if constexpr (MODE == kJacobi) {
     Mem::add(D + i, acc);
   } else if constexpr (MODE == kAtomic) {
     if (same_bits(yi, yi_start)) return;
     const float w = segments > 1 ? 1.0f / static_cast<float>(segments) : 1.0f;
-    Mem::add(Y + i, make_float2(w * (yi.x - yi_start.x), w * (yi.y - yi_start.y)));
+    Mem::add(Y + i, vscale(w, vsub(yi, yi_start)));
   } else {
     if (same_bits(yi, yi_start)) return;
     if (segments > 1) {
       Mem::store(Y + i, yi);
     } else {
-      const float2 cur = Mem::load(Y + i);
-      Mem::store(Y + i, make_float2(cur.x + (yi.x - yi_start.x), cur.y + (yi.y - yi_start.y)));
+      const P cur = Mem::load(Y + i);
+      Mem::store(Y + i, vadd(cur, vsub(yi, yi_start)));
     }
   }
 }
@@ -178,9 +260,9 @@ __device__ __forceinline__ int32_t row_segments(int64_t row_begin, int64_t row_e
   return d > hub ? static_cast<int32_t>((d + hub - 1) / hub) : 1;
 }
 
-template <int K, int MODE, bool DEGREE, class Mem>
-__device__ __forceinline__ void process_chunk(const GraphDesc& g, float2* __restrict__ Y,
-                                              float2* __restrict__ D, int64_t lc, int32_t t,
+template <int K, int MODE, bool DEGREE, class Mem, class P>
+__device__ __forceinline__ void process_chunk(const GraphDesc& g, P* __restrict__ Y,
+                                              P* __restrict__ D, int64_t lc, int32_t t,
                                               float eta) {
   constexpr int KS = K > 0 ? K : 1;
   const int64_t e0 = g.chunk_begin[lc];
@@ -188,9 +270,9 @@ __device__ __forceinline__ void process_chunk(const GraphDesc& g, float2* __rest
   int32_t i = g.chunk_src[lc];
   int64_t row_end = g.row_ptr[i + 1];
   int32_t segs = row_segments(g.row_ptr[i], row_end, g.hub);
-  float2 yi = Mem::load(Y + i);
-  float2 yi_start = yi;                // value at the start of the run
-  float2 acc = make_float2(0.f, 0.f);  // JACOBI: source contributions
+  P yi = Mem::load(Y + i);
+  P yi_start = yi;       // value at the start of the run
+  P acc = vzero<P>();    // JACOBI: source contributions
   const float ca = eta * g.alpha;
 
   for (int64_t e = e0; e < e_end; ++e) {
@@ -206,91 +288,76 @@ __device__ __forceinline__ void process_chunk(const GraphDesc& g, float2* __rest
       segs = row_segments(row_begin, row_end, g.hub);
       yi = Mem::load(Y + i);
       yi_start = yi;
-      acc = make_float2(0.f, 0.f);
+      acc = vzero<P>();
     }
     const int32_t j = __builtin_nontemporal_load(g.col + e);
     uint32_t s[KS];
     draw_k<K, DEGREE>(g, e, static_cast<uint32_t>(t), static_cast<uint32_t>(i), s);
 
     // issue every gather of the edge before any arithmetic
-    float2 yj = Mem::load(Y + j);
-    float2 ys[KS];
+    P yj = Mem::load(Y + j);
+    P ys[KS];
 #pragma unroll
     for (int m = 0; m < K; ++m) ys[m] = Mem::load(Y + s[m]);
 
     if constexpr (MODE == kJacobi) {
       {
-        const float dx = yi.x - yj.x, dy = yi.y - yj.y;
-        const float c = ca * (1.0f + g.beta * fast_rcp(1.0f + dx * dx + dy * dy));
-        acc.x -= c * dx;
-        acc.y -= c * dy;
-        Mem::add(D + j, make_float2(c * dx, c * dy));
+        const P d = vsub(yi, yj);
+        const float c = ca * (1.0f + g.beta * fast_rcp(1.0f + vnorm2(d)));
+        acc = vaxpy(acc, -c, d);
+        Mem::add(D + j, vscale(c, d));
       }
 #pragma unroll
       for (int m = 0; m < K; ++m) {
-        const float dx = yi.x - ys[m].x, dy = yi.y - ys[m].y;
-        const float h = eta * rep_coef(dx * dx + dy * dy, g.gamma);
-        acc.x += h * dx;
-        acc.y += h * dy;
-        Mem::add(D + s[m], make_float2(-h * dx, -h * dy));
+        const P d = vsub(yi, ys[m]);
+        const float h = eta * rep_coef(vnorm2(d), g.gamma);
+        acc = vaxpy(acc, h, d);
+        Mem::add(D + s[m], vscale(-h, d));
       }
     } else {
       // the gathered values: ATOMIC commits differences, both policies skip
       // positions that did not change
-      const float2 yj_old = yj;
-      float2 ys_old[KS];
+      const P yj_old = yj;
+      P ys_old[KS];
 #pragma unroll
       for (int m = 0; m < K; ++m) ys_old[m] = ys[m];
       {
-        const float dx = yi.x - yj.x, dy = yi.y - yj.y;
-        const float c = ca * (1.0f + g.beta * fast_rcp(1.0f + dx * dx + dy * dy));
-        yi.x -= c * dx;
-        yi.y -= c * dy;
-        yj.x += c * dx;
-        yj.y += c * dy;
+        const P d = vsub(yi, yj);
+        const float c = ca * (1.0f + g.beta * fast_rcp(1.0f + vnorm2(d)));
+        yi = vaxpy(yi, -c, d);
+        yj = vaxpy(yj, c, d);
       }
       // Forward this lane's own newer value when a negative repeats the
-      // neighbour or an earlier negative.  Written as per-element selects so
-      // that every array index stays a compile-time constant (a data-
+      // neighbour or an earlier negative.  Written as per-coordinate selects
+      // so that every array index stays a compile-time constant (a data-
       // dependent index would put the arrays in scratch memory).
       bool dup[KS];
 #pragma unroll
       for (int m = 0; m < K; ++m) {
         const bool is_j = s[m] == static_cast<uint32_t>(j);
-        float2 cur = ys[m];
-        cur.x = is_j ? yj.x : cur.x;
-        cur.y = is_j ? yj.y : cur.y;
-        bool d = is_j;
+        P cur = vpick(is_j, yj, ys[m]);
+        bool dm = is_j;
 #pragma unroll
         for (int m2 = 0; m2 < m; ++m2) {
           const bool same = s[m2] == s[m];
-          cur.x = same ? ys[m2].x : cur.x;
-          cur.y = same ? ys[m2].y : cur.y;
-          d = d || same;
+          cur = vpick(same, ys[m2], cur);
+          dm = dm || same;
         }
-        dup[m] = d;
-        const float dx = yi.x - cur.x, dy = yi.y - cur.y;
-        const float h = eta * rep_coef(dx * dx + dy * dy, g.gamma);
-        yi.x += h * dx;
-        yi.y += h * dy;
-        cur.x -= h * dx;
-        cur.y -= h * dy;
+        dup[m] = dm;
+        const P d = vsub(yi, cur);
+        const float h = eta * rep_coef(vnorm2(d), g.gamma);
+        yi = vaxpy(yi, h, d);
+        cur = vaxpy(cur, -h, d);
         ys[m] = cur;
-        yj.x = is_j ? cur.x : yj.x;
-        yj.y = is_j ? cur.y : yj.y;
+        yj = vpick(is_j, cur, yj);
 #pragma unroll
-        for (int m2 = 0; m2 < m; ++m2) {
-          const bool same = s[m2] == s[m];
-          ys[m2].x = same ? cur.x : ys[m2].x;
-          ys[m2].y = same ? cur.y : ys[m2].y;
-        }
+        for (int m2 = 0; m2 < m; ++m2) ys[m2] = vpick(s[m2] == s[m], cur, ys[m2]);
       }
       if constexpr (MODE == kAtomic) {
-        if (!same_bits(yj, yj_old)) Mem::add(Y + j, make_float2(yj.x - yj_old.x, yj.y - yj_old.y));
+        if (!same_bits(yj, yj_old)) Mem::add(Y + j, vsub(yj, yj_old));
 #pragma unroll
         for (int m = 0; m < K; ++m)
-          if (!dup[m] && !same_bits(ys[m], ys_old[m]))
-            Mem::add(Y + s[m], make_float2(ys[m].x - ys_old[m].x, ys[m].y - ys_old[m].y));
+          if (!dup[m] && !same_bits(ys[m], ys_old[m])) Mem::add(Y + s[m], vsub(ys[m], ys_old[m]));
       } else {
         if (!same_bits(yj, yj_old)) Mem::store(Y + j, yj);
 #pragma unroll
@@ -301,6 +368,12 @@ __device__ __forceinline__ void process_chunk(const GraphDesc& g, float2* __rest
   }
   // commit the last source of the chunk
   commit_source<MODE, Mem>(Y, D, i, yi, yi_start, acc, segs);
+}
+
+// The graph's positions (and Jacobi accumulator) as 2D or 3D positions.
+template <int DIM>
+__device__ __forceinline__ Pos<DIM>* pos_of(float2* p) {
+  return reinterpret_cast<Pos<DIM>*>(p);
 }
 
 // Graph of a position inside a round (tables are short; binary search).
@@ -322,7 +395,7 @@ __device__ __forceinline__ int find_graph(const GraphDesc* __restrict__ table, i
 // positions; a round holds a slice of every graph (in proportion to its
 // chunk count), so that the lanes in flight at any moment spread over all
 // graphs as they would over each graph alone (bounded per-node concurrency).
-template <int K, int MODE, bool DEGREE, class Mem = GlobalMem>
+template <int K, int MODE, bool DEGREE, class Mem = GlobalMem, int DIM = 2>
 static __global__ void __launch_bounds__(256)
     epoch_global_kernel(const GraphDesc* __restrict__ table, int G, int64_t total_index,
                         int64_t round_size, int32_t dt) {
@@ -339,7 +412,8 @@ static __global__ void __launch_bounds__(256)
     const int64_t local = r * g.slice + (w - g.chunk_base);
     if (local >= g.n_chunks) continue;  // past this graph's last chunk
     const int32_t t = g.t0 + dt;
-    process_chunk<K, MODE, DEGREE, Mem>(g, g.Y, g.D, g.chunk_offset + local, t, eta_of(g, t));
+    process_chunk<K, MODE, DEGREE, Mem>(g, pos_of<DIM>(g.Y), pos_of<DIM>(g.D),
+                                        g.chunk_offset + local, t, eta_of(g, t));
   }
 }
 
@@ -355,7 +429,7 @@ __device__ __forceinline__ int32_t xcd_id() {
 // (XCDs x wanted workgroups) workgroups.  Each wave of the owner XCD takes
 // 64 chunks at a time from *counter (starts at 0) until the table is done, so
 // the epoch completes however workgroups are spread over the XCDs.
-template <int K, bool DEGREE>
+template <int K, bool DEGREE, int DIM = 2>
 static __global__ void __launch_bounds__(256)
     epoch_xcd_kernel(const GraphDesc* __restrict__ table, int32_t* owner, int32_t* counter,
                      int32_t dt) {
@@ -379,7 +453,8 @@ static __global__ void __launch_bounds__(256)
     if (base >= n_chunks) break;
     const int32_t c = base + lane;
     if (c < n_chunks)
-      process_chunk<K, kStore, DEGREE, XcdLocalMem>(g, g.Y, g.D, g.chunk_offset + c, t, eta);
+      process_chunk<K, kStore, DEGREE, XcdLocalMem>(g, pos_of<DIM>(g.Y), pos_of<DIM>(g.D),
+                                                    g.chunk_offset + c, t, eta);
   }
 }
 
@@ -423,7 +498,8 @@ static __global__ void __launch_bounds__(256)
       const int64_t local = r * g.slice + (w - g.chunk_base);
       if (local >= g.n_chunks) continue;  // past this graph's last chunk
       const int32_t t = g.t0 + dt;
-      process_chunk<K, kStore, DEGREE, Mem>(g, g.Y, g.D, g.chunk_offset + local, t, eta_of(g, t));
+      process_chunk<K, kStore, DEGREE, Mem>(g, g.Y, g.D, g.chunk_offset + local, t,
+                                            eta_of(g, t));
     }
   }
 }
@@ -435,13 +511,16 @@ static __global__ void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32
 
 // Whole epochs [dt, dt + count) of one small graph per workgroup, positions in
 // LDS for the duration of the launch.
-template <int K, int MODE, bool DEGREE>
+template <int K, int MODE, bool DEGREE, int DIM = 2>
 static __global__ void __launch_bounds__(1024) epoch_lds_kernel(const GraphDesc* __restrict__ table,
                                                          const int32_t* __restrict__ graph_ids,
                                                          int32_t dt, int32_t count) {
-  extern __shared__ float2 sY[];
+  using P = Pos<DIM>;
+  extern __shared__ __align__(16) unsigned char lds_bytes[];
+  P* sY = reinterpret_cast<P*>(lds_bytes);
   const GraphDesc& g = table[graph_ids[blockIdx.x]];
-  for (int32_t v = threadIdx.x; v < g.n; v += blockDim.x) sY[v] = g.Y[v];
+  P* gY = pos_of<DIM>(g.Y);
+  for (int32_t v = threadIdx.x; v < g.n; v += blockDim.x) sY[v] = gY[v];
   __syncthreads();
   // only the first `lanes` threads work, so that each graph keeps its own
   // bounded concurrency inside a shared launch
@@ -453,22 +532,19 @@ static __global__ void __launch_bounds__(1024) epoch_lds_kernel(const GraphDesc*
     const float eta = eta_of(g, t);
     if (static_cast<int32_t>(threadIdx.x) < lanes)
       for (int64_t lc = threadIdx.x; lc < g.n_chunks; lc += lanes)
-        process_chunk<K, MODE, DEGREE, LdsMem>(g, sY, nullptr, lc, t, eta);
+        process_chunk<K, MODE, DEGREE, LdsMem>(g, sY, static_cast<P*>(nullptr), lc, t, eta);
     __syncthreads();
   }
-  for (int32_t v = threadIdx.x; v < g.n; v += blockDim.x) g.Y[v] = sY[v];
+  for (int32_t v = threadIdx.x; v < g.n; v += blockDim.x) gY[v] = sY[v];
 }
 
 // Jacobi apply: Y += D, D = 0.
-static __global__ void jacobi_apply_kernel(float2* __restrict__ Y, float2* __restrict__ D, int32_t n) {
+template <class P>
+static __global__ void jacobi_apply_kernel(P* __restrict__ Y, P* __restrict__ D, int32_t n) {
   const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const float2 d = D[v];
-  float2 y = Y[v];
-  y.x += d.x;
-  y.y += d.y;
-  Y[v] = y;
-  D[v] = make_float2(0.f, 0.f);
+  Y[v] = vadd(Y[v], D[v]);
+  D[v] = vzero<P>();
 }
 
 static __global__ void fill_zero_kernel(float2* __restrict__ p, int64_t n) {
@@ -546,17 +622,18 @@ static __global__ void validate_edges_kernel(const int32_t* __restrict__ row_ptr
   if (bad) atomicOr(err, bad);
 }
 
-// Initial positions: uniform in [-s, s]^2, s = sqrtf(n) computed on the host.
-// Coordinate c of node v comes from the top 24 bits of word x_c of the block
-// (v, 0, 0, tag 1): a signed 24-bit integer times 2^-23 (exact) times s (one
-// rounding).
+// Initial positions: uniform in [-s, s]^dim, s = sqrtf(n) computed on the
+// host.  Coordinate c of node v comes from the top 24 bits of word x_c of the
+// block (v, 0, 0, tag 1): a signed 24-bit integer times 2^-23 (exact) times s
+// (one rounding).
+__device__ __forceinline__ float init_coord(uint64_t word, float scale) {
+  const int32_t a = static_cast<int32_t>(word >> 40) - (1 << 23);
+  return __fmul_rn(__fmul_rn(static_cast<float>(a), 0x1p-23f), scale);
+}
+
 __device__ __forceinline__ float2 init_coords(int32_t v, uint64_t seed, float scale) {
   const U64x4 x = philox4x64_10(static_cast<uint64_t>(v), 0, 0, kTagInit, seed, kKeyDomain);
-  const int32_t a = static_cast<int32_t>(x.x0 >> 40) - (1 << 23);
-  const int32_t b = static_cast<int32_t>(x.x1 >> 40) - (1 << 23);
-  const float ua = __fmul_rn(static_cast<float>(a), 0x1p-23f);
-  const float ub = __fmul_rn(static_cast<float>(b), 0x1p-23f);
-  return make_float2(__fmul_rn(ua, scale), __fmul_rn(ub, scale));
+  return make_float2(init_coord(x.x0, scale), init_coord(x.x1, scale));
 }
 
 static __global__ void init_positions_kernel(float2* __restrict__ Y, int32_t n, uint64_t seed,
@@ -564,6 +641,15 @@ static __global__ void init_positions_kernel(float2* __restrict__ Y, int32_t n, 
   const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   Y[v] = init_coords(v, seed, scale);
+}
+
+static __global__ void init_positions3_kernel(float4* __restrict__ Y, int32_t n, uint64_t seed,
+                                              float scale) {
+  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const U64x4 x = philox4x64_10(static_cast<uint64_t>(v), 0, 0, kTagInit, seed, kKeyDomain);
+  Y[v] = make_float4(init_coord(x.x0, scale), init_coord(x.x1, scale), init_coord(x.x2, scale),
+                     0.f);
 }
 
 // Debug: the negatives the epoch kernels draw for every edge in epoch t.

@@ -104,11 +104,18 @@ int with_degree(bool degree, F&& f) {
   return f(std::false_type{});
 }
 
+template <class F>
+int with_dim(int dim, F&& f) {
+  if (dim == 3) return f(std::integral_constant<int, 3>{});
+  return f(std::integral_constant<int, 2>{});
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ handle
 struct layout {
   int32_t n = 0, k = 0, epochs = 0, t = 0;
+  int32_t dim = 2;  // positions: float2[n] (2) or float4[n] holding x, y, z (3)
   int64_t nnz = 0;
   uint64_t seed = 0;
   layout_opts opts{};
@@ -152,6 +159,7 @@ GlobalGroup global_group_of(const layout_t* L) {
   g.block = L->block;
   g.grid = L->opts.grid_blocks;
   g.max_lanes = L->n / (L->opts.nodes_per_lane > 0 ? L->opts.nodes_per_lane : kNodesPerLane);
+  g.dim = L->dim;
   g.jacobi_Y = L->host_desc.Y;
   g.jacobi_D = L->host_desc.D;
   g.jacobi_nodes = L->n;
@@ -163,7 +171,8 @@ LdsGroup lds_group_of(const layout_t* L) {
   g.d_table = L->d_table;
   g.d_ids = L->d_graph_ids;
   g.blocks = 1;
-  g.lds_bytes = lds_bytes_for(L->n);
+  g.lds_bytes = lds_bytes_for(L->n, L->dim);
+  g.dim = L->dim;
   g.k = L->k;
   g.mode = L->mode;
   g.degree = L->opts.neg_weights != LAYOUT_NEG_UNIFORM;
@@ -191,11 +200,15 @@ int launch_xcd_epochs(layout_t* L, int32_t count) {
     constexpr int K = decltype(kc)::value;
     return with_degree(L->opts.neg_weights != LAYOUT_NEG_UNIFORM, [&](auto dc) -> int {
       constexpr bool DEG = decltype(dc)::value;
-      for (int32_t ep = 0; ep < count; ++ep) {
-        const int32_t t = L->t + ep;
-        hipLaunchKernelGGL((epoch_xcd_kernel<K, DEG>), dim3(grid), dim3(L->block), 0, L->stream,
-                           L->d_table, L->d_xcd_owner + t, L->d_xcd_counter + t, t);
-      }
+      with_dim(L->dim, [&](auto dmc) -> int {
+        constexpr int DIM = decltype(dmc)::value;
+        for (int32_t ep = 0; ep < count; ++ep) {
+          const int32_t t = L->t + ep;
+          hipLaunchKernelGGL((epoch_xcd_kernel<K, DEG, DIM>), dim3(grid), dim3(L->block), 0,
+                             L->stream, L->d_table, L->d_xcd_owner + t, L->d_xcd_counter + t, t);
+        }
+        return LAYOUT_OK;
+      });
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return hip_fail(e, "epoch_xcd_kernel launch");
       return LAYOUT_OK;
@@ -280,7 +293,7 @@ int snap::build_alias_table(hipStream_t stream, const int32_t* d_row, const uint
   return LAYOUT_OK;
 }
 
-int snap::lds_bytes_for(int32_t n) { return std::max(8, n * 8); }
+int snap::lds_bytes_for(int32_t n, int dim) { return std::max(16, n * (dim == 3 ? 16 : 8)); }
 
 int snap::global_grid(const GlobalGroup& g) {
   if (g.grid > 0) return g.grid;
@@ -440,18 +453,24 @@ int snap::launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t
       constexpr bool DEG = decltype(dc)::value;
       return with_mode(g.mode, [&](auto mc) -> int {
         constexpr int MODE = decltype(mc)::value;
-        for (int32_t ep = 0; ep < count; ++ep) {
-          const int64_t index = g.G > 1 ? g.total_index : g.total_chunks;
-          hipLaunchKernelGGL((epoch_global_kernel<K, MODE, DEG>), dim3(grid), dim3(g.block), 0,
-                             stream, g.d_table, g.G, index, g.round_size, dt + ep);
-          if constexpr (MODE == kJacobi) {
-            hipLaunchKernelGGL(jacobi_apply_kernel, dim3(div_up(g.jacobi_nodes, 256)), dim3(256),
-                               0, stream, g.jacobi_Y, g.jacobi_D, g.jacobi_nodes);
+        return with_dim(g.dim, [&](auto dmc) -> int {
+          constexpr int DIM = decltype(dmc)::value;
+          using P = Pos<DIM>;
+          for (int32_t ep = 0; ep < count; ++ep) {
+            const int64_t index = g.G > 1 ? g.total_index : g.total_chunks;
+            hipLaunchKernelGGL((epoch_global_kernel<K, MODE, DEG, GlobalMem, DIM>), dim3(grid),
+                               dim3(g.block), 0, stream, g.d_table, g.G, index, g.round_size,
+                               dt + ep);
+            if constexpr (MODE == kJacobi) {
+              hipLaunchKernelGGL(jacobi_apply_kernel<P>, dim3(div_up(g.jacobi_nodes, 256)),
+                                 dim3(256), 0, stream, reinterpret_cast<P*>(g.jacobi_Y),
+                                 reinterpret_cast<P*>(g.jacobi_D), g.jacobi_nodes);
+            }
           }
-        }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "epoch_global_kernel launch");
-        return LAYOUT_OK;
+          hipError_t e = hipGetLastError();
+          if (e != hipSuccess) return hip_fail(e, "epoch_global_kernel launch");
+          return LAYOUT_OK;
+        });
       });
     });
   });
@@ -468,30 +487,37 @@ int snap::launch_lds_epochs(hipStream_t stream, const LdsGroup& g, int32_t dt, i
         if constexpr (MODE == kJacobi) {
           return fail(LAYOUT_E_UNSUPPORTED, "LDS engine has no Jacobi mode");
         } else {
-          hipLaunchKernelGGL((epoch_lds_kernel<K, MODE, DEG>), dim3(g.blocks), dim3(g.block),
-                             g.lds_bytes, stream, g.d_table, g.d_ids, dt, count);
-          hipError_t e = hipGetLastError();
-          if (e != hipSuccess) return hip_fail(e, "epoch_lds_kernel launch");
-          return LAYOUT_OK;
+          return with_dim(g.dim, [&](auto dmc) -> int {
+            constexpr int DIM = decltype(dmc)::value;
+            hipLaunchKernelGGL((epoch_lds_kernel<K, MODE, DEG, DIM>), dim3(g.blocks),
+                               dim3(g.block), g.lds_bytes, stream, g.d_table, g.d_ids, dt, count);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return hip_fail(e, "epoch_lds_kernel launch");
+            return LAYOUT_OK;
+          });
         }
       });
     });
   });
 }
 
-int snap::allow_lds(int k, int bytes) {
+int snap::allow_lds(int k, int bytes, int dim) {
   if (bytes <= 65536) return LAYOUT_OK;
   return with_k(k, [&](auto kc) -> int {
     constexpr int K = decltype(kc)::value;
-    const void* fns[] = {reinterpret_cast<const void*>(&epoch_lds_kernel<K, kStore, false>),
-                         reinterpret_cast<const void*>(&epoch_lds_kernel<K, kAtomic, false>),
-                         reinterpret_cast<const void*>(&epoch_lds_kernel<K, kStore, true>),
-                         reinterpret_cast<const void*>(&epoch_lds_kernel<K, kAtomic, true>)};
-    for (const void* fn : fns) {
-      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-      if (e != hipSuccess) return hip_fail(e, "raising the LDS limit");
-    }
-    return LAYOUT_OK;
+    return with_dim(dim, [&](auto dmc) -> int {
+      constexpr int D = decltype(dmc)::value;
+      const void* fns[] = {
+          reinterpret_cast<const void*>(&epoch_lds_kernel<K, kStore, false, D>),
+          reinterpret_cast<const void*>(&epoch_lds_kernel<K, kAtomic, false, D>),
+          reinterpret_cast<const void*>(&epoch_lds_kernel<K, kStore, true, D>),
+          reinterpret_cast<const void*>(&epoch_lds_kernel<K, kAtomic, true, D>)};
+      for (const void* fn : fns) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return hip_fail(e, "raising the LDS limit");
+      }
+      return LAYOUT_OK;
+    });
   });
 }
 
@@ -525,11 +551,16 @@ int snap::validate_csr(hipStream_t stream, const int32_t* d_row, const int32_t* 
   return LAYOUT_OK;
 }
 
-void snap::launch_init_positions(hipStream_t stream, float2* d_Y, int32_t n, uint64_t seed) {
+void snap::launch_init_positions(hipStream_t stream, float2* d_Y, int32_t n, uint64_t seed,
+                                 int dim) {
   if (n <= 0) return;
   const float scale = std::sqrt(static_cast<float>(n));
-  hipLaunchKernelGGL(init_positions_kernel, dim3(div_up(n, 256)), dim3(256), 0, stream, d_Y, n,
-                     seed, scale);
+  if (dim == 3)
+    hipLaunchKernelGGL(init_positions3_kernel, dim3(div_up(n, 256)), dim3(256), 0, stream,
+                       reinterpret_cast<float4*>(d_Y), n, seed, scale);
+  else
+    hipLaunchKernelGGL(init_positions_kernel, dim3(div_up(n, 256)), dim3(256), 0, stream, d_Y,
+                       n, seed, scale);
 }
 
 int snap::launch_dump_draws(hipStream_t stream, int k, bool degree, const GraphDesc& g, int32_t t,
@@ -633,7 +664,7 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
   g_last_error.clear();
   if (!out) return fail(LAYOUT_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  if (dim != 2) return fail(LAYOUT_E_UNSUPPORTED, "dim = %d (only 2 is supported)", dim);
+  if (dim != 2 && dim != 3) return fail(LAYOUT_E_UNSUPPORTED, "dim = %d (2 or 3)", dim);
   if (n < 0) return fail(LAYOUT_E_INVALID_ARG, "n = %d", n);
   if (k < 0 || k > 8) return fail(k < 0 ? LAYOUT_E_INVALID_ARG : LAYOUT_E_UNSUPPORTED,
                                   "k = %d (0..8 supported)", k);
@@ -656,6 +687,8 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
   if (o.engine < 0 || o.engine > 3) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
   if (o.init_mode != LAYOUT_INIT_UNIFORM && o.init_mode != LAYOUT_INIT_PMDS)
     return fail(LAYOUT_E_INVALID_ARG, "init_mode = %d", o.init_mode);
+  if (dim == 3 && o.init_mode == LAYOUT_INIT_PMDS && !o.init_pos)
+    return fail(LAYOUT_E_UNSUPPORTED, "the Pivot MDS start is 2D");
   if (o.pmds_pivots < 0 || o.pmds_pivots > 64)
     return fail(LAYOUT_E_INVALID_ARG, "pmds_pivots = %d (1..64, 0 = default)", o.pmds_pivots);
   if (o.bundle_edges < 0 || o.block_threads < 0 || o.grid_blocks < 0 || o.hub_split_edges < 0 ||
@@ -669,6 +702,7 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
   layout_t* L = new (std::nothrow) layout_t();
   if (!L) return fail(LAYOUT_E_OOM, "host allocation");
   L->n = n;
+  L->dim = dim;
   L->k = k;
   L->epochs = epochs;
   L->t = o.start_epoch;
@@ -703,20 +737,21 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
 
   // engine and launch shape
   const DeviceProps& dp = device_props();
-  const bool lds_fits = lds_bytes_for(n) <= dp.lds_per_block;
+  const int64_t pos_bytes = dim == 3 ? 16 : 8;  // one position
+  const bool lds_fits = lds_bytes_for(n, dim) <= dp.lds_per_block;
   if (o.engine == LAYOUT_ENGINE_LDS) {
     if (!lds_fits)
       return bail(fail(LAYOUT_E_UNSUPPORTED, "LDS engine: %d nodes need %d B of LDS (> %d)", n,
-                       lds_bytes_for(n), dp.lds_per_block));
+                       lds_bytes_for(n, dim), dp.lds_per_block));
     if (o.update_mode == LAYOUT_JACOBI)
       return bail(fail(LAYOUT_E_UNSUPPORTED, "LDS engine has no Jacobi mode"));
     L->engine = LAYOUT_ENGINE_LDS;
   } else if (o.engine == LAYOUT_ENGINE_GLOBAL) {
     L->engine = LAYOUT_ENGINE_GLOBAL;
   } else if (o.engine == LAYOUT_ENGINE_XCD) {
-    if (int64_t(n) * 8 > kXcdMaxPositionBytes)
+    if (int64_t(n) * pos_bytes > kXcdMaxPositionBytes)
       return bail(fail(LAYOUT_E_UNSUPPORTED, "XCD-local engine: %d nodes need %lld B (> %lld)", n,
-                       (long long)n * 8, (long long)kXcdMaxPositionBytes));
+                       (long long)(n * pos_bytes), (long long)kXcdMaxPositionBytes));
     if (o.update_mode != LAYOUT_UPDATE_AUTO && o.update_mode != LAYOUT_HOGWILD_STORE)
       return bail(fail(LAYOUT_E_UNSUPPORTED, "XCD-local engine runs HOGWILD_STORE only"));
     L->engine = LAYOUT_ENGINE_XCD;
@@ -724,7 +759,7 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
     const bool store_ok = o.update_mode == LAYOUT_UPDATE_AUTO || o.update_mode == LAYOUT_HOGWILD_STORE;
     if (lds_fits && L->nnz <= kLdsAutoMaxEdges && o.update_mode != LAYOUT_JACOBI)
       L->engine = LAYOUT_ENGINE_LDS;
-    else if (store_ok && int64_t(n) * 8 <= kXcdMaxPositionBytes)
+    else if (store_ok && int64_t(n) * pos_bytes <= kXcdMaxPositionBytes)
       L->engine = LAYOUT_ENGINE_XCD;
     else
       L->engine = LAYOUT_ENGINE_GLOBAL;
@@ -766,13 +801,13 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
       (rc = alloc(L, reinterpret_cast<void**>(&d_col), sizeof(int32_t) * size_t(L->nnz), "col")) ||
       (rc = alloc(L, reinterpret_cast<void**>(&d_chunk), sizeof(int32_t) * size_t(chunk_cap), "chunk src")) ||
       (rc = alloc(L, reinterpret_cast<void**>(&d_chunk_begin), sizeof(int32_t) * size_t(chunk_cap + 1), "chunk begin")) ||
-      (rc = alloc(L, reinterpret_cast<void**>(&d_Y), sizeof(float2) * size_t(n), "positions")) ||
+      (rc = alloc(L, reinterpret_cast<void**>(&d_Y), size_t(pos_bytes) * size_t(n), "positions")) ||
       (rc = alloc(L, reinterpret_cast<void**>(&d_err), sizeof(uint32_t), "flag")) ||
       (rc = alloc(L, reinterpret_cast<void**>(&L->d_table), sizeof(GraphDesc), "table")) ||
       (rc = alloc(L, reinterpret_cast<void**>(&L->d_graph_ids), sizeof(int32_t), "ids")))
     return bail(rc);
   if (L->mode == LAYOUT_JACOBI &&
-      (rc = alloc(L, reinterpret_cast<void**>(&d_D), sizeof(float2) * size_t(n), "jacobi delta")))
+      (rc = alloc(L, reinterpret_cast<void**>(&d_D), size_t(pos_bytes) * size_t(n), "jacobi delta")))
     return bail(rc);
 
   const hipMemcpyKind kind = inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -825,7 +860,13 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
 
   // initial positions
   if (n > 0) {
-    if (o.init_pos) {
+    if (o.init_pos && dim == 3) {
+      // n x 3 rows into 16-byte positions (w = 0)
+      e = hipMemsetAsync(d_Y, 0, size_t(pos_bytes) * size_t(n), L->stream);
+      if (e == hipSuccess)
+        e = hipMemcpy2DAsync(d_Y, 16, o.init_pos, 12, 12, size_t(n), kind, L->stream);
+      if (e != hipSuccess) return bail(hip_fail(e, "copying init_pos"));
+    } else if (o.init_pos) {
       e = hipMemcpyAsync(d_Y, o.init_pos, sizeof(float2) * size_t(n), kind, L->stream);
       if (e != hipSuccess) return bail(hip_fail(e, "copying init_pos"));
     } else if (o.init_mode == LAYOUT_INIT_PMDS) {
@@ -834,10 +875,10 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
                                nullptr, nullptr, nullptr)) != LAYOUT_OK)
         return bail(rc);
     } else {
-      launch_init_positions(L->stream, d_Y, n, seed);
+      launch_init_positions(L->stream, d_Y, n, seed, dim);
     }
   }
-  if (d_D) launch_fill_zero(L->stream, d_D, n);
+  if (d_D) launch_fill_zero(L->stream, d_D, int64_t(n) * (pos_bytes / 8));
   if (L->engine == LAYOUT_ENGINE_XCD) {
     const size_t b = sizeof(int32_t) * size_t(epochs);
     if ((rc = alloc(L, reinterpret_cast<void**>(&L->d_xcd_owner), b, "epoch owners")) ||
@@ -877,7 +918,8 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
     e = hipMemcpyAsync(L->d_graph_ids, &zero, sizeof zero, hipMemcpyHostToDevice, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   if (e != hipSuccess) return bail(hip_fail(e, "finishing create"));
-  if (L->engine == LAYOUT_ENGINE_LDS && (rc = allow_lds(k, lds_bytes_for(n))) != LAYOUT_OK)
+  if (L->engine == LAYOUT_ENGINE_LDS &&
+      (rc = allow_lds(k, lds_bytes_for(n, dim), dim)) != LAYOUT_OK)
     return bail(rc);
   *out = L;
   return LAYOUT_OK;
@@ -927,8 +969,11 @@ int layout_get_positions(const layout_t* L, float* host_out) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (!host_out) return fail(LAYOUT_E_INVALID_ARG, "host_out is NULL");
   if (L->n == 0) return LAYOUT_OK;
-  hipError_t e = hipMemcpyAsync(host_out, L->host_desc.Y, sizeof(float2) * size_t(L->n),
-                                hipMemcpyDeviceToHost, L->stream);
+  hipError_t e = L->dim == 3
+                     ? hipMemcpy2DAsync(host_out, 12, L->host_desc.Y, 16, 12, size_t(L->n),
+                                        hipMemcpyDeviceToHost, L->stream)
+                     : hipMemcpyAsync(host_out, L->host_desc.Y, sizeof(float2) * size_t(L->n),
+                                      hipMemcpyDeviceToHost, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   if (e != hipSuccess) return hip_fail(e, "reading positions");
   return LAYOUT_OK;
@@ -949,8 +994,10 @@ int layout_get_positions_device(const layout_t* L, float* dev_out, void* stream)
     (void)hipEventDestroy(ev);
   }
   if (e == hipSuccess)
-    e = hipMemcpyAsync(dev_out, L->host_desc.Y, sizeof(float2) * size_t(L->n),
-                       hipMemcpyDeviceToDevice, s);
+    e = L->dim == 3 ? hipMemcpy2DAsync(dev_out, 12, L->host_desc.Y, 16, 12, size_t(L->n),
+                                       hipMemcpyDeviceToDevice, s)
+                    : hipMemcpyAsync(dev_out, L->host_desc.Y, sizeof(float2) * size_t(L->n),
+                                     hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "copying positions");
   return LAYOUT_OK;
 }
@@ -959,8 +1006,11 @@ int layout_set_positions(layout_t* L, const float* host_in) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (!host_in) return fail(LAYOUT_E_INVALID_ARG, "host_in is NULL");
   if (L->n == 0) return LAYOUT_OK;
-  hipError_t e = hipMemcpyAsync(L->host_desc.Y, host_in, sizeof(float2) * size_t(L->n),
-                                hipMemcpyHostToDevice, L->stream);
+  hipError_t e = L->dim == 3
+                     ? hipMemcpy2DAsync(L->host_desc.Y, 16, host_in, 12, 12, size_t(L->n),
+                                        hipMemcpyHostToDevice, L->stream)
+                     : hipMemcpyAsync(L->host_desc.Y, host_in, sizeof(float2) * size_t(L->n),
+                                      hipMemcpyHostToDevice, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   if (e != hipSuccess) return hip_fail(e, "writing positions");
   return LAYOUT_OK;
@@ -991,6 +1041,7 @@ void layout_destroy(layout_t* L) {
 
 int layout_sampled_energy(layout_t* L, int32_t epoch, double* attr_out, double* rep_out) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (L->dim != 2) return fail(LAYOUT_E_UNSUPPORTED, "energy monitors are 2D");
   if (!attr_out || !rep_out) return fail(LAYOUT_E_INVALID_ARG, "NULL output");
   if (epoch < 0) return fail(LAYOUT_E_INVALID_ARG, "epoch = %d", epoch);
   int rc = energy_buffer(L);
@@ -1009,6 +1060,7 @@ int layout_sampled_energy(layout_t* L, int32_t epoch, double* attr_out, double* 
 
 int layout_effective_energy(layout_t* L, double* attr_out, double* rep_out) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (L->dim != 2) return fail(LAYOUT_E_UNSUPPORTED, "energy monitors are 2D");
   if (!attr_out || !rep_out) return fail(LAYOUT_E_INVALID_ARG, "NULL output");
   int rc = energy_buffer(L);
   if (rc != LAYOUT_OK) return rc;
@@ -1036,6 +1088,7 @@ int layout_effective_energy(layout_t* L, double* attr_out, double* rep_out) {
 
 int layout_silhouette(layout_t* L, const int32_t* labels, double* si_out) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (L->dim != 2) return fail(LAYOUT_E_UNSUPPORTED, "the silhouette monitor is 2D");
   if (!labels || !si_out) return fail(LAYOUT_E_INVALID_ARG, "NULL labels or si_out");
   const int32_t n = L->n;
   if (n < 2) return fail(LAYOUT_E_INVALID_ARG, "silhouette needs at least 2 nodes");
@@ -1102,6 +1155,7 @@ int layout_silhouette(layout_t* L, const int32_t* labels, double* si_out) {
 int layout_neighbourhood(layout_t* L, const int32_t* nodes, int32_t count, int32_t radius,
                          int32_t* k_out, int32_t* inter_out, double* np_out) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (L->dim != 2) return fail(LAYOUT_E_UNSUPPORTED, "the NP monitor is 2D");
   if (count < 0) return fail(LAYOUT_E_INVALID_ARG, "count < 0");
   if (radius != 1 && radius != 2) return fail(LAYOUT_E_INVALID_ARG, "radius must be 1 or 2");
   if (count > 0 && (!nodes || !k_out || !inter_out))
@@ -1241,6 +1295,7 @@ int layout_debug_alias(const layout_t* L, uint32_t* thr_out, uint32_t* alias_out
 
 int layout_bench_gather(layout_t* L, int32_t mode, int32_t reps, float* ms) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (L->dim != 2) return fail(LAYOUT_E_UNSUPPORTED, "the gather roofline is 2D");
   if (!ms || reps < 1) return fail(LAYOUT_E_INVALID_ARG, "ms NULL or reps < 1");
   if (mode != kStore && mode != kAtomic) return fail(LAYOUT_E_INVALID_ARG, "mode %d", mode);
   if (L->nnz == 0) {

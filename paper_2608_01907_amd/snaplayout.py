@@ -243,8 +243,8 @@ def layout_epoch_timed(h, count):
     return ms.value
 
 
-def layout_get_positions(h, n):
-    out = np.zeros((n, 2), dtype=np.float32)
+def layout_get_positions(h, n, dim=2):
+    out = np.zeros((n, dim), dtype=np.float32)
     _check(lib().layout_get_positions(h, out.ctypes.data))
     return out
 
@@ -522,7 +522,7 @@ class Layout:
                  alpha=0.1, beta=8.0, gamma=2.0, init_pos=None, bundle_edges=0,
                  block_threads=0, grid_blocks=0, start_epoch=0, stream=None,
                  hub_split_edges=0, nodes_per_lane=0, init_mode=LAYOUT_INIT_UNIFORM,
-                 pmds_pivots=0, neg_weight_values=None):
+                 pmds_pivots=0, neg_weight_values=None, dim=2):
         o = layout_opts_init()
         o.init_mode, o.pmds_pivots = init_mode, pmds_pivots
         w_keep = None
@@ -548,10 +548,10 @@ class Layout:
                 o.init_pos = init_keep.ctypes.data
         if stream is not None:
             o.stream = stream
-        self.n, self.k, self.epochs = int(n), int(k), int(epochs)
+        self.n, self.k, self.epochs, self.dim = int(n), int(k), int(epochs), int(dim)
         self.nnz = int(row_ptr[-1]) if not on_device else int(row_ptr[-1].item())
-        self.h = layout_create_ex(row_ptr, col_idx, self.n, 2, self.k, self.epochs, seed, o,
-                                  int(on_device))
+        self.h = layout_create_ex(row_ptr, col_idx, self.n, self.dim, self.k, self.epochs, seed,
+                                  o, int(on_device))
         del init_keep, w_keep
 
     def run(self, count=None):
@@ -562,7 +562,7 @@ class Layout:
         return layout_epoch_timed(self.h, self.epochs if count is None else count)
 
     def positions(self):
-        return layout_get_positions(self.h, self.n)
+        return layout_get_positions(self.h, self.n, self.dim)
 
     def set_positions(self, Y):
         layout_set_positions(self.h, Y)

@@ -210,7 +210,7 @@ def test_rejects_bad_arguments():
     rp, col = S.csr_from_pairs(np.array([0]), np.array([1]), 2)
     h = SL.layout_create(rp, col, 2, 2, 5, 3, 0)
     SL.layout_destroy(h)
-    for args, code in [((rp, col, 2, 3, 5, 3, 0), SL.LAYOUT_E_UNSUPPORTED),
+    for args, code in [((rp, col, 2, 4, 5, 3, 0), SL.LAYOUT_E_UNSUPPORTED),
                        ((rp, col, 2, 2, 9, 3, 0), SL.LAYOUT_E_UNSUPPORTED),
                        ((rp, col, 2, 2, -1, 3, 0), SL.LAYOUT_E_INVALID_ARG),
                        ((rp, col, 2, 2, 5, 0, 0), SL.LAYOUT_E_INVALID_ARG)]:
