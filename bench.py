@@ -58,16 +58,18 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(row_ptr: np.ndarray, n: int, k: int, hub: int, n_chunks: int) -> int:
+def algorithmic_bytes(row_ptr: np.ndarray, n: int, k: int, hub: int, n_chunks: int,
+                      dim: int = 2) -> int:
     """Bytes one epoch must move at minimum: per directed edge the col entry
-    (4 B) and (1 + k) position read-modify-writes (16 B each); per source run
-    (a row, or one segment of a row split above `hub` edges) the source read
-    and commit (16 B); per chunk its table entries (8 B); the row pointers
-    (4 B per row)."""
+    (4 B) and (1 + k) position read-modify-writes (2 x 8 B in 2D, 2 x 16 B for
+    the 16-byte 3D positions); per source run (a row, or one segment of a row
+    split above `hub` edges) the source read and commit (same); per chunk its
+    table entries (8 B); the row pointers (4 B per row)."""
     nnz = int(row_ptr[-1])
+    rmw = 16 if dim == 2 else 32
     deg = np.diff(row_ptr.astype(np.int64))
     runs = int(np.where(deg > hub, (deg + hub - 1) // hub, (deg > 0).astype(np.int64)).sum())
-    return int(nnz * (4 + 16 * (1 + k)) + 16 * runs + 8 * n_chunks + 4 * (n + 1))
+    return int(nnz * (4 + rmw * (1 + k)) + rmw * runs + 8 * n_chunks + 4 * (n + 1))
 
 
 def committed_traffic(workload: str):
@@ -129,7 +131,8 @@ def bench_plain(args):
         f"dmax={int(np.diff(g.row_ptr).max())} ({time.perf_counter() - t0:.1f}s)")
     mode = {"auto": SL.LAYOUT_UPDATE_AUTO, "atomic": SL.LAYOUT_ATOMIC,
             "store": SL.LAYOUT_HOGWILD_STORE}[args.mode]
-    out_d = torch.empty((g.n, 2), dtype=torch.float32, device=dev)
+    dim = args.dim
+    out_d = torch.empty((g.n, dim), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
 
     def opts():
@@ -140,7 +143,7 @@ def bench_plain(args):
         return o
 
     if args.profile_epochs:
-        h = SL.layout_create_ex(rp_d, col_d, g.n, 2, k, T, seed, opts(), 1)
+        h = SL.layout_create_ex(rp_d, col_d, g.n, dim, k, T, seed, opts(), 1)
         SL.layout_epoch(h, args.profile_epochs)
         SL.layout_sync(h)
         SL.layout_destroy(h)
@@ -148,7 +151,7 @@ def bench_plain(args):
         return None
 
     def step():
-        h = SL.layout_create_ex(rp_d, col_d, g.n, 2, k, T, seed, opts(), 1)
+        h = SL.layout_create_ex(rp_d, col_d, g.n, dim, k, T, seed, opts(), 1)
         SL.layout_epoch(h, T)
         SL.layout_get_positions_device(h, out_d)
         SL.layout_sync(h)
@@ -167,17 +170,17 @@ def bench_plain(args):
     log(f"[bench] {args.steps} steps, {ms_step:.2f} ms/step")
 
     # dominant kernel: the epoch kernel, timed with HIP events on its stream
-    h = SL.layout_create_ex(rp_d, col_d, g.n, 2, k, T, seed, opts(), 1)
+    h = SL.layout_create_ex(rp_d, col_d, g.n, dim, k, T, seed, opts(), 1)
     info = SL.layout_get_info(h)
     ms_epoch = SL.layout_epoch_timed(h, T) / T
-    Y = SL.layout_get_positions(h, g.n)
+    Y = SL.layout_get_positions(h, g.n, dim)
     finite = bool(np.all(np.isfinite(Y)))
     SL.layout_destroy(h)
-    nbytes = algorithmic_bytes(g.row_ptr, g.n, k, info["hub_split_edges"], info["n_chunks"])
+    nbytes = algorithmic_bytes(g.row_ptr, g.n, k, info["hub_split_edges"], info["n_chunks"], dim)
     achieved = nbytes / (ms_epoch * 1e-3) / 1e9
     policy = {0: "store", 1: "atomic", 2: "jacobi"}[info["update_mode"]]
     gather = {}
-    if info["engine"] == SL.LAYOUT_ENGINE_GLOBAL:
+    if info["engine"] == SL.LAYOUT_ENGINE_GLOBAL and dim == 2:
         h = SL.layout_create_ex(rp_d, col_d, g.n, 2, k, T, seed, opts(), 1)
         for name, m in (("store", SL.LAYOUT_HOGWILD_STORE), ("atomic", SL.LAYOUT_ATOMIC)):
             SL.layout_bench_gather(h, m, 2)
@@ -187,7 +190,7 @@ def bench_plain(args):
     copy_gbs = 2 * (1 << 30) / (copy_ms * 1e-3) / 1e9
     log(f"[bench] epoch {ms_epoch:.3f} ms, {achieved:.1f} GB/s algorithmic, gather {gather}, "
         f"copy {copy_gbs:.0f} GB/s")
-    traffic, tinfo = committed_traffic(args.workload)
+    traffic, tinfo = committed_traffic(args.workload) if dim == 2 else (None, None)
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": (f"epoch_global_kernel<{k},{policy}>" if info["engine"] == 1
@@ -203,6 +206,8 @@ def bench_plain(args):
     cpu = None
     if not args.no_cpu and maker.startswith("gpu:"):
         log("[bench] no CPU baseline for a device-generated workload (headline workload only)")
+    elif not args.no_cpu and dim != 2:
+        log("[bench] the CPU oracle baseline is timed on the 2D workload only")
     elif not args.no_cpu:
         log("[bench] timing the CPU oracle baseline")
         cpu = cpu_baseline(g, k, T, seed)
@@ -213,7 +218,7 @@ def bench_plain(args):
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": g.name, "n": g.n, "edges": n_edges, "k": k, "epochs": T,
-                   "update_mode": policy, "engine": info["engine"],
+                   "dim": dim, "update_mode": policy, "engine": info["engine"],
                    "bundle_edges": info["bundle_edges"],
                    "hub_split_edges": info["hub_split_edges"],
                    "grid_blocks": info["grid_blocks"]},
@@ -426,6 +431,8 @@ def main():
     ap.add_argument("--workload", default="lj-like-4m",
                     choices=sorted(PLAIN) + ["batched-512", "served"])
     ap.add_argument("--mode", default="auto", choices=["auto", "atomic", "store"])
+    ap.add_argument("--dim", type=int, default=2, choices=[2, 3],
+                    help="layout dimension of the plain workloads (the paper's layouts are 2D)")
     ap.add_argument("--bundle", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")

@@ -56,6 +56,7 @@
 namespace snap {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 // --------------------------------------------------------------- memory ops
 // Global positions: device-scope relaxed accesses, so that every lane reads
@@ -75,22 +76,43 @@ struct GlobalMem {
     __hip_atomic_fetch_add(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_fetch_add(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  // 3D: one 16-byte access with system-scope cache bits (coherent across
-  // XCDs like the 8-byte accesses above; a random 16-byte access costs the
-  // memory system the same request as an 8-byte one, while splitting it into
-  // 8 + 4 bytes would take two)
-  static __device__ __forceinline__ float4 load(const float4* p) {
-    const v4f v = *reinterpret_cast<const volatile v4f*>(p);
-    return make_float4(v.x, v.y, v.z, v.w);
-  }
-  static __device__ __forceinline__ void store(float4* p, float4 v) {
-    *reinterpret_cast<volatile v4f*>(p) = v4f{v.x, v.y, v.z, v.w};
-  }
   static __device__ __forceinline__ void add(float4* p, float4 v) {
     __hip_atomic_fetch_add(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_fetch_add(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_fetch_add(&p->z, v.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+};
+
+// 3D positions of one graph on all CUs: 16-byte buffer accesses with the
+// device-scope cache bit, the coherence of the 8-byte agent-scope atomics
+// above.  A random 16-byte access costs the memory system one request, as an
+// 8-byte one does (8 + 4 bytes would take two).  The buffer form keeps the
+// loads of an edge in flight together; a C++ volatile access has the same
+// cache bits but makes the compiler wait for each load before the next.
+// Positions are addressed by 32-bit byte offsets: n < 2^28.
+struct GlobalMem3 {
+  static constexpr int kDeviceScope = 16;          // cache-policy bit sc1
+  static constexpr int kRawDwords = 0x00020000;    // descriptor word 3: raw 32-bit data
+  __amdgpu_buffer_rsrc_t rsrc;
+  const char* base;
+  __device__ __forceinline__ GlobalMem3(const float4* Y, int32_t n)
+      : rsrc(__builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float4*>(Y), static_cast<short>(0),
+            static_cast<int>(static_cast<uint32_t>(n) * 16u), kRawDwords)),
+        base(reinterpret_cast<const char*>(Y)) {}
+  __device__ __forceinline__ uint32_t offset(const float4* p) const {
+    return static_cast<uint32_t>(reinterpret_cast<const char*>(p) - base);
+  }
+  __device__ __forceinline__ float4 load(const float4* p) const {
+    const v4f v = __builtin_bit_cast(
+        v4f, __builtin_amdgcn_raw_buffer_load_b128(rsrc, offset(p), 0, kDeviceScope));
+    return make_float4(v.x, v.y, v.z, v.w);
+  }
+  __device__ __forceinline__ void store(float4* p, float4 v) const {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, v4f{v.x, v.y, v.z, v.w}),
+                                           rsrc, offset(p), 0, kDeviceScope);
+  }
+  __device__ __forceinline__ void add(float4* p, float4 v) const { GlobalMem::add(p, v); }
 };
 
 // Positions touched by the CUs of one XCD only (the XCD-local engine): plain
@@ -122,13 +144,9 @@ struct LdsMem {
     __hip_atomic_fetch_add(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __hip_atomic_fetch_add(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
-  static __device__ __forceinline__ float4 load(const float4* p) {
-    const v4f v = *reinterpret_cast<const volatile v4f*>(p);
-    return make_float4(v.x, v.y, v.z, v.w);
-  }
-  static __device__ __forceinline__ void store(float4* p, float4 v) {
-    *reinterpret_cast<volatile v4f*>(p) = v4f{v.x, v.y, v.z, v.w};
-  }
+  // 3D: one 16-byte LDS access (LDS is coherent within the workgroup)
+  static __device__ __forceinline__ float4 load(const float4* p) { return *p; }
+  static __device__ __forceinline__ void store(float4* p, float4 v) { *p = v; }
   static __device__ __forceinline__ void add(float4* p, float4 v) {
     __hip_atomic_fetch_add(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __hip_atomic_fetch_add(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -236,21 +254,22 @@ __device__ __forceinline__ void draw_k(const GraphDesc& g, int64_t e, uint32_t t
 //   ATOMIC: y_i += change / segments      (the mean of the segments' moves)
 // JACOBI sums contributions into D, which is exact in every case.
 template <int MODE, class Mem, class P>
-__device__ __forceinline__ void commit_source(P* __restrict__ Y, P* __restrict__ D, int32_t i,
-                                              P yi, P yi_start, P acc, int32_t segments) {
+__device__ __forceinline__ void commit_source(const Mem& mem, P* __restrict__ Y,
+                                              P* __restrict__ D, int32_t i, P yi, P yi_start,
+                                              P acc, int32_t segments) {
   if constexpr (MODE == kJacobi) {
-    Mem::add(D + i, acc);
+    mem.add(D + i, acc);
   } else if constexpr (MODE == kAtomic) {
     if (same_bits(yi, yi_start)) return;
     const float w = segments > 1 ? 1.0f / static_cast<float>(segments) : 1.0f;
-    Mem::add(Y + i, vscale(w, vsub(yi, yi_start)));
+    mem.add(Y + i, vscale(w, vsub(yi, yi_start)));
   } else {
     if (same_bits(yi, yi_start)) return;
     if (segments > 1) {
-      Mem::store(Y + i, yi);
+      mem.store(Y + i, yi);
     } else {
-      const P cur = Mem::load(Y + i);
-      Mem::store(Y + i, vadd(cur, vsub(yi, yi_start)));
+      const P cur = mem.load(Y + i);
+      mem.store(Y + i, vadd(cur, vsub(yi, yi_start)));
     }
   }
 }
@@ -260,17 +279,19 @@ __device__ __forceinline__ int32_t row_segments(int64_t row_begin, int64_t row_e
   return d > hub ? static_cast<int32_t>((d + hub - 1) / hub) : 1;
 }
 
+// mem: the memory operations (load, store, add on positions); the stateless
+// kinds are passed as empty objects.
 template <int K, int MODE, bool DEGREE, class Mem, class P>
-__device__ __forceinline__ void process_chunk(const GraphDesc& g, P* __restrict__ Y,
-                                              P* __restrict__ D, int64_t lc, int32_t t,
-                                              float eta) {
+__device__ __forceinline__ void process_chunk(const Mem& mem, const GraphDesc& g,
+                                              P* __restrict__ Y, P* __restrict__ D, int64_t lc,
+                                              int32_t t, float eta) {
   constexpr int KS = K > 0 ? K : 1;
   const int64_t e0 = g.chunk_begin[lc];
   const int64_t e_end = g.chunk_begin[lc + 1];
   int32_t i = g.chunk_src[lc];
   int64_t row_end = g.row_ptr[i + 1];
   int32_t segs = row_segments(g.row_ptr[i], row_end, g.hub);
-  P yi = Mem::load(Y + i);
+  P yi = mem.load(Y + i);
   P yi_start = yi;       // value at the start of the run
   P acc = vzero<P>();    // JACOBI: source contributions
   const float ca = eta * g.alpha;
@@ -278,7 +299,7 @@ __device__ __forceinline__ void process_chunk(const GraphDesc& g, P* __restrict_
   for (int64_t e = e0; e < e_end; ++e) {
     if (e >= row_end) {
       // the row is finished: commit the source, move to the next non-empty row
-      commit_source<MODE, Mem>(Y, D, i, yi, yi_start, acc, segs);
+      commit_source<MODE>(mem, Y, D, i, yi, yi_start, acc, segs);
       int64_t row_begin;
       do {
         ++i;
@@ -286,7 +307,7 @@ __device__ __forceinline__ void process_chunk(const GraphDesc& g, P* __restrict_
         row_end = g.row_ptr[i + 1];
       } while (e >= row_end);
       segs = row_segments(row_begin, row_end, g.hub);
-      yi = Mem::load(Y + i);
+      yi = mem.load(Y + i);
       yi_start = yi;
       acc = vzero<P>();
     }
@@ -295,24 +316,24 @@ __device__ __forceinline__ void process_chunk(const GraphDesc& g, P* __restrict_
     draw_k<K, DEGREE>(g, e, static_cast<uint32_t>(t), static_cast<uint32_t>(i), s);
 
     // issue every gather of the edge before any arithmetic
-    P yj = Mem::load(Y + j);
+    P yj = mem.load(Y + j);
     P ys[KS];
 #pragma unroll
-    for (int m = 0; m < K; ++m) ys[m] = Mem::load(Y + s[m]);
+    for (int m = 0; m < K; ++m) ys[m] = mem.load(Y + s[m]);
 
     if constexpr (MODE == kJacobi) {
       {
         const P d = vsub(yi, yj);
         const float c = ca * (1.0f + g.beta * fast_rcp(1.0f + vnorm2(d)));
         acc = vaxpy(acc, -c, d);
-        Mem::add(D + j, vscale(c, d));
+        mem.add(D + j, vscale(c, d));
       }
 #pragma unroll
       for (int m = 0; m < K; ++m) {
         const P d = vsub(yi, ys[m]);
         const float h = eta * rep_coef(vnorm2(d), g.gamma);
         acc = vaxpy(acc, h, d);
-        Mem::add(D + s[m], vscale(-h, d));
+        mem.add(D + s[m], vscale(-h, d));
       }
     } else {
       // the gathered values: ATOMIC commits differences, both policies skip
@@ -354,20 +375,20 @@ __device__ __forceinline__ void process_chunk(const GraphDesc& g, P* __restrict_
         for (int m2 = 0; m2 < m; ++m2) ys[m2] = vpick(s[m2] == s[m], cur, ys[m2]);
       }
       if constexpr (MODE == kAtomic) {
-        if (!same_bits(yj, yj_old)) Mem::add(Y + j, vsub(yj, yj_old));
+        if (!same_bits(yj, yj_old)) mem.add(Y + j, vsub(yj, yj_old));
 #pragma unroll
         for (int m = 0; m < K; ++m)
-          if (!dup[m] && !same_bits(ys[m], ys_old[m])) Mem::add(Y + s[m], vsub(ys[m], ys_old[m]));
+          if (!dup[m] && !same_bits(ys[m], ys_old[m])) mem.add(Y + s[m], vsub(ys[m], ys_old[m]));
       } else {
-        if (!same_bits(yj, yj_old)) Mem::store(Y + j, yj);
+        if (!same_bits(yj, yj_old)) mem.store(Y + j, yj);
 #pragma unroll
         for (int m = 0; m < K; ++m)
-          if (!dup[m] && !same_bits(ys[m], ys_old[m])) Mem::store(Y + s[m], ys[m]);
+          if (!dup[m] && !same_bits(ys[m], ys_old[m])) mem.store(Y + s[m], ys[m]);
       }
     }
   }
   // commit the last source of the chunk
-  commit_source<MODE, Mem>(Y, D, i, yi, yi_start, acc, segs);
+  commit_source<MODE>(mem, Y, D, i, yi, yi_start, acc, segs);
 }
 
 // The graph's positions (and Jacobi accumulator) as 2D or 3D positions.
@@ -395,25 +416,38 @@ __device__ __forceinline__ int find_graph(const GraphDesc* __restrict__ table, i
 // positions; a round holds a slice of every graph (in proportion to its
 // chunk count), so that the lanes in flight at any moment spread over all
 // graphs as they would over each graph alone (bounded per-node concurrency).
+// 3D layouts run one graph per launch (G = 1), whose position base then is
+// uniform and addresses the buffer accesses of GlobalMem3.
 template <int K, int MODE, bool DEGREE, class Mem = GlobalMem, int DIM = 2>
 static __global__ void __launch_bounds__(256)
     epoch_global_kernel(const GraphDesc* __restrict__ table, int G, int64_t total_index,
                         int64_t round_size, int32_t dt) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < total_index;
-       c += stride) {
-    int64_t r = 0, w = c;
-    if (G > 1) {
-      r = c / round_size;
-      w = c - r * round_size;
-    }
-    const int gi = G == 1 ? 0 : find_graph(table, G, w);
-    const GraphDesc& g = table[gi];
-    const int64_t local = r * g.slice + (w - g.chunk_base);
-    if (local >= g.n_chunks) continue;  // past this graph's last chunk
+  if constexpr (DIM == 3) {
+    const GraphDesc& g = table[0];
+    const GlobalMem3 mem(pos_of<3>(g.Y), g.n);
     const int32_t t = g.t0 + dt;
-    process_chunk<K, MODE, DEGREE, Mem>(g, pos_of<DIM>(g.Y), pos_of<DIM>(g.D),
-                                        g.chunk_offset + local, t, eta_of(g, t));
+    const float eta = eta_of(g, t);
+    for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+         c < g.n_chunks; c += stride)
+      process_chunk<K, MODE, DEGREE>(mem, g, pos_of<3>(g.Y), pos_of<3>(g.D), g.chunk_offset + c,
+                                     t, eta);
+  } else {
+    for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+         c < total_index; c += stride) {
+      int64_t r = 0, w = c;
+      if (G > 1) {
+        r = c / round_size;
+        w = c - r * round_size;
+      }
+      const int gi = G == 1 ? 0 : find_graph(table, G, w);
+      const GraphDesc& g = table[gi];
+      const int64_t local = r * g.slice + (w - g.chunk_base);
+      if (local >= g.n_chunks) continue;  // past this graph's last chunk
+      const int32_t t = g.t0 + dt;
+      process_chunk<K, MODE, DEGREE>(Mem{}, g, pos_of<DIM>(g.Y), pos_of<DIM>(g.D),
+                                     g.chunk_offset + local, t, eta_of(g, t));
+    }
   }
 }
 
@@ -453,8 +487,8 @@ static __global__ void __launch_bounds__(256)
     if (base >= n_chunks) break;
     const int32_t c = base + lane;
     if (c < n_chunks)
-      process_chunk<K, kStore, DEGREE, XcdLocalMem>(g, pos_of<DIM>(g.Y), pos_of<DIM>(g.D),
-                                                    g.chunk_offset + c, t, eta);
+      process_chunk<K, kStore, DEGREE>(XcdLocalMem{}, g, pos_of<DIM>(g.Y), pos_of<DIM>(g.D),
+                                       g.chunk_offset + c, t, eta);
   }
 }
 
@@ -498,8 +532,8 @@ static __global__ void __launch_bounds__(256)
       const int64_t local = r * g.slice + (w - g.chunk_base);
       if (local >= g.n_chunks) continue;  // past this graph's last chunk
       const int32_t t = g.t0 + dt;
-      process_chunk<K, kStore, DEGREE, Mem>(g, g.Y, g.D, g.chunk_offset + local, t,
-                                            eta_of(g, t));
+      process_chunk<K, kStore, DEGREE>(Mem{}, g, g.Y, g.D, g.chunk_offset + local, t,
+                                       eta_of(g, t));
     }
   }
 }
@@ -532,7 +566,7 @@ static __global__ void __launch_bounds__(1024) epoch_lds_kernel(const GraphDesc*
     const float eta = eta_of(g, t);
     if (static_cast<int32_t>(threadIdx.x) < lanes)
       for (int64_t lc = threadIdx.x; lc < g.n_chunks; lc += lanes)
-        process_chunk<K, MODE, DEGREE, LdsMem>(g, sY, static_cast<P*>(nullptr), lc, t, eta);
+        process_chunk<K, MODE, DEGREE>(LdsMem{}, g, sY, static_cast<P*>(nullptr), lc, t, eta);
     __syncthreads();
   }
   for (int32_t v = threadIdx.x; v < g.n; v += blockDim.x) gY[v] = sY[v];

@@ -453,6 +453,8 @@ int snap::launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t
       constexpr bool DEG = decltype(dc)::value;
       return with_mode(g.mode, [&](auto mc) -> int {
         constexpr int MODE = decltype(mc)::value;
+        if (g.dim == 3 && g.G != 1)
+          return fail(LAYOUT_E_UNSUPPORTED, "3D layouts run one graph per launch");
         return with_dim(g.dim, [&](auto dmc) -> int {
           constexpr int DIM = decltype(dmc)::value;
           using P = Pos<DIM>;
@@ -687,6 +689,8 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
   if (o.engine < 0 || o.engine > 3) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
   if (o.init_mode != LAYOUT_INIT_UNIFORM && o.init_mode != LAYOUT_INIT_PMDS)
     return fail(LAYOUT_E_INVALID_ARG, "init_mode = %d", o.init_mode);
+  if (dim == 3 && int64_t(n) * 16 > int64_t(0xFFFFFFFF))
+    return fail(LAYOUT_E_UNSUPPORTED, "3D layouts address positions by 32-bit offsets: n < 2^28");
   if (dim == 3 && o.init_mode == LAYOUT_INIT_PMDS && !o.init_pos)
     return fail(LAYOUT_E_UNSUPPORTED, "the Pivot MDS start is 2D");
   if (o.pmds_pivots < 0 || o.pmds_pivots > 64)
