@@ -57,62 +57,90 @@ namespace snap {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
 // --------------------------------------------------------------- memory ops
+// Pointers to device memory in the global address space: accesses through
+// them are global_* instructions, which count against the vector-memory
+// counter only (a generic pointer gives flat_* instructions, which the
+// compiler must also wait for on the LDS counter).
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gptr(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
 // Global positions: device-scope relaxed accesses, so that every lane reads
 // the value last committed at device level (no stale per-CU L1 copy), 64-bit
 // for a position pair.
 struct GlobalMem {
   static __device__ __forceinline__ float2 load(const float2* p) {
-    const uint64_t b = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t b = __hip_atomic_load(gptr(reinterpret_cast<const uint64_t*>(p)),
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return __builtin_bit_cast(float2, b);
   }
   static __device__ __forceinline__ void store(float2* p, float2 v) {
-    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), __builtin_bit_cast(uint64_t, v),
+    __hip_atomic_store(gptr(reinterpret_cast<uint64_t*>(p)), __builtin_bit_cast(uint64_t, v),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   static __device__ __forceinline__ void add(float2* p, float2 v) {
-    __hip_atomic_fetch_add(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(gptr(&p->x), v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(gptr(&p->y), v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   static __device__ __forceinline__ void add(float4* p, float4 v) {
-    __hip_atomic_fetch_add(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&p->z, v.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(gptr(&p->x), v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(gptr(&p->y), v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(gptr(&p->z), v.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 };
 
-// 3D positions of one graph on all CUs: 16-byte buffer accesses with the
-// device-scope cache bit, the coherence of the 8-byte agent-scope atomics
-// above.  A random 16-byte access costs the memory system one request, as an
-// 8-byte one does (8 + 4 bytes would take two).  The buffer form keeps the
-// loads of an edge in flight together; a C++ volatile access has the same
-// cache bits but makes the compiler wait for each load before the next.
-// Positions are addressed by 32-bit byte offsets: n < 2^28.
-struct GlobalMem3 {
-  static constexpr int kDeviceScope = 16;          // cache-policy bit sc1
-  static constexpr int kRawDwords = 0x00020000;    // descriptor word 3: raw 32-bit data
+// Positions of one graph on all CUs, addressed through a buffer descriptor:
+// 8-byte (2D) or 16-byte (3D) accesses with the device-scope cache bit, the
+// coherence of GlobalMem's agent-scope atomics.  The descriptor takes the
+// graph's position base in scalar registers and each access a 32-bit byte
+// offset, which saves the 64-bit address arithmetic of every gather and
+// scatter; a random 16-byte access costs the memory system one request, as
+// an 8-byte one does (8 + 4 bytes would take two).  (A C++ volatile access
+// has the same cache bits, but the compiler then waits for each load before
+// issuing the next.)  Needs n * sizeof(P) < 2^32.
+template <class P>
+struct BufferMem {
+  static constexpr int kDeviceScope = 16;        // cache-policy bit sc1
+  static constexpr int kRawDwords = 0x00020000;  // descriptor word 3: raw 32-bit data
   __amdgpu_buffer_rsrc_t rsrc;
   const char* base;
-  __device__ __forceinline__ GlobalMem3(const float4* Y, int32_t n)
+  __device__ __forceinline__ BufferMem(const P* Y, int32_t n)
       : rsrc(__builtin_amdgcn_make_buffer_rsrc(
-            const_cast<float4*>(Y), static_cast<short>(0),
-            static_cast<int>(static_cast<uint32_t>(n) * 16u), kRawDwords)),
+            const_cast<P*>(Y), static_cast<short>(0),
+            static_cast<int>(static_cast<uint32_t>(n) * static_cast<uint32_t>(sizeof(P))),
+            kRawDwords)),
         base(reinterpret_cast<const char*>(Y)) {}
-  __device__ __forceinline__ uint32_t offset(const float4* p) const {
+  __device__ __forceinline__ uint32_t offset(const P* p) const {
     return static_cast<uint32_t>(reinterpret_cast<const char*>(p) - base);
   }
-  __device__ __forceinline__ float4 load(const float4* p) const {
-    const v4f v = __builtin_bit_cast(
-        v4f, __builtin_amdgcn_raw_buffer_load_b128(rsrc, offset(p), 0, kDeviceScope));
-    return make_float4(v.x, v.y, v.z, v.w);
+  __device__ __forceinline__ P load(const P* p) const {
+    if constexpr (sizeof(P) == 8) {
+      return __builtin_bit_cast(
+          P, __builtin_amdgcn_raw_buffer_load_b64(rsrc, offset(p), 0, kDeviceScope));
+    } else {
+      const v4f v = __builtin_bit_cast(
+          v4f, __builtin_amdgcn_raw_buffer_load_b128(rsrc, offset(p), 0, kDeviceScope));
+      return make_float4(v.x, v.y, v.z, v.w);
+    }
   }
-  __device__ __forceinline__ void store(float4* p, float4 v) const {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, v4f{v.x, v.y, v.z, v.w}),
-                                           rsrc, offset(p), 0, kDeviceScope);
+  __device__ __forceinline__ void store(P* p, P v) const {
+    if constexpr (sizeof(P) == 8) {
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), rsrc, offset(p), 0,
+                                            kDeviceScope);
+    } else {
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, v4f{v.x, v.y, v.z, v.w}),
+                                             rsrc, offset(p), 0, kDeviceScope);
+    }
   }
-  __device__ __forceinline__ void add(float4* p, float4 v) const { GlobalMem::add(p, v); }
+  __device__ __forceinline__ void add(P* p, P v) const { GlobalMem::add(p, v); }
 };
 
 // Positions touched by the CUs of one XCD only (the XCD-local engine): plain
@@ -121,11 +149,20 @@ struct GlobalMem3 {
 // line's short L1 lifetime, which is one more stale read of the lock-free
 // scheme.  HOGWILD_STORE only.
 struct XcdLocalMem {
-  static __device__ __forceinline__ float2 load(const float2* p) { return *p; }
-  static __device__ __forceinline__ void store(float2* p, float2 v) { *p = v; }
+  static __device__ __forceinline__ float2 load(const float2* p) {
+    return __builtin_bit_cast(float2, *gptr(reinterpret_cast<const uint64_t*>(p)));
+  }
+  static __device__ __forceinline__ void store(float2* p, float2 v) {
+    *gptr(reinterpret_cast<uint64_t*>(p)) = __builtin_bit_cast(uint64_t, v);
+  }
   static __device__ __forceinline__ void add(float2* p, float2 v) { GlobalMem::add(p, v); }
-  static __device__ __forceinline__ float4 load(const float4* p) { return *p; }
-  static __device__ __forceinline__ void store(float4* p, float4 v) { *p = v; }
+  static __device__ __forceinline__ float4 load(const float4* p) {
+    const v4f v = *gptr(reinterpret_cast<const v4f*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+  }
+  static __device__ __forceinline__ void store(float4* p, float4 v) {
+    *gptr(reinterpret_cast<v4f*>(p)) = v4f{v.x, v.y, v.z, v.w};
+  }
   static __device__ __forceinline__ void add(float4* p, float4 v) { GlobalMem::add(p, v); }
 };
 
@@ -286,11 +323,11 @@ __device__ __forceinline__ void process_chunk(const Mem& mem, const GraphDesc& g
                                               P* __restrict__ Y, P* __restrict__ D, int64_t lc,
                                               int32_t t, float eta) {
   constexpr int KS = K > 0 ? K : 1;
-  const int64_t e0 = g.chunk_begin[lc];
-  const int64_t e_end = g.chunk_begin[lc + 1];
-  int32_t i = g.chunk_src[lc];
-  int64_t row_end = g.row_ptr[i + 1];
-  int32_t segs = row_segments(g.row_ptr[i], row_end, g.hub);
+  const int64_t e0 = *gptr(g.chunk_begin + lc);
+  const int64_t e_end = *gptr(g.chunk_begin + lc + 1);
+  int32_t i = *gptr(g.chunk_src + lc);
+  int64_t row_end = *gptr(g.row_ptr + i + 1);
+  int32_t segs = row_segments(*gptr(g.row_ptr + i), row_end, g.hub);
   P yi = mem.load(Y + i);
   P yi_start = yi;       // value at the start of the run
   P acc = vzero<P>();    // JACOBI: source contributions
@@ -304,14 +341,14 @@ __device__ __forceinline__ void process_chunk(const Mem& mem, const GraphDesc& g
       do {
         ++i;
         row_begin = row_end;
-        row_end = g.row_ptr[i + 1];
+        row_end = *gptr(g.row_ptr + i + 1);
       } while (e >= row_end);
       segs = row_segments(row_begin, row_end, g.hub);
       yi = mem.load(Y + i);
       yi_start = yi;
       acc = vzero<P>();
     }
-    const int32_t j = __builtin_nontemporal_load(g.col + e);
+    const int32_t j = __builtin_nontemporal_load(gptr(g.col + e));
     uint32_t s[KS];
     draw_k<K, DEGREE>(g, e, static_cast<uint32_t>(t), static_cast<uint32_t>(i), s);
 
@@ -416,25 +453,28 @@ __device__ __forceinline__ int find_graph(const GraphDesc* __restrict__ table, i
 // positions; a round holds a slice of every graph (in proportion to its
 // chunk count), so that the lanes in flight at any moment spread over all
 // graphs as they would over each graph alone (bounded per-node concurrency).
-// 3D layouts run one graph per launch (G = 1), whose position base then is
-// uniform and addresses the buffer accesses of GlobalMem3.
+// A single graph (G = 1) has a uniform position base, which its accesses use
+// through BufferMem when n * sizeof(position) < 2^32; 3D layouts always run
+// one graph per launch.
 template <int K, int MODE, bool DEGREE, class Mem = GlobalMem, int DIM = 2>
 static __global__ void __launch_bounds__(256)
     epoch_global_kernel(const GraphDesc* __restrict__ table, int G, int64_t total_index,
                         int64_t round_size, int32_t dt) {
+  using P = Pos<DIM>;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  if constexpr (DIM == 3) {
+  const int64_t first = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (DIM == 3 || (G == 1 && int64_t(table[0].n) * int64_t(sizeof(P)) < (int64_t(1) << 32))) {
     const GraphDesc& g = table[0];
-    const GlobalMem3 mem(pos_of<3>(g.Y), g.n);
+    const BufferMem<P> mem(pos_of<DIM>(g.Y), g.n);
     const int32_t t = g.t0 + dt;
     const float eta = eta_of(g, t);
-    for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-         c < g.n_chunks; c += stride)
-      process_chunk<K, MODE, DEGREE>(mem, g, pos_of<3>(g.Y), pos_of<3>(g.D), g.chunk_offset + c,
-                                     t, eta);
-  } else {
-    for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-         c < total_index; c += stride) {
+    for (int64_t c = first; c < g.n_chunks; c += stride)
+      process_chunk<K, MODE, DEGREE>(mem, g, pos_of<DIM>(g.Y), pos_of<DIM>(g.D),
+                                     g.chunk_offset + c, t, eta);
+    return;
+  }
+  if constexpr (DIM == 2) {
+    for (int64_t c = first; c < total_index; c += stride) {
       int64_t r = 0, w = c;
       if (G > 1) {
         r = c / round_size;
@@ -445,8 +485,8 @@ static __global__ void __launch_bounds__(256)
       const int64_t local = r * g.slice + (w - g.chunk_base);
       if (local >= g.n_chunks) continue;  // past this graph's last chunk
       const int32_t t = g.t0 + dt;
-      process_chunk<K, MODE, DEGREE>(Mem{}, g, pos_of<DIM>(g.Y), pos_of<DIM>(g.D),
-                                     g.chunk_offset + local, t, eta_of(g, t));
+      process_chunk<K, MODE, DEGREE>(Mem{}, g, g.Y, g.D, g.chunk_offset + local, t,
+                                     eta_of(g, t));
     }
   }
 }
