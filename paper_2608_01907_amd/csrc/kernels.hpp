@@ -105,10 +105,11 @@ struct GlobalMem {
 // scatter; a random 16-byte access costs the memory system one request, as
 // an 8-byte one does (8 + 4 bytes would take two).  (A C++ volatile access
 // has the same cache bits, but the compiler then waits for each load before
-// issuing the next.)  Needs n * sizeof(P) < 2^32.
-template <class P>
+// issuing the next.)  Needs n * sizeof(P) < 2^32.  AUX = 0 gives plain
+// (L2-coherent) accesses, for the XCD-local engine.
+template <class P, int AUX = 16>
 struct BufferMem {
-  static constexpr int kDeviceScope = 16;        // cache-policy bit sc1
+  static constexpr int kCachePolicy = AUX;       // cache-policy bits (16: sc1)
   static constexpr int kRawDwords = 0x00020000;  // descriptor word 3: raw 32-bit data
   __amdgpu_buffer_rsrc_t rsrc;
   const char* base;
@@ -124,20 +125,20 @@ struct BufferMem {
   __device__ __forceinline__ P load(const P* p) const {
     if constexpr (sizeof(P) == 8) {
       return __builtin_bit_cast(
-          P, __builtin_amdgcn_raw_buffer_load_b64(rsrc, offset(p), 0, kDeviceScope));
+          P, __builtin_amdgcn_raw_buffer_load_b64(rsrc, offset(p), 0, kCachePolicy));
     } else {
       const v4f v = __builtin_bit_cast(
-          v4f, __builtin_amdgcn_raw_buffer_load_b128(rsrc, offset(p), 0, kDeviceScope));
+          v4f, __builtin_amdgcn_raw_buffer_load_b128(rsrc, offset(p), 0, kCachePolicy));
       return make_float4(v.x, v.y, v.z, v.w);
     }
   }
   __device__ __forceinline__ void store(P* p, P v) const {
     if constexpr (sizeof(P) == 8) {
       __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), rsrc, offset(p), 0,
-                                            kDeviceScope);
+                                            kCachePolicy);
     } else {
       __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, v4f{v.x, v.y, v.z, v.w}),
-                                             rsrc, offset(p), 0, kDeviceScope);
+                                             rsrc, offset(p), 0, kCachePolicy);
     }
   }
   __device__ __forceinline__ void add(P* p, P v) const { GlobalMem::add(p, v); }
@@ -516,6 +517,8 @@ static __global__ void __launch_bounds__(256)
   __syncthreads();
   if (!mine) return;
   const GraphDesc& g = table[0];
+  // plain accesses through a buffer descriptor (positions <= 3 MiB here)
+  const BufferMem<Pos<DIM>, 0> mem(pos_of<DIM>(g.Y), g.n);
   const int32_t t = g.t0 + dt;
   const float eta = eta_of(g, t);
   const int lane = static_cast<int>(threadIdx.x & 63);
@@ -527,7 +530,7 @@ static __global__ void __launch_bounds__(256)
     if (base >= n_chunks) break;
     const int32_t c = base + lane;
     if (c < n_chunks)
-      process_chunk<K, kStore, DEGREE>(XcdLocalMem{}, g, pos_of<DIM>(g.Y), pos_of<DIM>(g.D),
+      process_chunk<K, kStore, DEGREE>(mem, g, pos_of<DIM>(g.Y), pos_of<DIM>(g.D),
                                        g.chunk_offset + c, t, eta);
   }
 }
@@ -765,45 +768,55 @@ static __global__ void copy_kernel(const float4* __restrict__ src, float4* __res
 // The memory pattern of an epoch without the force arithmetic or the
 // generator: per directed edge one read-modify-write at col[e] and k at
 // hashed uniform nodes, plus the source per chunk (random-gather roofline).
+template <int K, int MODE, class M>
+__device__ __forceinline__ void gather_rmw_chunk(const M& mem, const GraphDesc& g, int64_t c) {
+  const int64_t e0 = *gptr(g.chunk_begin + c);
+  const int64_t e_end = *gptr(g.chunk_begin + c + 1);
+  int32_t i = *gptr(g.chunk_src + c);
+  float2 yi = mem.load(g.Y + i);
+  for (int64_t e = e0; e < e_end; ++e) {
+    const int32_t j = __builtin_nontemporal_load(gptr(g.col + e));
+    uint32_t s[K > 0 ? K : 1];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      uint32_t h = static_cast<uint32_t>(e) * 0x9E3779B1u + static_cast<uint32_t>(m) * 0x85EBCA77u;
+      h ^= h >> 15;
+      h *= 0x2C1B3C6Du;
+      h ^= h >> 12;
+      s[m] = static_cast<uint32_t>((static_cast<uint64_t>(h) * g.sc.n) >> 32);
+    }
+    float2 yj = mem.load(g.Y + j);
+    float2 ys[K > 0 ? K : 1];
+#pragma unroll
+    for (int m = 0; m < K; ++m) ys[m] = mem.load(g.Y + s[m]);
+    yi.x += 1e-7f * yj.x;
+    if constexpr (MODE == kAtomic) {
+      mem.add(g.Y + j, make_float2(1e-7f * yj.y, 0.f));
+#pragma unroll
+      for (int m = 0; m < K; ++m) mem.add(g.Y + s[m], make_float2(1e-7f * ys[m].y, 0.f));
+    } else {
+      mem.store(g.Y + j, make_float2(yj.x + 1e-7f * yj.y, yj.y));
+#pragma unroll
+      for (int m = 0; m < K; ++m)
+        mem.store(g.Y + s[m], make_float2(ys[m].x + 1e-7f * ys[m].y, ys[m].y));
+    }
+  }
+  mem.store(g.Y + i, yi);
+}
+
+// Same memory path as the single-graph epoch: BufferMem when the positions
+// fit 32-bit offsets, else Mem.
 template <int K, int MODE, class Mem>
 static __global__ void __launch_bounds__(256) gather_rmw_kernel(const GraphDesc* __restrict__ table,
                                                          int64_t total_chunks) {
   const GraphDesc& g = table[0];
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < total_chunks;
-       c += stride) {
-    const int64_t e0 = g.chunk_begin[c];
-    const int64_t e_end = g.chunk_begin[c + 1];
-    int32_t i = g.chunk_src[c];
-    float2 yi = Mem::load(g.Y + i);
-    for (int64_t e = e0; e < e_end; ++e) {
-      const int32_t j = __builtin_nontemporal_load(g.col + e);
-      uint32_t s[K > 0 ? K : 1];
-#pragma unroll
-      for (int m = 0; m < K; ++m) {
-        uint32_t h = static_cast<uint32_t>(e) * 0x9E3779B1u + static_cast<uint32_t>(m) * 0x85EBCA77u;
-        h ^= h >> 15;
-        h *= 0x2C1B3C6Du;
-        h ^= h >> 12;
-        s[m] = static_cast<uint32_t>((static_cast<uint64_t>(h) * g.sc.n) >> 32);
-      }
-      float2 yj = Mem::load(g.Y + j);
-      float2 ys[K > 0 ? K : 1];
-#pragma unroll
-      for (int m = 0; m < K; ++m) ys[m] = Mem::load(g.Y + s[m]);
-      yi.x += 1e-7f * yj.x;
-      if constexpr (MODE == kAtomic) {
-        Mem::add(g.Y + j, make_float2(1e-7f * yj.y, 0.f));
-#pragma unroll
-        for (int m = 0; m < K; ++m) Mem::add(g.Y + s[m], make_float2(1e-7f * ys[m].y, 0.f));
-      } else {
-        Mem::store(g.Y + j, make_float2(yj.x + 1e-7f * yj.y, yj.y));
-#pragma unroll
-        for (int m = 0; m < K; ++m)
-          Mem::store(g.Y + s[m], make_float2(ys[m].x + 1e-7f * ys[m].y, ys[m].y));
-      }
-    }
-    Mem::store(g.Y + i, yi);
+  const int64_t first = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (int64_t(g.n) * 8 < (int64_t(1) << 32)) {
+    const BufferMem<float2> mem(g.Y, g.n);
+    for (int64_t c = first; c < total_chunks; c += stride) gather_rmw_chunk<K, MODE>(mem, g, c);
+  } else {
+    for (int64_t c = first; c < total_chunks; c += stride) gather_rmw_chunk<K, MODE>(Mem{}, g, c);
   }
 }
 
