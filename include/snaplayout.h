@@ -313,7 +313,12 @@ typedef struct layout_graph {
     int32_t n;
     int32_t reserved;
     uint64_t seed;          /* keys this graph's draws */
-    const float *init_pos;  /* n*2 or NULL (seeded uniform init) */
+    const float *init_pos;  /* n*2 or NULL (opts->init_mode: seeded uniform or
+                               Pivot MDS) */
+    const uint32_t *neg_weight_values; /* n negative weights (host, or device when
+                               inputs_on_device) when opts->neg_weights is
+                               LAYOUT_NEG_CUSTOM (each graph: 0 < sum < 2^32),
+                               else NULL */
 } layout_graph;
 
 typedef struct layout_batch layout_batch_t;
@@ -330,7 +335,9 @@ typedef struct layout_batch_info {
 
 /* Creates a batch of count graphs (validated like layout_create).  opts as for
  * layout_create_ex; init_pos and start_epoch are ignored (per-graph init_pos
- * lives in layout_graph).  Graphs that fit LDS run whole in one workgroup
+ * and caller weights live in layout_graph).  init_mode LAYOUT_INIT_PMDS runs
+ * the Pivot MDS start of every graph without init_pos at create, one graph
+ * after another.  Graphs that fit LDS run whole in one workgroup
  * each; with engine AUTO the others run on XCD-local bins when all of them
  * fit one XCD's L2 (HOGWILD_STORE, automatic launch shape),
  * else in one all-CU launch per epoch; engine GLOBAL forces that launch for
@@ -399,7 +406,8 @@ enum {
     LAYOUT_JOB_QUEUED = 0,
     LAYOUT_JOB_RUNNING = 1,
     LAYOUT_JOB_DONE = 2,
-    LAYOUT_JOB_FAILED = 3
+    LAYOUT_JOB_FAILED = 3,
+    LAYOUT_JOB_CANCELLED = 4
 };
 
 typedef struct layout_server_stats {
@@ -410,6 +418,7 @@ typedef struct layout_server_stats {
     double edge_updates;   /* sum over completed jobs of |E| (1 + k) epochs */
     double busy_seconds;   /* wall time with at least one job admitted */
     double p50_latency_s, p99_latency_s, mean_latency_s; /* over completed jobs */
+    int64_t cancelled;
 } layout_server_stats;
 
 /* Starts a server.  hbm_budget_bytes: cap on the summed device footprint of
@@ -431,10 +440,28 @@ int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t ro
 int layout_server_submit(layout_server_t *S, const int32_t *row_ptr, const int32_t *col_idx,
                          int32_t n, int32_t k, int32_t epochs, uint64_t seed, int64_t *job_id);
 
+/* As layout_server_submit, with per-job inputs (host arrays, copied before
+ * returning).  neg_weight_values: n weights, required exactly when the
+ * server's opts->neg_weights is LAYOUT_NEG_CUSTOM (0 < sum < 2^32), else
+ * NULL; otherwise LAYOUT_E_INVALID_ARG.  init_pos: n*2 initial positions or
+ * NULL (the server's init_mode: seeded uniform, or Pivot MDS computed at
+ * admission, which holds the scheduler for that job's PMDS time). */
+int layout_server_submit_ex(layout_server_t *S, const int32_t *row_ptr, const int32_t *col_idx,
+                            int32_t n, int32_t k, int32_t epochs, uint64_t seed,
+                            const uint32_t *neg_weight_values, const float *init_pos,
+                            int64_t *job_id);
+
+/* Cancels a job.  A queued job ends at once; a running one is retired after
+ * the round in flight, its device memory freed.  Its state becomes
+ * LAYOUT_JOB_CANCELLED; layout_server_wait then returns LAYOUT_E_INVALID_ARG
+ * and layout_server_take forgets it.  A job that has already ended (or an
+ * unknown id): LAYOUT_E_INVALID_ARG.  Thread-safe. */
+int layout_server_cancel(layout_server_t *S, int64_t job_id);
+
 /* Current state (LAYOUT_JOB_*) of a job.  Thread-safe. */
 int layout_server_poll(layout_server_t *S, int64_t job_id, int32_t *state);
 
-/* Waits until the job is DONE or FAILED or timeout_s passes (< 0: no limit);
+/* Waits until the job is DONE, FAILED or CANCELLED, or timeout_s passes (< 0: no limit);
  * returns LAYOUT_OK when it is DONE, LAYOUT_E_DEVICE/BAD_GRAPH for a failed
  * job (message in layout_last_error), LAYOUT_E_INVALID_ARG on timeout. */
 int layout_server_wait(layout_server_t *S, int64_t job_id, double timeout_s);

@@ -289,17 +289,24 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
     layout_opts_init(&o);
   if (o.update_mode < 0 || o.update_mode > 3)
     return fail(LAYOUT_E_INVALID_ARG, "update_mode = %d", o.update_mode);
-  if (o.neg_weights == LAYOUT_NEG_CUSTOM)
-    return fail(LAYOUT_E_UNSUPPORTED, "per-node negative weights: single-graph layouts only");
-  if (o.neg_weights != LAYOUT_NEG_UNIFORM && o.neg_weights != LAYOUT_NEG_DEGREE)
+  if (o.neg_weights != LAYOUT_NEG_UNIFORM && o.neg_weights != LAYOUT_NEG_DEGREE &&
+      o.neg_weights != LAYOUT_NEG_CUSTOM)
     return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
+  for (int32_t g = 0; g < count; ++g) {
+    const bool has_w = graphs[g].neg_weight_values != nullptr;
+    if (has_w != (o.neg_weights == LAYOUT_NEG_CUSTOM && graphs[g].n > 0))
+      return fail(LAYOUT_E_INVALID_ARG,
+                  "graph %d: neg_weight_values must be given exactly with LAYOUT_NEG_CUSTOM", g);
+  }
   if (o.engine < 0 || o.engine > 3) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
   if (o.bundle_edges < 0 || o.block_threads < 0 || o.grid_blocks < 0 || o.hub_split_edges < 0 ||
       o.nodes_per_lane < 0 || o.block_threads > 1024 || (o.block_threads % 64) != 0)
     return fail(LAYOUT_E_INVALID_ARG, "bad launch option");
   if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g (must be > 1)", o.gamma);
-  if (o.init_mode != LAYOUT_INIT_UNIFORM)
-    return fail(LAYOUT_E_UNSUPPORTED, "init_mode = %d (only the seeded uniform init here)", o.init_mode);
+  if (o.init_mode != LAYOUT_INIT_UNIFORM && o.init_mode != LAYOUT_INIT_PMDS)
+    return fail(LAYOUT_E_INVALID_ARG, "init_mode = %d", o.init_mode);
+  if (o.pmds_pivots < 0 || o.pmds_pivots > 64)
+    return fail(LAYOUT_E_INVALID_ARG, "pmds_pivots = %d (1..64, 0 = default)", o.pmds_pivots);
 
   layout_batch_t* B = new (std::nothrow) layout_batch_t();
   if (!B) return fail(LAYOUT_E_OOM, "host allocation");
@@ -431,7 +438,8 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
     return bail(rc);
   if (jacobi && (rc = balloc(B, reinterpret_cast<void**>(&B->d_D), sizeof(float2) * size_t(B->nodes), "delta")))
     return bail(rc);
-  const bool degree = o.neg_weights == LAYOUT_NEG_DEGREE;
+  // weighted negatives (degrees or the caller's weights): one alias table per graph
+  const bool degree = o.neg_weights != LAYOUT_NEG_UNIFORM;
   if (degree &&
       ((rc = balloc(B, reinterpret_cast<void**>(&B->d_thr), sizeof(uint32_t) * size_t(B->nodes), "alias thr")) ||
        (rc = balloc(B, reinterpret_cast<void**>(&B->d_alias), sizeof(uint32_t) * size_t(B->nodes), "alias"))))
@@ -483,13 +491,28 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
     if (degree && B->nnz[g] > 0) {
       d.thr = B->d_thr + B->node_off[g];
       d.alias = B->d_alias + B->node_off[g];
-      if ((rc = build_alias_table(B->stream, row, nullptr, gr.n, B->nnz[g], const_cast<uint32_t*>(d.thr),
-                                  const_cast<uint32_t*>(d.alias))) != LAYOUT_OK)
+      if (o.neg_weights == LAYOUT_NEG_CUSTOM) {
+        if ((rc = upload_weights_and_build_alias(B->stream, row, gr.neg_weight_values, gr.n,
+                                                 inputs_on_device != 0,
+                                                 const_cast<uint32_t*>(d.thr),
+                                                 const_cast<uint32_t*>(d.alias))) != LAYOUT_OK) {
+          std::string m = g_last_error;
+          return bail(fail(rc, "graph %d: %s", g, m.c_str()));
+        }
+      } else if ((rc = build_alias_table(B->stream, row, nullptr, gr.n, B->nnz[g],
+                                         const_cast<uint32_t*>(d.thr),
+                                         const_cast<uint32_t*>(d.alias))) != LAYOUT_OK) {
         return bail(rc);
+      }
     }
     if (gr.init_pos) {
       e = hipMemcpyAsync(Y, gr.init_pos, sizeof(float2) * size_t(gr.n), kind, B->stream);
       if (e != hipSuccess) return bail(hip_fail(e, "copying init_pos"));
+    } else if (o.init_mode == LAYOUT_INIT_PMDS && gr.n > 0) {
+      if ((rc = pmds_positions(B->stream, row, col, gr.n,
+                               o.pmds_pivots ? o.pmds_pivots : kDefaultPivots, gr.seed, Y,
+                               nullptr, nullptr, nullptr)) != LAYOUT_OK)
+        return bail(rc);
     } else {
       launch_init_positions(B->stream, Y, gr.n, gr.seed);
     }
@@ -617,7 +640,7 @@ int layout_batch_debug_draws(const layout_batch_t* B, int32_t g, int32_t epoch, 
   int32_t* d_out = nullptr;
   hipError_t e = hipMalloc(&d_out, bytes);
   if (e != hipSuccess) return hip_fail(e, "debug draws buffer");
-  int rc = launch_dump_draws(B->stream, B->k, B->opts.neg_weights == LAYOUT_NEG_DEGREE, B->desc[g],
+  int rc = launch_dump_draws(B->stream, B->k, B->opts.neg_weights != LAYOUT_NEG_UNIFORM, B->desc[g],
                              epoch, d_out);
   if (rc == LAYOUT_OK) {
     e = hipMemcpyAsync(host_out, d_out, bytes, hipMemcpyDeviceToHost, B->stream);

@@ -59,6 +59,12 @@ int build_chunk_table(hipStream_t stream, const int32_t* d_row, int32_t n, int64
 // d_row), W = their sum, 0 < W < 2^32.
 int build_alias_table(hipStream_t stream, const int32_t* d_row, const uint32_t* d_weights,
                       int32_t n, int64_t W, uint32_t* d_thr, uint32_t* d_alias);
+// The alias table of caller weights (host, or device when on_device; n
+// entries whose sum W must satisfy 0 < W < 2^32, else LAYOUT_E_INVALID_ARG).
+// Synchronises the stream.
+int upload_weights_and_build_alias(hipStream_t stream, const int32_t* d_row,
+                                   const uint32_t* weights, int32_t n, bool on_device,
+                                   uint32_t* d_thr, uint32_t* d_alias);
 // Device validation of one CSR (LAYOUT_E_BAD_GRAPH with a message on failure);
 // err is a device word of scratch.
 int validate_csr(hipStream_t stream, const int32_t* d_row, const int32_t* d_col, int32_t n,

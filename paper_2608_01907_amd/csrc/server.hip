@@ -6,16 +6,18 @@
 // scheduler
 //   1. admits queued jobs in arrival order while a slot is free and the job's
 //      device footprint fits the budget (device copy, validation, chunk
-//      table, seeded init);
+//      table, alias table of weighted negatives, initial positions: the
+//      caller's, seeded uniform or Pivot MDS);
 //   2. launches, on two streams, the LDS engine for newly admitted small jobs
 //      (all their epochs) and one multi-graph launch of the global engine
 //      that advances every other job by a slice of its current epoch (the
 //      slices share the round's edge budget);
 //   3. waits, advances epoch counters, and retires finished jobs (positions to
-//      host, device memory freed, latency recorded).
+//      host, device memory freed, latency recorded) and cancelled ones.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -41,6 +43,7 @@ double now_s() {
 }
 
 constexpr int64_t kDefaultRoundEdges = 32ll << 20;
+constexpr int kCancelled = 1;  // finish_job code of a cancelled job (not an error)
 constexpr int64_t kMinSliceEdges = 1ll << 18;
 
 struct Job {
@@ -49,7 +52,10 @@ struct Job {
   uint64_t seed = 0;
   int64_t nnz = 0;
   std::vector<int32_t> row, col;  // host copy, dropped once on the device
+  std::vector<uint32_t> weights;  // caller's negative weights (LAYOUT_NEG_CUSTOM)
+  std::vector<float> init;        // caller's initial positions (n*2) or empty
   std::vector<float> result;
+  std::atomic<bool> cancel{false};  // set by layout_server_cancel while running
   int state = LAYOUT_JOB_QUEUED;
   int err_code = LAYOUT_OK;
   std::string error;
@@ -97,7 +103,7 @@ struct layout_server {
   int32_t* d_xcd_ctr = nullptr;
   int lds_cap = 0;
   // stats (under mu)
-  int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, rounds = 0;
+  int64_t submitted = 0, completed = 0, failed = 0, rejected = 0, cancelled = 0, rounds = 0;
   double edge_updates = 0, busy_seconds = 0;
   std::vector<double> latencies;
 };
@@ -106,9 +112,9 @@ namespace {
 
 int64_t footprint_of(const layout_server_t* S, const Job& j, int32_t bundle, int32_t hub) {
   const int64_t cap = j.nnz > 0 ? chunk_bound(j.nnz, bundle, hub) : 0;
-  // row_ptr, col, positions, chunk table, alias table (degree-weighted only)
+  // row_ptr, col, positions, chunk table, alias table (weighted negatives)
   int64_t b = 4 * (int64_t(j.n) + 1) + 4 * j.nnz + 8 * int64_t(j.n) + 8 * cap + 4;
-  if (S->opts.neg_weights == LAYOUT_NEG_DEGREE) b += 8 * int64_t(j.n);
+  if (S->opts.neg_weights != LAYOUT_NEG_UNIFORM) b += 8 * int64_t(j.n);
   return b;
 }
 
@@ -158,13 +164,28 @@ int setup_job(layout_server_t* S, Job& j) {
   if (j.nnz > 0 && (rc = build_chunk_table(S->stream, row, j.n, j.nnz, j.bundle, j.hub, cb, cs,
                                            &j.n_chunks)) != LAYOUT_OK)
     return rc;
-  if (S->opts.neg_weights == LAYOUT_NEG_DEGREE && j.nnz > 0) {
+  if (S->opts.neg_weights != LAYOUT_NEG_UNIFORM && j.nnz > 0) {
     if ((rc = jalloc(j, reinterpret_cast<void**>(&thr), 4 * size_t(j.n), "alias thr")) ||
-        (rc = jalloc(j, reinterpret_cast<void**>(&alias), 4 * size_t(j.n), "alias")) ||
-        (rc = build_alias_table(S->stream, row, nullptr, j.n, j.nnz, thr, alias)))
+        (rc = jalloc(j, reinterpret_cast<void**>(&alias), 4 * size_t(j.n), "alias")))
       return rc;
+    rc = S->opts.neg_weights == LAYOUT_NEG_CUSTOM
+             ? upload_weights_and_build_alias(S->stream, row, j.weights.data(), j.n, false, thr,
+                                              alias)
+             : build_alias_table(S->stream, row, nullptr, j.n, j.nnz, thr, alias);
+    if (rc != LAYOUT_OK) return rc;
   }
-  launch_init_positions(S->stream, Y, j.n, j.seed);
+  if (!j.init.empty()) {
+    e = hipMemcpyAsync(Y, j.init.data(), 8 * size_t(j.n), hipMemcpyHostToDevice, S->stream);
+    if (e != hipSuccess) return hip_fail(e, "copying init_pos");
+  } else if (S->opts.init_mode == LAYOUT_INIT_PMDS && j.n > 0) {
+    // blocks the scheduler for the job's Pivot MDS (synchronises the stream)
+    if ((rc = pmds_positions(S->stream, row, col, j.n,
+                             S->opts.pmds_pivots ? S->opts.pmds_pivots : kDefaultPivots, j.seed,
+                             Y, nullptr, nullptr, nullptr)) != LAYOUT_OK)
+      return rc;
+  } else {
+    launch_init_positions(S->stream, Y, j.n, j.seed);
+  }
   GraphDesc& d = j.desc;
   d = GraphDesc{};
   d.row_ptr = row;
@@ -187,9 +208,11 @@ int setup_job(layout_server_t* S, Job& j) {
   d.lanes = j.lds ? j.lanes : 0;
   e = hipStreamSynchronize(S->stream);
   if (e != hipSuccess) return hip_fail(e, "job setup");
-  // the host copy of the graph is no longer needed
+  // the host copies are no longer needed
   std::vector<int32_t>().swap(j.row);
   std::vector<int32_t>().swap(j.col);
+  std::vector<uint32_t>().swap(j.weights);
+  std::vector<float>().swap(j.init);
   return LAYOUT_OK;
 }
 
@@ -203,6 +226,9 @@ void finish_job(layout_server_t* S, Job* j, int code, const std::string& msg) {
     S->completed += 1;
     S->edge_updates += double(j->nnz / 2) * (1 + j->k) * j->epochs;
     S->latencies.push_back(j->t_done - j->t_submit);
+  } else if (code == kCancelled) {
+    j->state = LAYOUT_JOB_CANCELLED;
+    S->cancelled += 1;
   } else {
     j->state = LAYOUT_JOB_FAILED;
     j->err_code = code;
@@ -273,7 +299,7 @@ int run_round(layout_server_t* S) {
     lg.lds_bytes = max_lds;
     lg.k = k;
     lg.mode = S->mode_lds;
-    lg.degree = S->opts.neg_weights == LAYOUT_NEG_DEGREE;
+    lg.degree = S->opts.neg_weights != LAYOUT_NEG_UNIFORM;
     int lds_block = 64;
     for (Job* j : lds_jobs) lds_block = std::max(lds_block, j->lanes);
     lg.block = lds_block;
@@ -318,7 +344,7 @@ int run_round(layout_server_t* S) {
       xg.d_counters = S->d_xcd_ctr;
       xg.n_segs = static_cast<int32_t>(segs.size());
       xg.k = k;
-      xg.degree = S->opts.neg_weights == LAYOUT_NEG_DEGREE;
+      xg.degree = S->opts.neg_weights != LAYOUT_NEG_UNIFORM;
       for (const GraphDesc& d : gx) xg.total_chunks += d.n_chunks;
       e = hipMemcpyAsync(S->d_table_xcd, table.data(), sizeof(GraphDesc) * table.size(),
                          hipMemcpyHostToDevice, S->stream);
@@ -345,7 +371,7 @@ int run_round(layout_server_t* S) {
     for (const GraphDesc& d : gt) gg.total_chunks += d.n_chunks;
     gg.k = k;
     gg.mode = S->mode_global;
-    gg.degree = S->opts.neg_weights == LAYOUT_NEG_DEGREE;
+    gg.degree = S->opts.neg_weights != LAYOUT_NEG_UNIFORM;
     gg.block = S->opts.block_threads && S->opts.block_threads <= 256 ? S->opts.block_threads : 256;
     gg.grid = S->opts.grid_blocks;
     gg.max_lanes = fair_lanes(gt, S->opts.nodes_per_lane);
@@ -394,6 +420,10 @@ void scheduler(layout_server_t* S) {
     }
     const double t0 = now_s();
     for (Job* j : admit) {
+      if (j->cancel.load()) {
+        finish_job(S, j, kCancelled, "cancelled");
+        continue;
+      }
       g_last_error.clear();
       const int rc = setup_job(S, *j);
       if (rc != LAYOUT_OK) {
@@ -420,9 +450,13 @@ void scheduler(layout_server_t* S) {
       S->dead_msg = msg;
       break;
     }
-    // retire finished jobs
+    // retire finished and cancelled jobs
     std::vector<Job*> still;
     for (Job* j : S->active) {
+      if (j->cancel.load()) {
+        finish_job(S, j, kCancelled, "cancelled");
+        continue;
+      }
       if (j->t < j->epochs && j->nnz > 0) {
         still.push_back(j);
         continue;
@@ -473,14 +507,15 @@ int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t ro
     return fail(LAYOUT_E_INVALID_ARG, "update_mode = %d", o.update_mode);
   if (o.update_mode == LAYOUT_JACOBI)
     return fail(LAYOUT_E_UNSUPPORTED, "the server runs the lock-free policies only");
-  if (o.neg_weights == LAYOUT_NEG_CUSTOM)
-    return fail(LAYOUT_E_UNSUPPORTED, "per-node negative weights: single-graph layouts only");
-  if (o.neg_weights != LAYOUT_NEG_UNIFORM && o.neg_weights != LAYOUT_NEG_DEGREE)
+  if (o.neg_weights != LAYOUT_NEG_UNIFORM && o.neg_weights != LAYOUT_NEG_DEGREE &&
+      o.neg_weights != LAYOUT_NEG_CUSTOM)
     return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
   if (o.engine < 0 || o.engine > 3) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
   if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g", o.gamma);
-  if (o.init_mode != LAYOUT_INIT_UNIFORM)
-    return fail(LAYOUT_E_UNSUPPORTED, "init_mode = %d (only the seeded uniform init here)", o.init_mode);
+  if (o.init_mode != LAYOUT_INIT_UNIFORM && o.init_mode != LAYOUT_INIT_PMDS)
+    return fail(LAYOUT_E_INVALID_ARG, "init_mode = %d", o.init_mode);
+  if (o.pmds_pivots < 0 || o.pmds_pivots > 64)
+    return fail(LAYOUT_E_INVALID_ARG, "pmds_pivots = %d (1..64, 0 = default)", o.pmds_pivots);
   if (o.block_threads < 0 || o.block_threads > 1024 || (o.block_threads % 64) != 0 ||
       o.bundle_edges < 0 || o.hub_split_edges < 0 || o.grid_blocks < 0 || o.nodes_per_lane < 0)
     return fail(LAYOUT_E_INVALID_ARG, "bad launch option");
@@ -524,8 +559,10 @@ int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t ro
   return LAYOUT_OK;
 }
 
-int layout_server_submit(layout_server_t* S, const int32_t* row_ptr, const int32_t* col_idx,
-                         int32_t n, int32_t k, int32_t epochs, uint64_t seed, int64_t* job_id) {
+int layout_server_submit_ex(layout_server_t* S, const int32_t* row_ptr, const int32_t* col_idx,
+                            int32_t n, int32_t k, int32_t epochs, uint64_t seed,
+                            const uint32_t* neg_weight_values, const float* init_pos,
+                            int64_t* job_id) {
   g_last_error.clear();
   if (!S || !job_id || !row_ptr || n < 0)
     return fail(LAYOUT_E_INVALID_ARG, "NULL server/job_id/row_ptr or n < 0");
@@ -533,6 +570,17 @@ int layout_server_submit(layout_server_t* S, const int32_t* row_ptr, const int32
   if (epochs < 1) return fail(LAYOUT_E_INVALID_ARG, "epochs = %d", epochs);
   const int32_t nnz = row_ptr[n];
   if (nnz < 0 || (nnz > 0 && !col_idx)) return fail(LAYOUT_E_INVALID_ARG, "bad row_ptr[n] or col");
+  const bool custom = S->opts.neg_weights == LAYOUT_NEG_CUSTOM;
+  if ((neg_weight_values != nullptr) != (custom && n > 0))
+    return fail(LAYOUT_E_INVALID_ARG,
+                "neg_weight_values must be given exactly when the server uses LAYOUT_NEG_CUSTOM");
+  if (custom && n > 0) {
+    int64_t W = 0;
+    for (int32_t v = 0; v < n; ++v) W += neg_weight_values[v];
+    if (W <= 0 || W >= (int64_t(1) << 32))
+      return fail(LAYOUT_E_INVALID_ARG, "negative weights sum to %lld (need 0 < W < 2^32)",
+                  (long long)W);
+  }
   Job* j = new (std::nothrow) Job();
   if (!j) return fail(LAYOUT_E_OOM, "host allocation");
   j->n = n;
@@ -542,6 +590,8 @@ int layout_server_submit(layout_server_t* S, const int32_t* row_ptr, const int32
   j->nnz = nnz;
   j->row.assign(row_ptr, row_ptr + n + 1);
   if (nnz > 0) j->col.assign(col_idx, col_idx + nnz);
+  if (custom && n > 0) j->weights.assign(neg_weight_values, neg_weight_values + n);
+  if (init_pos && n > 0) j->init.assign(init_pos, init_pos + 2 * size_t(n));
   j->t_submit = now_s();
   plan_job(S, *j);
   std::lock_guard<std::mutex> lk(S->mu);
@@ -571,6 +621,35 @@ int layout_server_submit(layout_server_t* S, const int32_t* row_ptr, const int32
   return LAYOUT_OK;
 }
 
+int layout_server_submit(layout_server_t* S, const int32_t* row_ptr, const int32_t* col_idx,
+                         int32_t n, int32_t k, int32_t epochs, uint64_t seed, int64_t* job_id) {
+  return layout_server_submit_ex(S, row_ptr, col_idx, n, k, epochs, seed, nullptr, nullptr,
+                                 job_id);
+}
+
+int layout_server_cancel(layout_server_t* S, int64_t job_id) {
+  if (!S) return fail(LAYOUT_E_INVALID_ARG, "NULL server");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->jobs.find(job_id);
+  if (it == S->jobs.end()) return fail(LAYOUT_E_INVALID_ARG, "unknown job %lld", (long long)job_id);
+  Job* j = it->second;
+  if (j->state == LAYOUT_JOB_QUEUED) {
+    auto q = std::find(S->queue.begin(), S->queue.end(), j);
+    if (q != S->queue.end()) S->queue.erase(q);
+    j->state = LAYOUT_JOB_CANCELLED;
+    j->t_done = now_s();
+    S->cancelled += 1;
+    S->cv_done.notify_all();
+    S->cv_work.notify_one();  // a slot may admit the next job
+    return LAYOUT_OK;
+  }
+  if (j->state == LAYOUT_JOB_RUNNING) {
+    j->cancel.store(true);  // retired after the current round
+    return LAYOUT_OK;
+  }
+  return fail(LAYOUT_E_INVALID_ARG, "job %lld has already ended", (long long)job_id);
+}
+
 int layout_server_poll(layout_server_t* S, int64_t job_id, int32_t* state) {
   if (!S || !state) return fail(LAYOUT_E_INVALID_ARG, "NULL argument");
   std::lock_guard<std::mutex> lk(S->mu);
@@ -586,13 +665,18 @@ int layout_server_wait(layout_server_t* S, int64_t job_id, double timeout_s) {
   auto it = S->jobs.find(job_id);
   if (it == S->jobs.end()) return fail(LAYOUT_E_INVALID_ARG, "unknown job %lld", (long long)job_id);
   Job* j = it->second;
-  auto done = [&] { return j->state == LAYOUT_JOB_DONE || j->state == LAYOUT_JOB_FAILED; };
+  auto done = [&] {
+    return j->state == LAYOUT_JOB_DONE || j->state == LAYOUT_JOB_FAILED ||
+           j->state == LAYOUT_JOB_CANCELLED;
+  };
   if (timeout_s < 0) {
     S->cv_done.wait(lk, done);
   } else if (!S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) {
     return fail(LAYOUT_E_INVALID_ARG, "timeout waiting for job %lld", (long long)job_id);
   }
   if (j->state == LAYOUT_JOB_FAILED) return fail(j->err_code, "%s", j->error.c_str());
+  if (j->state == LAYOUT_JOB_CANCELLED)
+    return fail(LAYOUT_E_INVALID_ARG, "job %lld was cancelled", (long long)job_id);
   return LAYOUT_OK;
 }
 
@@ -608,6 +692,11 @@ int layout_server_take(layout_server_t* S, int64_t job_id, float* host_out, doub
     S->jobs.erase(it);
     delete j;
     return fail(code, "%s", msg.c_str());
+  }
+  if (j->state == LAYOUT_JOB_CANCELLED) {
+    S->jobs.erase(it);
+    delete j;
+    return fail(LAYOUT_E_INVALID_ARG, "job %lld was cancelled", (long long)job_id);
   }
   if (j->state != LAYOUT_JOB_DONE) return fail(LAYOUT_E_INVALID_ARG, "job not done");
   if (host_out && !j->result.empty())
@@ -626,6 +715,7 @@ int layout_server_get_stats(layout_server_t* S, layout_server_stats* st) {
   st->completed = S->completed;
   st->failed = S->failed;
   st->rejected = S->rejected;
+  st->cancelled = S->cancelled;
   st->queued = int64_t(S->queue.size());
   int64_t running = 0;
   for (auto& kv : S->jobs) running += kv.second->state == LAYOUT_JOB_RUNNING ? 1 : 0;

@@ -293,6 +293,33 @@ int snap::build_alias_table(hipStream_t stream, const int32_t* d_row, const uint
   return LAYOUT_OK;
 }
 
+int snap::upload_weights_and_build_alias(hipStream_t stream, const int32_t* d_row,
+                                         const uint32_t* weights, int32_t n, bool on_device,
+                                         uint32_t* d_thr, uint32_t* d_alias) {
+  std::vector<uint32_t> w(static_cast<size_t>(n));
+  hipError_t e = hipSuccess;
+  if (on_device)
+    e = hipMemcpy(w.data(), weights, sizeof(uint32_t) * size_t(n), hipMemcpyDeviceToHost);
+  else
+    std::memcpy(w.data(), weights, sizeof(uint32_t) * size_t(n));
+  if (e != hipSuccess) return hip_fail(e, "reading neg_weight_values");
+  int64_t W = 0;
+  for (uint32_t x : w) W += x;
+  if (W <= 0 || W >= (int64_t(1) << 32))
+    return fail(LAYOUT_E_INVALID_ARG, "negative weights sum to %lld (need 0 < W < 2^32)",
+                (long long)W);
+  uint32_t* d_w = nullptr;
+  e = hipMalloc(&d_w, sizeof(uint32_t) * size_t(n));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_w, w.data(), sizeof(uint32_t) * size_t(n), hipMemcpyHostToDevice, stream);
+  int rc = LAYOUT_OK;
+  if (e == hipSuccess) rc = build_alias_table(stream, d_row, d_w, n, W, d_thr, d_alias);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (d_w) (void)hipFree(d_w);
+  if (e != hipSuccess) return hip_fail(e, "building the weighted alias table");
+  return rc;
+}
+
 int snap::lds_bytes_for(int32_t n, int dim) { return std::max(16, n * (dim == 3 ? 16 : 8)); }
 
 int snap::global_grid(const GlobalGroup& g) {
@@ -836,30 +863,12 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
     if ((rc = alloc(L, reinterpret_cast<void**>(&d_thr), sizeof(uint32_t) * size_t(n), "alias thr")) ||
         (rc = alloc(L, reinterpret_cast<void**>(&d_alias), sizeof(uint32_t) * size_t(n), "alias")))
       return bail(rc);
-    int64_t W = L->nnz;
-    uint32_t* d_w = nullptr;
-    if (o.neg_weight_values) {
-      std::vector<uint32_t> w(static_cast<size_t>(n));
-      if (inputs_on_device)
-        e = hipMemcpy(w.data(), o.neg_weight_values, sizeof(uint32_t) * size_t(n),
-                      hipMemcpyDeviceToHost);
-      else
-        std::memcpy(w.data(), o.neg_weight_values, sizeof(uint32_t) * size_t(n));
-      if (e != hipSuccess) return bail(hip_fail(e, "reading neg_weight_values"));
-      W = 0;
-      for (uint32_t x : w) W += x;
-      if (W <= 0 || W >= (int64_t(1) << 32))
-        return bail(fail(LAYOUT_E_INVALID_ARG, "negative weights sum to %lld (need 0 < W < 2^32)",
-                         (long long)W));
-      if ((rc = alloc(L, reinterpret_cast<void**>(&d_w), sizeof(uint32_t) * size_t(n), "weights")))
-        return bail(rc);
-      e = hipMemcpyAsync(d_w, w.data(), sizeof(uint32_t) * size_t(n), hipMemcpyHostToDevice,
-                         L->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
-      if (e != hipSuccess) return bail(hip_fail(e, "copying neg_weight_values"));
-    }
-    if ((rc = build_alias_table(L->stream, d_row, d_w, n, W, d_thr, d_alias)) != LAYOUT_OK)
-      return bail(rc);
+    if (o.neg_weight_values)
+      rc = upload_weights_and_build_alias(L->stream, d_row, o.neg_weight_values, n,
+                                          inputs_on_device != 0, d_thr, d_alias);
+    else
+      rc = build_alias_table(L->stream, d_row, nullptr, n, L->nnz, d_thr, d_alias);
+    if (rc != LAYOUT_OK) return bail(rc);
   }
 
   // initial positions

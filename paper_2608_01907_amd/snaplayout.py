@@ -80,6 +80,7 @@ class layout_graph(ctypes.Structure):
         ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
         ("n", ctypes.c_int32), ("reserved", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("init_pos", ctypes.c_void_p),
+        ("neg_weight_values", ctypes.c_void_p),
     ]
 
 
@@ -106,7 +107,7 @@ class layout_server_stats(ctypes.Structure):
         ("rounds", ctypes.c_int64),
         ("edge_updates", ctypes.c_double), ("busy_seconds", ctypes.c_double),
         ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
-        ("mean_latency_s", ctypes.c_double),
+        ("mean_latency_s", ctypes.c_double), ("cancelled", ctypes.c_int64),
     ]
 
 
@@ -114,6 +115,7 @@ LAYOUT_JOB_QUEUED = 0
 LAYOUT_JOB_RUNNING = 1
 LAYOUT_JOB_DONE = 2
 LAYOUT_JOB_FAILED = 3
+LAYOUT_JOB_CANCELLED = 4
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -168,6 +170,9 @@ _SIGNATURES = {
                                             ctypes.POINTER(_vp)]),
     "layout_server_submit": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _i32, _u64,
                                             ctypes.POINTER(_i64)]),
+    "layout_server_submit_ex": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _i32, _u64, _vp, _vp,
+                                               ctypes.POINTER(_i64)]),
+    "layout_server_cancel": (ctypes.c_int, [_vp, _i64]),
     "layout_server_poll": (ctypes.c_int, [_vp, _i64, ctypes.POINTER(_i32)]),
     "layout_server_wait": (ctypes.c_int, [_vp, _i64, ctypes.c_double]),
     "layout_server_take": (ctypes.c_int, [_vp, _i64, _vp, ctypes.POINTER(ctypes.c_double)]),
@@ -389,13 +394,15 @@ def layout_bench_copy(nbytes, reps):
 
 # ------------------------------------------------------------- batches
 def layout_batch_create(graphs, k, epochs, opts=None, inputs_on_device=0):
-    """graphs: list of dicts with row_ptr, col_idx, n, seed[, init_pos]."""
+    """graphs: list of dicts with row_ptr, col_idx, n, seed[, init_pos,
+    neg_weight_values]."""
     arr = (layout_graph * len(graphs))()
     keep = []
     for q, g in enumerate(graphs):
         if inputs_on_device:
             rp_p, ci_p = _ptr(g["row_ptr"])[0], _ptr(g["col_idx"])[0]
             ip = _ptr(g.get("init_pos"))[0]
+            wp = _ptr(g.get("neg_weight_values"))[0]
         else:
             rp = np.ascontiguousarray(g["row_ptr"], dtype=np.int32)
             ci = np.ascontiguousarray(g["col_idx"], dtype=np.int32)
@@ -406,8 +413,14 @@ def layout_batch_create(graphs, k, epochs, opts=None, inputs_on_device=0):
                 a = np.ascontiguousarray(g["init_pos"], dtype=np.float32)
                 keep.append(a)
                 ip = a.ctypes.data
+            wp = None
+            if g.get("neg_weight_values") is not None:
+                w = np.ascontiguousarray(g["neg_weight_values"], dtype=np.uint32)
+                keep.append(w)
+                wp = w.ctypes.data
         arr[q].row_ptr, arr[q].col_idx, arr[q].n = rp_p, ci_p, int(g["n"])
         arr[q].seed, arr[q].init_pos = int(g.get("seed", 0)), ip
+        arr[q].neg_weight_values = wp
     o = opts if opts is not None else layout_opts_init()
     h = _vp()
     _check(lib().layout_batch_create(arr, len(graphs), k, epochs, ctypes.byref(o),
@@ -483,6 +496,25 @@ def layout_server_submit(h, row_ptr, col_idx, n, k, epochs, seed):
     _check(lib().layout_server_submit(h, rp.ctypes.data, ci.ctypes.data, n, k, epochs, seed,
                                       ctypes.byref(jid)))
     return jid.value
+
+
+def layout_server_submit_ex(h, row_ptr, col_idx, n, k, epochs, seed, neg_weight_values=None,
+                            init_pos=None):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    w = None if neg_weight_values is None else np.ascontiguousarray(neg_weight_values,
+                                                                    dtype=np.uint32)
+    ip = None if init_pos is None else np.ascontiguousarray(init_pos, dtype=np.float32)
+    jid = _i64()
+    _check(lib().layout_server_submit_ex(h, rp.ctypes.data, ci.ctypes.data, n, k, epochs, seed,
+                                         None if w is None else w.ctypes.data,
+                                         None if ip is None else ip.ctypes.data,
+                                         ctypes.byref(jid)))
+    return jid.value
+
+
+def layout_server_cancel(h, job):
+    _check(lib().layout_server_cancel(h, job))
 
 
 def layout_server_poll(h, job):
@@ -615,9 +647,10 @@ class BatchLayout:
     def __init__(self, graphs, k=5, epochs=50, *, update_mode=LAYOUT_UPDATE_AUTO,
                  engine=LAYOUT_ENGINE_AUTO, eta0=1.0, bundle_edges=0, hub_split_edges=0,
                  block_threads=0, grid_blocks=0, neg_weights=LAYOUT_NEG_UNIFORM,
-                 nodes_per_lane=0):
+                 nodes_per_lane=0, init_mode=LAYOUT_INIT_UNIFORM, pmds_pivots=0):
         o = layout_opts_init()
         o.update_mode, o.engine, o.eta0 = update_mode, engine, eta0
+        o.init_mode, o.pmds_pivots = init_mode, pmds_pivots
         o.bundle_edges, o.hub_split_edges = bundle_edges, hub_split_edges
         o.block_threads, o.grid_blocks, o.neg_weights = block_threads, grid_blocks, neg_weights
         o.nodes_per_lane = nodes_per_lane

@@ -141,3 +141,66 @@ def test_batch_rejects_bad_graph(mix):
     with pytest.raises(SL.LayoutError) as ei:
         SL.BatchLayout(bad, k=3, epochs=2)
     assert ei.value.code == SL.LAYOUT_E_BAD_GRAPH and "graph 2" in str(ei.value)
+
+
+# ------------------------------------------ caller weights and PMDS starts
+def _weights(g, seed):
+    rng = np.random.default_rng(seed)
+    w = rng.integers(0, 50, g.n).astype(np.uint32)
+    w[rng.integers(0, g.n)] += 1  # never all zero
+    return w
+
+
+def test_batch_custom_weights_draws_bit_exact(mix):
+    """Each graph's draws follow the alias table of its own weights, as the
+    oracle builds it (Walker's integer sweep) and samples it."""
+    desc = _desc(mix)
+    ws = []
+    for q, (d, g) in enumerate(zip(desc, mix)):
+        w = _weights(g, q) if g.n > 0 else None
+        d["neg_weight_values"] = w
+        ws.append(w)
+    with SL.BatchLayout(desc, k=5, epochs=10, neg_weights=SL.LAYOUT_NEG_CUSTOM) as B:
+        for q, g in enumerate(mix):
+            if g.nnz == 0:
+                continue
+            thr, alias = O.alias_build(ws[q].astype(np.int64))
+            ref = O.draw_negatives(g.row_ptr, g.col, g.n, 5, 7, 100 + q, mode=O.NEG_DEGREE,
+                                   thr=thr, alias=alias)
+            assert np.array_equal(B.draws(q, 7), ref), q
+        B.run()
+        for q, g in enumerate(mix):
+            assert np.all(np.isfinite(B.positions(q)))
+
+
+def test_batch_custom_weights_rejected(mix):
+    desc = _desc(mix)  # no weights
+    with pytest.raises(SL.LayoutError) as ei:
+        SL.BatchLayout(desc, k=5, epochs=5, neg_weights=SL.LAYOUT_NEG_CUSTOM)
+    assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
+    desc = _desc(mix)
+    desc[0]["neg_weight_values"] = _weights(mix[0], 1)
+    with pytest.raises(SL.LayoutError) as ei:  # weights without the custom mode
+        SL.BatchLayout(desc, k=5, epochs=5)
+    assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
+    desc = _desc(mix)
+    for q, (d, g) in enumerate(zip(desc, mix)):
+        d["neg_weight_values"] = np.zeros(g.n, np.uint32) if g.n > 0 else None
+    with pytest.raises(SL.LayoutError) as ei:  # weights summing to 0
+        SL.BatchLayout(desc, k=5, epochs=5, neg_weights=SL.LAYOUT_NEG_CUSTOM)
+    assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
+
+
+def test_batch_pmds_start_equals_single_graph_pmds(mix):
+    """With eta0 = 0 the epochs leave the start in place: every graph's
+    positions are its Pivot MDS layout (the same as layout_pmds)."""
+    with SL.BatchLayout(_desc(mix), k=5, epochs=2, eta0=0.0,
+                        init_mode=SL.LAYOUT_INIT_PMDS) as B:
+        B.run()
+        got = [B.positions(q) for q in range(len(mix))]
+    for q, g in enumerate(mix):
+        if g.n == 0:
+            continue
+        ref = SL.layout_pmds(g.row_ptr, g.col, g.n, 0, 100 + q)
+        tol = 1e-5 * max(_diam(ref), 1e-6)
+        assert np.abs(got[q] - ref).max() <= tol, q

@@ -146,3 +146,116 @@ def test_server_small_job_moves_and_stays_finite(pool):
         SL.layout_server_destroy(srv)
     Y0 = O.init_positions(g.n, 9)
     assert np.all(np.isfinite(Y)) and not np.allclose(Y, Y0)
+
+
+# ------------------------------------ caller weights, PMDS starts, cancel
+def _server(**kw):
+    o = SL.layout_opts_init()
+    for k_, v in kw.items():
+        setattr(o, k_, v)
+    return SL.layout_server_create(0, 16, 1 << 20, o)
+
+
+def test_server_custom_weights_match_the_plain_path(pool):
+    """Weighted negatives through the server: the same layout quality as the
+    plain path with the same weights (paired over seeds), and the argument
+    rules of layout_server_submit_ex."""
+    T = 30
+    g = pool[3]
+    w = np.diff(g.row_ptr).astype(np.uint32) + 1  # degree + 1
+    srv = _server(neg_weights=SL.LAYOUT_NEG_CUSTOM)
+    try:
+        ids = [(sd, SL.layout_server_submit_ex(srv, g.row_ptr, g.col, g.n, 5, T, sd,
+                                               neg_weight_values=w)) for sd in range(500, 505)]
+        res = {}
+        for sd, jid in ids:
+            SL.layout_server_wait(srv, jid, 120.0)
+            res[sd] = SL.layout_server_take(srv, jid, g.n)[0]
+        with pytest.raises(SL.LayoutError) as ei:  # weights required
+            SL.layout_server_submit(srv, g.row_ptr, g.col, g.n, 5, T, 1)
+        assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
+        with pytest.raises(SL.LayoutError) as ei:  # zero mass
+            SL.layout_server_submit_ex(srv, g.row_ptr, g.col, g.n, 5, T, 1,
+                                       neg_weight_values=np.zeros(g.n, np.uint32))
+        assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
+    finally:
+        SL.layout_server_destroy(srv)
+    plain = {}
+    for sd, _ in ids:
+        with SL.Layout(g.row_ptr, g.col, g.n, k=5, epochs=T, seed=sd,
+                       neg_weights=SL.LAYOUT_NEG_CUSTOM, neg_weight_values=w) as L:
+            L.run()
+            plain[sd] = L.positions()
+    qa = [M.quality(g.row_ptr, g.col, plain[sd], g.labels, sample=4000) for sd, _ in ids]
+    qs = [M.quality(g.row_ptr, g.col, res[sd], g.labels, sample=4000) for sd, _ in ids]
+    assert_paired_close(qa, qs, label="custom")
+    srv = _server()
+    try:
+        with pytest.raises(SL.LayoutError) as ei:  # weights without the custom mode
+            SL.layout_server_submit_ex(srv, g.row_ptr, g.col, g.n, 5, T, 1, neg_weight_values=w)
+        assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
+    finally:
+        SL.layout_server_destroy(srv)
+
+
+def test_server_pmds_start_and_caller_init(pool):
+    """eta0 = 0 keeps the start: a PMDS server returns each job's Pivot MDS
+    layout; a caller's init_pos comes back unchanged."""
+    srv = _server(init_mode=SL.LAYOUT_INIT_PMDS, eta0=0.0)
+    try:
+        jobs = [(gi, SL.layout_server_submit(srv, g.row_ptr, g.col, g.n, 5, 3, 40 + gi))
+                for gi, g in enumerate(pool)]
+        Y0 = np.random.default_rng(1).standard_normal((pool[0].n, 2)).astype(np.float32)
+        own = SL.layout_server_submit_ex(srv, pool[0].row_ptr, pool[0].col, pool[0].n, 5, 3, 7,
+                                         init_pos=Y0)
+        for gi, jid in jobs:
+            SL.layout_server_wait(srv, jid, 120.0)
+            Y = SL.layout_server_take(srv, jid, pool[gi].n)[0]
+            g = pool[gi]
+            ref = SL.layout_pmds(g.row_ptr, g.col, g.n, 0, 40 + gi)
+            diam = float(np.linalg.norm(ref.max(0) - ref.min(0)))
+            assert np.abs(Y - ref).max() <= 1e-5 * diam, gi
+        SL.layout_server_wait(srv, own, 120.0)
+        assert np.array_equal(SL.layout_server_take(srv, own, pool[0].n)[0], Y0)
+    finally:
+        SL.layout_server_destroy(srv)
+
+
+def test_server_cancel(pool):
+    """Cancel a queued job (ends at once) and a running one (retired after its
+    round); the other jobs complete, the budget is released, and the
+    cancelled ids answer as documented."""
+    big = pool[4]
+    srv = SL.layout_server_create(0, 1, 1 << 16)  # one slot: jobs queue up
+    try:
+        # thousands of short rounds: seconds of work, so the cancel lands mid-run
+        running = SL.layout_server_submit(srv, big.row_ptr, big.col, big.n, 5, 3000, 1)
+        queued = [SL.layout_server_submit(srv, big.row_ptr, big.col, big.n, 5, 10, 2 + q)
+                  for q in range(3)]
+        deadline = time.time() + 60
+        while SL.layout_server_poll(srv, running) != SL.LAYOUT_JOB_RUNNING:
+            assert time.time() < deadline
+            time.sleep(0.01)
+        SL.layout_server_cancel(srv, queued[1])
+        assert SL.layout_server_poll(srv, queued[1]) == SL.LAYOUT_JOB_CANCELLED
+        SL.layout_server_cancel(srv, running)
+        with pytest.raises(SL.LayoutError):
+            SL.layout_server_wait(srv, running, 60.0)  # ends cancelled
+        assert SL.layout_server_poll(srv, running) == SL.LAYOUT_JOB_CANCELLED
+        for jid in (queued[0], queued[2]):
+            SL.layout_server_wait(srv, jid, 120.0)
+            Y, _ = SL.layout_server_take(srv, jid, big.n)
+            assert np.all(np.isfinite(Y))
+        for jid in (running, queued[1]):
+            with pytest.raises(SL.LayoutError) as ei:
+                SL.layout_server_take(srv, jid, big.n)
+            assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
+            with pytest.raises(SL.LayoutError):  # forgotten after take
+                SL.layout_server_poll(srv, jid)
+        with pytest.raises(SL.LayoutError) as ei:
+            SL.layout_server_cancel(srv, 10**9)
+        assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
+        st = SL.layout_server_get_stats(srv)
+        assert st["cancelled"] == 2 and st["completed"] == 2 and st["hbm_in_use"] == 0
+    finally:
+        SL.layout_server_destroy(srv)
