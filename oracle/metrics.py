@@ -171,6 +171,105 @@ def cq_score(Y, labels, sample: int | None = None, seed: int = 12345) -> float:
     return float(adjusted_rand_score(labels[nodes], km.labels_))
 
 
+# ----------------------------------------------- CQ: k-means and the ARI
+# The clustering behind CQ written out plainly (seeded k-means++ start, then
+# Lloyd's iterations), so that a device implementation can be held to it.
+KMEANS_TAG = 4  # generator tag of the k-means++ draws: counter (c, 0, 0, 4)
+
+
+def kmeans_draws(seed: int, K: int) -> np.ndarray:
+    """Word x0 of the Philox block (c, 0, 0, KMEANS_TAG) for c < K."""
+    from oracle import oracle as O
+
+    return O.philox_bulk((seed, O.KEY_DOMAIN), (0, 0, 0, KMEANS_TAG), K)[:, 0].copy()
+
+
+def kmeans_pp(Y, K: int, seed: int) -> np.ndarray:
+    """k-means++ (Arthur and Vassilvitskii, SODA 2007) on FP32 points widened
+    to FP64: the first center is point floor(x_0 n / 2^64); center c >= 1 is
+    the first point i whose running sum of D^2 (squared distance to the
+    nearest chosen center) exceeds u_c * sum(D^2), u_c = (x_c >> 11) 2^-53;
+    when every D^2 is 0 it is point floor(x_c n / 2^64).  Returns indices."""
+    X = np.asarray(Y, dtype=np.float32).astype(np.float64)
+    n = X.shape[0]
+    words = kmeans_draws(seed, K)
+    first = int((int(words[0]) * n) >> 64)
+    chosen = [first]
+    d2 = np.full(n, np.inf)
+    for c in range(1, K):
+        cx, cy = X[chosen[-1]]
+        dx = X[:, 0] - cx
+        dy = X[:, 1] - cy
+        d2 = np.minimum(d2, dx * dx + dy * dy)
+        total = float(np.sum(d2))
+        if total > 0.0:
+            t = float(int(words[c]) >> 11) * 2.0 ** -53 * total
+            idx = int(np.searchsorted(np.cumsum(d2), t, side="right"))
+            chosen.append(min(idx, n - 1))
+        else:
+            chosen.append(int((int(words[c]) * n) >> 64))
+    return np.array(chosen, dtype=np.int64)
+
+
+def kmeans_lloyd(Y, centers, max_iter: int = 300):
+    """Lloyd's iterations from the given centers (FP64): assign each point to
+    the nearest center (lowest index on ties), move each center to the mean
+    of its points (an empty cluster keeps its center), stop when an
+    assignment after the first repeats the previous one or after max_iter.
+    Returns (assignment, centers, iterations)."""
+    X = np.asarray(Y, dtype=np.float32).astype(np.float64)
+    C = np.array(centers, dtype=np.float64).reshape(-1, 2)
+    K = C.shape[0]
+    prev = None
+    it = 0
+    for it in range(1, max_iter + 1):
+        dx = X[:, 0][:, None] - C[:, 0][None, :]
+        dy = X[:, 1][:, None] - C[:, 1][None, :]
+        a = np.argmin(dx * dx + dy * dy, axis=1)
+        if prev is not None and np.array_equal(a, prev):
+            break
+        prev = a
+        cnt = np.bincount(a, minlength=K)
+        sx = np.bincount(a, weights=X[:, 0], minlength=K)
+        sy = np.bincount(a, weights=X[:, 1], minlength=K)
+        nz = cnt > 0
+        C[nz, 0] = sx[nz] / cnt[nz]
+        C[nz, 1] = sy[nz] / cnt[nz]
+    return a.astype(np.int64), C, it
+
+
+def ari(labels, assign) -> float:
+    """Adjusted Rand index (Hubert and Arabie, 1985) from its definition:
+    (index - expected) / (max - expected) over the contingency table, with
+    index = sum C(n_ij, 2), expected = sum C(a_i, 2) sum C(b_j, 2) / C(n, 2),
+    max = (sum C(a_i, 2) + sum C(b_j, 2)) / 2; 1 when max = expected."""
+    _, li = np.unique(np.asarray(labels), return_inverse=True)
+    _, ci = np.unique(np.asarray(assign), return_inverse=True)
+    n = li.size
+    table = np.zeros((li.max() + 1, ci.max() + 1), dtype=np.int64)
+    np.add.at(table, (li, ci), 1)
+
+    def c2(x):
+        x = np.asarray(x, dtype=np.float64)
+        return x * (x - 1) / 2
+
+    index = c2(table).sum()
+    sa, sb = c2(table.sum(1)).sum(), c2(table.sum(0)).sum()
+    expected = sa * sb / c2(n) if n > 1 else 0.0
+    mx = (sa + sb) / 2
+    if mx == expected:
+        return 1.0
+    return float((index - expected) / (mx - expected))
+
+
+def cq_kmeans(Y, labels, seed: int, max_iter: int = 300) -> float:
+    """CQ with the k-means written out above (K = number of labels)."""
+    K = np.unique(np.asarray(labels)).size
+    X = np.asarray(Y, dtype=np.float32)
+    a, _, _ = kmeans_lloyd(X, X[kmeans_pp(X, K, seed)], max_iter)
+    return ari(labels, a)
+
+
 def quality(row_ptr, col, Y, labels, sample: int | None = None, seed: int = 12345,
             with_cq: bool = False) -> dict:
     out = {"np": np_score(row_ptr, col, Y, sample=sample, seed=seed),

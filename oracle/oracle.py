@@ -33,6 +33,7 @@ ORDER_SHUFFLED = 0
 ORDER_CSR = 1
 
 ALPHA, BETA, GAMMA, ETA0 = 0.1, 8.0, 2.0, 1.0
+KEY_DOMAIN = 0x534E41502D744644  # second key word of every draw ("SNAP-tFD")
 
 _lib = None
 

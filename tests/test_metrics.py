@@ -128,3 +128,64 @@ def test_np_counts_f32_agree_with_the_fp64_metric(small):
     assert np.array_equal(k1, np.diff(small.row_ptr))
     assert abs(float(np.mean(i1[k1 > 0] / (2 * k1[k1 > 0] - i1[k1 > 0])))
                - M.np_score(small.row_ptr, small.col, Y.astype(np.float64), r=1)) <= 1e-12
+
+
+# --------------------------------------------------------- CQ: k-means, ARI
+def test_ari_matches_sklearn_and_degenerate_cases():
+    from sklearn.metrics import adjusted_rand_score
+
+    rng = np.random.default_rng(8)
+    for _ in range(5):
+        a = rng.integers(0, 6, 500)
+        b = np.where(rng.random(500) < 0.7, a, rng.integers(0, 9, 500))
+        assert abs(M.ari(a, b) - adjusted_rand_score(a, b)) <= 1e-12
+    a = rng.integers(0, 4, 50)
+    assert M.ari(a, a + 10) == 1.0  # a relabelling is perfect agreement
+    for x, y in [(np.zeros(7), np.zeros(7)), (np.arange(7), np.arange(7)),
+                 (np.zeros(7), np.arange(7))]:
+        assert abs(M.ari(x, y) - adjusted_rand_score(x, y)) <= 1e-12
+
+
+def test_kmeans_pp_first_center_and_d2_rule():
+    rng = np.random.default_rng(1)
+    Y = rng.standard_normal((400, 2)).astype(np.float32)
+    seed, K = 5, 6
+    words = M.kmeans_draws(seed, K)
+    c = M.kmeans_pp(Y, K, seed)
+    assert c[0] == (int(words[0]) * 400) >> 64
+    assert np.unique(c).size == K  # a chosen point has D^2 = 0 and is never drawn again
+    # center 1 by brute force over the cumulative D^2 from center 0
+    X = Y.astype(np.float64)
+    d2 = ((X - X[c[0]]) ** 2).sum(1)
+    t = (int(words[1]) >> 11) * 2.0 ** -53 * d2.sum()
+    cum = 0.0
+    for i in range(400):
+        cum += d2[i]
+        if cum > t:
+            break
+    assert c[1] == i
+
+
+def test_kmeans_pp_samples_in_proportion_to_d2():
+    """Two tight groups, one far point: the second center lands in the group
+    far from the first center with the D^2 share it carries."""
+    Y = np.concatenate([np.zeros((50, 2)), np.full((50, 2), 10.0)]).astype(np.float32)
+    hits = 0
+    for seed in range(400):
+        c = M.kmeans_pp(Y, 2, seed)
+        hits += (c[0] < 50) != (c[1] < 50)
+    assert hits == 400  # all of D^2 sits in the other group
+
+
+def test_lloyd_recovers_separated_blobs_and_converges():
+    rng = np.random.default_rng(3)
+    labels = np.repeat(np.arange(5), 80)
+    centres = rng.uniform(-100, 100, (5, 2))
+    Y = (centres[labels] + rng.standard_normal((400, 2))).astype(np.float32)
+    a, C, it = M.kmeans_lloyd(Y, Y[[0, 80, 160, 240, 320]], 100)
+    assert M.ari(labels, a) == 1.0 and it <= 3
+    assert np.allclose(np.sort(C, axis=0), np.sort(centres, axis=0), atol=0.5)
+    assert M.cq_kmeans(Y, labels, seed=0) > 0.9
+    # an empty cluster keeps its center
+    a2, C2, _ = M.kmeans_lloyd(Y[:80], np.array([[0.0, 0.0], [1e6, 1e6]]), 10)
+    assert np.all(a2 == 0) and tuple(C2[1]) == (1e6, 1e6)
