@@ -265,6 +265,31 @@ int layout_silhouette(layout_t *L, const int32_t *labels, double *si_out);
 int layout_neighbourhood(layout_t *L, const int32_t *nodes, int32_t count, int32_t radius,
                          int32_t *k_out, int32_t *inter_out, double *np_out);
 
+/* Clustering quality of the current positions (the CQ metric of Sec. 4.1):
+ * k-means of the layout, then the adjusted Rand index (Hubert and Arabie)
+ * between the clusters and labels (host int32[n], any values).
+ *   clusters: K, 0 = the number of distinct labels; 1 <= K <= min(n, 4096),
+ *     and labels x K <= 2^27, else E_INVALID_ARG.
+ *   init_centers (nullable): host K x 2 FP32 starting centers.  NULL = a
+ *     k-means++ start (Arthur and Vassilvitskii) drawn from seed.  The first
+ *     center is point floor(x_0 n / 2^64).  Center c is the first point
+ *     whose running sum of D^2 (FP64, in node order) exceeds
+ *     u_c * sum(D^2), with u_c = (x_c >> 11) 2^-53 and x_c word x0 of
+ *     Philox block (c, 0, 0, 4).
+ *   Lloyd's iterations: nearest center by FP64 squared distance (lowest
+ *     index on ties); centers move to their clusters' means (an empty
+ *     cluster keeps its center).  They stop when an assignment after the
+ *     first changes nothing, or after max_iter (>= 1) passes.
+ *   cq_out: the ARI (1 when both partitions are trivial in the same way).
+ *   Optional outputs (host): assign_out int32[n], the final clusters;
+ *     iters_out, the assignment passes; centers_out int32[K], the k-means++
+ *     points (-1 when init_centers is given).
+ * 2D handles only (E_UNSUPPORTED for 3D).  Allocates and frees temporary
+ * device memory; synchronises the handle's stream. */
+int layout_cluster_quality(layout_t *L, const int32_t *labels, int32_t clusters, uint64_t seed,
+                           int32_t max_iter, const float *init_centers, double *cq_out,
+                           int32_t *assign_out, int32_t *iters_out, int32_t *centers_out);
+
 /* Writes the k negatives the epoch kernels draw for every directed edge in
  * epoch t (host array nnz*k, int32, edge-major).  Does not change positions. */
 int layout_debug_draws(layout_t *L, int32_t epoch, int32_t *host_out);

@@ -82,6 +82,13 @@ int pmds_positions(hipStream_t stream, const int32_t* d_row, const int32_t* d_co
                    int32_t pivots, uint64_t seed, float2* d_Y, int32_t* d_pivots_out,
                    int32_t* d_dist_out, int32_t* pivots_used);
 void launch_fill_zero(hipStream_t stream, float2* d_p, int64_t n);
+// CQ of the positions (cluster.hip): k-means (k-means++ start from seed, or
+// init_centers, host K x 2) and the ARI against host labels[n].  Outputs
+// (nullable but ari_out) on the host.  Synchronises the stream.
+int kmeans_cq(hipStream_t stream, const float2* d_Y, int32_t n, const int32_t* labels,
+              int32_t K, uint64_t seed, int32_t max_iter, const float* init_centers,
+              double* ari_out, int32_t* assign_out, int32_t* iters_out,
+              int32_t* centers_idx_out);
 // k_i and |R_i ∩ K_i| of the NP metric for host query nodes (neighbours.hip;
 // host outputs, count entries).  Synchronises the stream.
 int neighbourhood_counts(hipStream_t stream, const int32_t* d_row, const int32_t* d_col,

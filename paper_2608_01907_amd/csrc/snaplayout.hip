@@ -1193,6 +1193,19 @@ int layout_neighbourhood(layout_t* L, const int32_t* nodes, int32_t count, int32
   return LAYOUT_OK;
 }
 
+int layout_cluster_quality(layout_t* L, const int32_t* labels, int32_t clusters, uint64_t seed,
+                           int32_t max_iter, const float* init_centers, double* cq_out,
+                           int32_t* assign_out, int32_t* iters_out, int32_t* centers_out) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (L->dim != 2) return fail(LAYOUT_E_UNSUPPORTED, "the CQ monitor is 2D");
+  if (!labels || !cq_out) return fail(LAYOUT_E_INVALID_ARG, "NULL labels or cq_out");
+  if (L->n < 1) return fail(LAYOUT_E_INVALID_ARG, "CQ needs at least one node");
+  if (clusters < 0 || max_iter < 1)
+    return fail(LAYOUT_E_INVALID_ARG, "clusters = %d, max_iter = %d", clusters, max_iter);
+  return kmeans_cq(L->stream, L->host_desc.Y, L->n, labels, clusters, seed, max_iter,
+                   init_centers, cq_out, assign_out, iters_out, centers_out);
+}
+
 int layout_get_info(const layout_t* L, layout_info* info) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (!info) return fail(LAYOUT_E_INVALID_ARG, "info is NULL");

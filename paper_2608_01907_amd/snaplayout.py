@@ -142,6 +142,9 @@ _SIGNATURES = {
     "layout_silhouette": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double)]),
     "layout_neighbourhood": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp,
                                             ctypes.POINTER(ctypes.c_double)]),
+    "layout_cluster_quality": (ctypes.c_int, [_vp, _vp, _i32, _u64, _i32, _vp,
+                                              ctypes.POINTER(ctypes.c_double), _vp,
+                                              ctypes.POINTER(_i32), _vp]),
     "layout_pmds": (ctypes.c_int, [_vp, _vp, _i32, _i32, _u64, _i32, _vp, _vp, _vp,
                                    ctypes.POINTER(_i32)]),
     "layout_sampled_energy": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_double),
@@ -341,6 +344,22 @@ def layout_neighbourhood(h, nodes, radius=2):
     _check(lib().layout_neighbourhood(h, q.ctypes.data, int(q.size), int(radius), k.ctypes.data,
                                       inter.ctypes.data, ctypes.byref(out)))
     return out.value, k[:q.size], inter[:q.size]
+
+
+def layout_cluster_quality(h, labels, clusters=0, seed=0, max_iter=300, init_centers=None):
+    """(CQ, assignment, iterations, k-means++ center indices) of the layout."""
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    n = lab.size
+    K = clusters if clusters else int(np.unique(lab).size)
+    ic = None if init_centers is None else np.ascontiguousarray(init_centers, dtype=np.float32)
+    assign = np.zeros(max(n, 1), dtype=np.int32)
+    centers = np.zeros(max(K, 1), dtype=np.int32)
+    cq, iters = ctypes.c_double(), _i32()
+    _check(lib().layout_cluster_quality(h, lab.ctypes.data, int(clusters), int(seed),
+                                        int(max_iter), None if ic is None else ic.ctypes.data,
+                                        ctypes.byref(cq), assign.ctypes.data, ctypes.byref(iters),
+                                        centers.ctypes.data))
+    return cq.value, assign[:n], iters.value, centers[:K]
 
 
 def layout_sampled_energy(h, epoch):
@@ -616,6 +635,9 @@ class Layout:
 
     def neighbourhood(self, nodes, radius=2):
         return layout_neighbourhood(self.h, nodes, radius)
+
+    def cluster_quality(self, labels, clusters=0, seed=0, max_iter=300, init_centers=None):
+        return layout_cluster_quality(self.h, labels, clusters, seed, max_iter, init_centers)
 
     def status(self):
         return layout_status(self.h)
