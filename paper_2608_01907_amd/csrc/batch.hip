@@ -271,6 +271,48 @@ void cache_store(const char* path, const std::string& key, int bundle, int bpc, 
 
 }  // namespace
 
+namespace {
+
+// Balance the two halves of a replay.  An LDS graph runs all its epochs on
+// one CU, while the other graphs share the whole device epoch by epoch, so
+// the LDS half lasts as long as its largest graph.  The largest LDS graphs
+// move to the device-wide group while one of them alone would outlast it:
+// nnz_g > X / kLdsBalance, with X the device-wide group's directed edges.
+// kLdsBalance is the measured ratio of the device's edge rate on the XCD
+// bins to one CU's on the LDS engine (about 700 on MI355X at k = 5: 1.07e10
+// against 1.5e7 directed edges per second).  Graphs below kLdsKeepEdges stay
+// in LDS, so a batch of small graphs keeps its one-launch replay.  Then, at
+// most one LDS graph per CU: a second LDS workgroup on a CU waits for the
+// first when their positions do not fit its LDS together, so the largest
+// graphs beyond the CU count move as well.
+constexpr double kLdsBalance = 700.0;
+constexpr int64_t kLdsKeepEdges = 100000;
+
+void balance_lds(const std::vector<int64_t>& nnz, std::vector<uint8_t>& in_lds, int cus) {
+  std::vector<int32_t> cand;
+  int64_t X = 0;
+  for (size_t g = 0; g < nnz.size(); ++g) {
+    if (in_lds[g])
+      cand.push_back(static_cast<int32_t>(g));
+    else
+      X += nnz[g];
+  }
+  if (X == 0) return;
+  std::sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) {
+    return nnz[a] != nnz[b] ? nnz[a] > nnz[b] : a < b;
+  });
+  size_t moved = 0;
+  for (int32_t g : cand) {
+    if (nnz[g] < kLdsKeepEdges || double(nnz[g]) * kLdsBalance <= double(X)) break;
+    in_lds[g] = 0;
+    X += nnz[g];
+    ++moved;
+  }
+  for (size_t q = moved; cus > 0 && cand.size() - q > size_t(cus); ++q) in_lds[cand[q]] = 0;
+}
+
+}  // namespace
+
 extern "C" {
 
 int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, int32_t epochs,
@@ -345,6 +387,7 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
   B->lds_hub.resize(count);
   int64_t rows = 0, chunks = 0;
   int max_lds = 8;
+  // sizes first, then the engine of every graph
   for (int32_t g = 0; g < count; ++g) {
     const layout_graph& gr = graphs[g];
     if (gr.n < 0 || !gr.row_ptr) return bail(fail(LAYOUT_E_INVALID_ARG, "graph %d: bad n/row_ptr", g));
@@ -359,9 +402,6 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
     if (nnz > 0 && !gr.col_idx) return bail(fail(LAYOUT_E_INVALID_ARG, "graph %d: col NULL", g));
     B->n[g] = gr.n;
     B->nnz[g] = nnz;
-    B->node_off[g] = B->nodes;
-    B->edge_off[g] = B->total_nnz;
-    B->row_off[g] = rows;
     const bool fits = lds_bytes_for(gr.n) <= dp.lds_per_block;
     bool lds = false;
     if (!jacobi) {
@@ -373,6 +413,15 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
       }
     }
     B->in_lds[g] = lds;
+  }
+  if (o.engine == LAYOUT_ENGINE_AUTO && !jacobi) balance_lds(B->nnz, B->in_lds, dp.cus);
+  for (int32_t g = 0; g < count; ++g) {
+    const layout_graph& gr = graphs[g];
+    const int32_t nnz = static_cast<int32_t>(B->nnz[g]);
+    B->node_off[g] = B->nodes;
+    B->edge_off[g] = B->total_nnz;
+    B->row_off[g] = rows;
+    const bool lds = B->in_lds[g];
     int64_t cap;
     if (lds) {
       const int block = o.block_threads ? o.block_threads : lds_lanes_for(gr.n, o.nodes_per_lane);
