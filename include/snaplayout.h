@@ -300,6 +300,28 @@ int layout_debug_draws(layout_t *L, int32_t epoch, int32_t *host_out);
 int layout_debug_draws_at(layout_t *L, int32_t epoch, const int64_t *edges, int64_t count,
                           int32_t *host_out);
 
+/* Conflict counter: runs min(count, remaining) epochs like layout_epoch,
+ * through an instrumented copy of the epoch (slower; same chunks, draws and
+ * launch shape) that keeps a version word per node.  *stores = position
+ * writes; *conflicts = writes that followed another lane's write of the same
+ * node since this lane loaded it (a lost update under HOGWILD_STORE, a
+ * change computed from a stale read under ATOMIC: the conflicts of the
+ * lock-free scheme, Sec. 3.4); *untracked = writes whose load the counter no
+ * longer held (source commits of long runs without a reload).  2D layouts on
+ * the global engine, lock-free policies (else E_UNSUPPORTED).  Synchronises;
+ * allocates a version word per node for the call. */
+int layout_debug_conflicts(layout_t *L, int32_t count, int64_t *stores, int64_t *conflicts,
+                           int64_t *untracked);
+
+/* Atomic probe: every lane of a launch of 8 workgroups (256 lanes) per CU
+ * adds 1, reps times, at device scope to one FP64 and one u64 counter
+ * (spread = 0), or each lane to its own pair of counters (spread = 1).
+ * *fsum_out and *isum_out receive the totals, *adds_out the number of adds
+ * per counter kind (exact totals show atomic visibility across the XCDs),
+ * *ms the launch time.  Allocates and frees its counters. */
+int layout_bench_atomics(int32_t reps, int32_t spread, double *fsum_out, int64_t *isum_out,
+                         int64_t *adds_out, float *ms);
+
 /* Copies the chunk table: begin[n_chunks + 1] (first directed edge of each
  * lane chunk, begin[n_chunks] = nnz) and src[n_chunks] (row holding that
  * edge).  n_chunks comes from layout_get_info. */

@@ -89,6 +89,12 @@ int kmeans_cq(hipStream_t stream, const float2* d_Y, int32_t n, const int32_t* l
               int32_t K, uint64_t seed, int32_t max_iter, const float* init_centers,
               double* ari_out, int32_t* assign_out, int32_t* iters_out,
               int32_t* centers_idx_out);
+// Epochs [t, t + count) of one single-graph table with the conflict counter
+// (probes.hip): writes, writes that followed a concurrent write of the same
+// node since their load, and writes whose load the counter no longer held.
+int run_conflict_epochs(hipStream_t stream, const GraphDesc* d_table, int32_t n, int k,
+                        int mode, bool degree, int grid, int block, int32_t t, int32_t count,
+                        int64_t* stores, int64_t* conflicts, int64_t* untracked);
 // k_i and |R_i ∩ K_i| of the NP metric for host query nodes (neighbours.hip;
 // host outputs, count entries).  Synchronises the stream.
 int neighbourhood_counts(hipStream_t stream, const int32_t* d_row, const int32_t* d_col,

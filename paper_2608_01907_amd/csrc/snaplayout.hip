@@ -1206,6 +1206,29 @@ int layout_cluster_quality(layout_t* L, const int32_t* labels, int32_t clusters,
                    init_centers, cq_out, assign_out, iters_out, centers_out);
 }
 
+int layout_debug_conflicts(layout_t* L, int32_t count, int64_t* stores, int64_t* conflicts,
+                           int64_t* untracked) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  if (!stores || !conflicts || !untracked || count < 0)
+    return fail(LAYOUT_E_INVALID_ARG, "NULL output or count < 0");
+  if (L->engine != LAYOUT_ENGINE_GLOBAL || L->dim != 2 || L->mode == LAYOUT_JACOBI)
+    return fail(LAYOUT_E_UNSUPPORTED,
+                "the conflict counter runs 2D lock-free layouts on the global engine");
+  if (L->t >= L->epochs) return fail(LAYOUT_E_DONE, "all %d epochs done", L->epochs);
+  const int32_t run = std::min(count, L->epochs - L->t);
+  *stores = *conflicts = *untracked = 0;
+  if (run == 0 || L->nnz == 0) {
+    L->t += run;
+    return LAYOUT_OK;
+  }
+  const GlobalGroup g = global_group_of(L);
+  const int rc = run_conflict_epochs(L->stream, L->d_table, L->n, L->k, L->mode, g.degree,
+                                     global_grid(g), g.block, L->t, run, stores, conflicts,
+                                     untracked);
+  if (rc == LAYOUT_OK) L->t += run;
+  return rc;
+}
+
 int layout_get_info(const layout_t* L, layout_info* info) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (!info) return fail(LAYOUT_E_INVALID_ARG, "info is NULL");

@@ -156,6 +156,10 @@ _SIGNATURES = {
     "layout_debug_chunks": (ctypes.c_int, [_vp, _vp, _vp]),
     "layout_bench_gather": (ctypes.c_int, [_vp, _i32, _i32, _f32p]),
     "layout_bench_copy": (ctypes.c_int, [_i64, _i32, _f32p]),
+    "layout_debug_conflicts": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i64),
+                                              ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "layout_bench_atomics": (ctypes.c_int, [_i32, _i32, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(_i64), ctypes.POINTER(_i64), _f32p]),
     "layout_batch_create": (ctypes.c_int, [ctypes.POINTER(layout_graph), _i32, _i32, _i32,
                                            ctypes.POINTER(layout_opts), _i32,
                                            ctypes.POINTER(_vp)]),
@@ -360,6 +364,22 @@ def layout_cluster_quality(h, labels, clusters=0, seed=0, max_iter=300, init_cen
                                         ctypes.byref(cq), assign.ctypes.data, ctypes.byref(iters),
                                         centers.ctypes.data))
     return cq.value, assign[:n], iters.value, centers[:K]
+
+
+def layout_debug_conflicts(h, count):
+    """(writes, conflicting writes, untracked writes) over count epochs."""
+    st, cf, un = _i64(), _i64(), _i64()
+    _check(lib().layout_debug_conflicts(h, int(count), ctypes.byref(st), ctypes.byref(cf),
+                                        ctypes.byref(un)))
+    return st.value, cf.value, un.value
+
+
+def layout_bench_atomics(reps, spread=0):
+    """(FP64 total, u64 total, adds per kind, ms) of the atomic probe."""
+    f, i, a, ms = ctypes.c_double(), _i64(), _i64(), ctypes.c_float()
+    _check(lib().layout_bench_atomics(int(reps), int(spread), ctypes.byref(f), ctypes.byref(i),
+                                      ctypes.byref(a), ctypes.byref(ms)))
+    return f.value, i.value, a.value, ms.value
 
 
 def layout_sampled_energy(h, epoch):
