@@ -1,0 +1,87 @@
+"""Parity at full size, in the launch configuration the benchmark times
+(inputs resident on the device, default options: the global engine at its
+automatic launch shape).
+
+* the 4M-node graph: initial positions at 20,000 sampled nodes and the
+  negatives of 20,000 sampled directed edges in the first and last epochs,
+  bit-exact against the oracle;
+* one synchronous (Jacobi) epoch of the whole 4M-node graph and of the
+  259k-node graph against the FP64 oracle, within 1e-5 x the output's
+  diameter (eta0 = 1/d_max, the step at which a hub stays inside the layout;
+  the same bar as the smaller cases);
+* one ATOMIC epoch of the 4M-node graph conserves the centroid (every pair
+  update adds +v and -v) within 1e-4 of the layout's extent.
+"""
+import numpy as np
+import pytest
+
+import synthgraph as S
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+SL = pytest.importorskip("paper_2608_01907_amd.snaplayout")
+torch = pytest.importorskip("torch")
+
+
+def _diam(Y):
+    return float(np.linalg.norm(Y.max(0) - Y.min(0)))
+
+
+@pytest.fixture(scope="module")
+def d3():
+    return S.cached("lj-like-4m", S.lj_like)
+
+
+@pytest.fixture(scope="module")
+def d3_dev(d3):
+    dev = torch.device("cuda:0")
+    return torch.from_numpy(d3.row_ptr).to(dev), torch.from_numpy(d3.col).to(dev)
+
+
+def test_d3_init_and_draws_bit_exact(d3, d3_dev):
+    rp, col = d3_dev
+    rng = np.random.default_rng(4)
+    nodes = rng.choice(d3.n, 20_000, replace=False)
+    edges = rng.choice(d3.nnz, 20_000, replace=False).astype(np.int64)
+    with SL.Layout(rp, col, d3.n, k=5, epochs=30, seed=0) as L:
+        assert L.info()["engine"] == SL.LAYOUT_ENGINE_GLOBAL
+        Y = L.positions()
+        assert np.array_equal(Y[nodes], O.init_positions_at(d3.n, 0, nodes).astype(np.float32))
+        for t in (0, 29):
+            got = SL.layout_debug_draws_at(L.h, t, edges, 5)
+            ref = O.draw_edges(d3.row_ptr, d3.n, 5, t, 0, edges)
+            assert np.array_equal(got, ref), t
+
+
+@pytest.mark.parametrize("which", ["lj-like-4m", "orkut-like-259k"])
+def test_full_size_jacobi_epoch(which, d3, d3_dev):
+    if which == "lj-like-4m":
+        g = d3
+        rp, col = d3_dev
+    else:
+        g = S.cached(which, S.orkut_like)
+        rp, col = g.row_ptr, g.col
+    eta0 = 1.0 / float(g.degrees().max())
+    Y0 = O.init_positions(g.n, 0).astype(np.float32)
+    ref = O.jacobi_epoch(g.row_ptr, g.col, g.n, 5, 0, 30, 0, Y0.astype(np.float64), eta0=eta0)
+    init = torch.from_numpy(Y0).to("cuda:0") if hasattr(rp, "is_cuda") else Y0
+    with SL.Layout(rp, col, g.n, k=5, epochs=30, seed=0, update_mode=SL.LAYOUT_JACOBI,
+                   eta0=eta0, init_pos=init) as L:
+        L.run(1)
+        Y = L.positions().astype(np.float64)
+    err = float(np.abs(Y - ref).max())
+    print(f"{which}: Jacobi epoch max error {err:.3e}, diameter {_diam(ref):.1f}", flush=True)
+    assert err <= 1e-5 * _diam(ref), (err, _diam(ref))
+
+
+def test_d3_atomic_epoch_conserves_centroid(d3, d3_dev):
+    rp, col = d3_dev
+    with SL.Layout(rp, col, d3.n, k=5, epochs=30, seed=0, update_mode=SL.LAYOUT_ATOMIC,
+                   hub_split_edges=1 << 30) as L:
+        Y0 = L.positions().astype(np.float64)
+        L.run(1)
+        Y1 = L.positions().astype(np.float64)
+    extent = float(np.abs(Y0).max())
+    drift = float(np.abs(Y1.mean(0) - Y0.mean(0)).max())
+    assert np.all(np.isfinite(Y1)) and drift <= 1e-4 * extent, (drift, extent)
