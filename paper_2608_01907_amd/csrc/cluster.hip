@@ -130,7 +130,8 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   int32_t moved = 0;
-  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
     const float2 p = Y[i];
     const double x = p.x, y = p.y;
     int32_t best = 0;

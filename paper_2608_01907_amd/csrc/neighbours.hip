@@ -68,17 +68,18 @@ __global__ void __launch_bounds__(256)
   uint32_t* b = bits + static_cast<int64_t>(q) * words;
   const int32_t r0 = row_ptr[i], r1 = row_ptr[i + 1];
   // hop 1
-  for (int32_t m = r0 + blockIdx.x * blockDim.x + threadIdx.x; m < r1;
-       m += gridDim.x * blockDim.x)
+  for (int64_t m = r0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; m < r1;
+       m += int64_t(gridDim.x) * blockDim.x)
     set_bit(b, col[m]);
   if (radius < 2) return;
   // hop 2: one neighbour row per wave
   const int32_t waves = blockDim.x >> 6;
   const int32_t lane = threadIdx.x & 63;
-  for (int32_t m = r0 + blockIdx.x * waves + (threadIdx.x >> 6); m < r1; m += gridDim.x * waves) {
+  for (int64_t m = r0 + int64_t(blockIdx.x) * waves + (threadIdx.x >> 6); m < r1;
+       m += int64_t(gridDim.x) * waves) {
     const int32_t j = col[m];
     const int32_t s0 = row_ptr[j], s1 = row_ptr[j + 1];
-    for (int32_t e = s0 + lane; e < s1; e += 64) set_bit(b, col[e]);
+    for (int64_t e = s0 + lane; e < s1; e += 64) set_bit(b, col[e]);
   }
 }
 
@@ -160,7 +161,8 @@ __global__ void __launch_bounds__(256)
   if (!any) return;
   const int shift_pre = pass > 0 ? 64 - 8 * pass : 0;  // bits above the current digit
   const int shift_dig = 56 - 8 * pass;
-  for (int32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < n; l += gridDim.x * blockDim.x) {
+  for (int64_t l = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; l < n;
+       l += int64_t(gridDim.x) * blockDim.x) {
     const float2 yl = Y[l];
 #pragma unroll
     for (int a = 0; a < kQueriesPerBlock; ++a) {

@@ -87,7 +87,8 @@ __global__ void __launch_bounds__(256)
     degree_argmax_kernel(const int32_t* __restrict__ row, int32_t n, uint64_t* best) {
   __shared__ uint64_t red[4];
   uint64_t k = 0;
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += int64_t(gridDim.x) * blockDim.x) {
     const uint64_t c = argmax_key(row[v + 1] - row[v], v);
     k = c > k ? c : k;
   }
@@ -99,7 +100,8 @@ __global__ void __launch_bounds__(256)
     bfs_start_kernel(int32_t* __restrict__ dist, int32_t n, const uint64_t* best,
                      int32_t* __restrict__ pivots, int32_t j) {
   const int32_t src = key_node(*best);
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += int64_t(gridDim.x) * blockDim.x)
     dist[v] = v == src ? 0 : -1;
   if (blockIdx.x == 0 && threadIdx.x == 0) pivots[j] = src;
 }
@@ -113,7 +115,8 @@ __global__ void __launch_bounds__(256)
                      int32_t* dist, int32_t n, int32_t level, int32_t* flags,
                      int32_t* __restrict__ heavy) {
   bool found = false;
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += int64_t(gridDim.x) * blockDim.x) {
     if (dist[v] != level) continue;
     const int32_t b = row[v], e = row[v + 1];
     if (e - b > kLightDegree) {
@@ -162,7 +165,8 @@ __global__ void __launch_bounds__(256)
   __shared__ uint64_t redc[4];
   uint64_t k = 0, cnt = 0;
   double s = 0.0;
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += int64_t(gridDim.x) * blockDim.x) {
     const int32_t d = dist[v];
     int32_t m;
     if (first) {
@@ -386,7 +390,8 @@ __global__ void __launch_bounds__(256)
     w2[threadIdx.x] = mu2 > 0.0 && mu2 > 1e-6 * mu1 ? eig[p + threadIdx.x] / sqrt(sqrt(mu2)) : 0.0;
   }
   __syncthreads();
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += int64_t(gridDim.x) * blockDim.x) {
     if (mind[v] < 0) {
       X[v] = make_float2(0.f, 0.f);
       continue;
@@ -413,7 +418,8 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x < static_cast<unsigned>(p)) xp[threadIdx.x] = X[pivots[threadIdx.x]];
   __syncthreads();
   double num = 0.0, den = 0.0;
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += int64_t(gridDim.x) * blockDim.x) {
     if (mind[v] < 0) continue;
     const float2 xv = X[v];
     for (int j = 0; j < p; ++j) {
@@ -439,7 +445,8 @@ __global__ void __launch_bounds__(256)
   __shared__ float red[4];
   const double s = sums[1] > 0.0 ? sums[0] / sums[1] : 1.0;
   float m = 0.f;
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += int64_t(gridDim.x) * blockDim.x) {
     if (mind[v] < 0) continue;
     const float2 x = X[v];
     const float2 y = make_float2(static_cast<float>(s * double(x.x)), static_cast<float>(s * double(x.y)));
@@ -456,7 +463,8 @@ __global__ void __launch_bounds__(256)
                       const unsigned* __restrict__ maxbits, float2* __restrict__ Y) {
   float R = __uint_as_float(*maxbits);
   if (!(R > 0.f)) R = 1.f;
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+  for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += int64_t(gridDim.x) * blockDim.x)
     if (mind[v] < 0) Y[v] = init_coords(v, seed, R);
 }
 
