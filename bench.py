@@ -42,6 +42,7 @@ PLAIN = {
     "orkut-like-259k": ("orkut_like", 5, 30),
     "sbm-2000": ("sbm_2000", 5, 50),
     "friendster-like-65m": ("gpu:friendster_like", 5, 30),
+    "friendster-full-65m": ("gpu:friendster_full", 5, 30),
 }
 KERNEL_SOURCES = ["paper_2608_01907_amd/csrc/kernels.hpp", "paper_2608_01907_amd/csrc/rng.hpp",
                   "paper_2608_01907_amd/csrc/desc.hpp"]
@@ -113,11 +114,13 @@ def bench_plain(args):
     seed = 0
     t0 = time.perf_counter()
     dev = torch.device("cuda:0")
-    if maker == "gpu:friendster_like":
-        # generated on the device (10^9 edges): inputs never leave HBM
+    if maker.startswith("gpu:"):
+        # generated on the device (10^9 or 1.8 x 10^9 edges): inputs never leave HBM
         from synthgraph import gpu as G
-        rp_d, col_d, labels_d = G.friendster_like_gpu(seed=0)
+        make = G.friendster_full_gpu if maker == "gpu:friendster_full" else G.friendster_like_gpu
+        rp_d, col_d, labels_d = make(seed=0)
         del labels_d
+        torch.cuda.empty_cache()
         row_ptr = rp_d.cpu().numpy()
         g = S.Graph(row_ptr, np.zeros(0, np.int32), len(row_ptr) - 1, None, args.workload)
         nnz = int(row_ptr[-1])

@@ -167,6 +167,16 @@ int layout_create_ex(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, 
                      int32_t k, int32_t epochs, uint64_t seed, const layout_opts *opts,
                      int32_t inputs_on_device, layout_t **out);
 
+/* As layout_create_ex with 64-bit row pointers (row_ptr: n+1 int64), for
+ * graphs of 2^31 or more directed edges (the com-friendster shape of the
+ * paper's case study: 1.8 billion undirected edges).  Internally every graph
+ * uses 64-bit row pointers and chunk starts; the int32 entry points widen
+ * theirs on the device.  Edge counts up to 2^31 x 16 (chunk indices stay
+ * 32-bit); the degree-weighted alias table needs nnz < 2^32. */
+int layout_create64(const int64_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t dim,
+                    int32_t k, int32_t epochs, uint64_t seed, const layout_opts *opts,
+                    int32_t inputs_on_device, layout_t **out);
+
 /* Enqueues min(count, remaining) epochs on the handle's stream and returns
  * without waiting.  Returns LAYOUT_E_DONE when no epoch remains. */
 int layout_epoch(layout_t *L, int32_t count);
@@ -322,10 +332,10 @@ int layout_debug_conflicts(layout_t *L, int32_t count, int64_t *stores, int64_t 
 int layout_bench_atomics(int32_t reps, int32_t spread, double *fsum_out, int64_t *isum_out,
                          int64_t *adds_out, float *ms);
 
-/* Copies the chunk table: begin[n_chunks + 1] (first directed edge of each
- * lane chunk, begin[n_chunks] = nnz) and src[n_chunks] (row holding that
- * edge).  n_chunks comes from layout_get_info. */
-int layout_debug_chunks(const layout_t *L, int32_t *begin_out, int32_t *src_out);
+/* Copies the chunk table: begin[n_chunks + 1] (int64, first directed edge of
+ * each lane chunk, begin[n_chunks] = nnz) and src[n_chunks] (row holding
+ * that edge).  n_chunks comes from layout_get_info. */
+int layout_debug_chunks(const layout_t *L, int64_t *begin_out, int32_t *src_out);
 
 /* Copies the alias table (n entries each) used by LAYOUT_NEG_DEGREE. */
 int layout_debug_alias(const layout_t *L, uint32_t *thr_out, uint32_t *alias_out);

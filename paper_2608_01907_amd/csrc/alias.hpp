@@ -41,7 +41,7 @@ __device__ __forceinline__ AliasScanItem operator+(const AliasScanItem& a,
 }
 
 // Weight of item s: weights[s] when given, else the degree of s.
-__device__ __forceinline__ int64_t alias_weight(const int32_t* __restrict__ row_ptr,
+__device__ __forceinline__ int64_t alias_weight(const int64_t* __restrict__ row_ptr,
                                                 const uint32_t* __restrict__ weights, int64_t s) {
   return weights ? static_cast<int64_t>(weights[s])
                  : static_cast<int64_t>(row_ptr[s + 1] - row_ptr[s]);
@@ -49,7 +49,7 @@ __device__ __forceinline__ int64_t alias_weight(const int32_t* __restrict__ row_
 
 // Item s of the scan: heavy/light classification of M_s = w_s * n against W.
 struct AliasLoad {
-  const int32_t* row_ptr;
+  const int64_t* row_ptr;
   const uint32_t* weights;  // nullable: degrees
   int64_t n, W;
   __device__ AliasScanItem operator()(int64_t s) const {
@@ -120,7 +120,7 @@ __device__ __forceinline__ uint32_t alias_threshold(int64_t own, int64_t W) {
 }
 
 // Phase 4: one thread per item writes thr/alias.
-static __global__ void alias_fill_kernel(const int32_t* __restrict__ row_ptr,
+static __global__ void alias_fill_kernel(const int64_t* __restrict__ row_ptr,
                                   const uint32_t* __restrict__ weights, int64_t n, int64_t W,
                                   const AliasScanItem* __restrict__ grand,
                                   const int32_t* __restrict__ heavy_item,

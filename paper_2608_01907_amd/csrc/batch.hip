@@ -49,11 +49,11 @@ struct layout_batch {
   std::vector<uint8_t> in_lds;
   std::vector<GraphDesc> desc;  // by graph index
   // packed device arrays
-  int32_t* d_row = nullptr;
+  int64_t* d_row = nullptr;
   int32_t* d_col = nullptr;
   float2* d_Y = nullptr;
   float2* d_D = nullptr;
-  int32_t* d_chunk_begin = nullptr;
+  int64_t* d_chunk_begin = nullptr;
   int32_t* d_chunk_src = nullptr;
   uint32_t* d_thr = nullptr;
   uint32_t* d_alias = nullptr;
@@ -106,7 +106,7 @@ int build_global_chunks(layout_batch_t* B) {
     int64_t nc = 0;
     if (B->nnz[g] > 0) {
       const int rc = build_chunk_table(B->stream, d.row_ptr, B->n[g], B->nnz[g], B->bundle, B->hub,
-                                       const_cast<int32_t*>(d.chunk_begin),
+                                       const_cast<int64_t*>(d.chunk_begin),
                                        const_cast<int32_t*>(d.chunk_src), &nc);
       if (rc != LAYOUT_OK) return rc;
     }
@@ -468,10 +468,10 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
 
   // packed allocations
   int rc;
-  if ((rc = balloc(B, reinterpret_cast<void**>(&B->d_row), sizeof(int32_t) * size_t(rows), "row_ptr")) ||
+  if ((rc = balloc(B, reinterpret_cast<void**>(&B->d_row), sizeof(int64_t) * size_t(rows), "row_ptr")) ||
       (rc = balloc(B, reinterpret_cast<void**>(&B->d_col), sizeof(int32_t) * size_t(B->total_nnz), "col")) ||
       (rc = balloc(B, reinterpret_cast<void**>(&B->d_Y), sizeof(float2) * size_t(B->nodes), "positions")) ||
-      (rc = balloc(B, reinterpret_cast<void**>(&B->d_chunk_begin), sizeof(int32_t) * size_t(chunks), "chunk begin")) ||
+      (rc = balloc(B, reinterpret_cast<void**>(&B->d_chunk_begin), sizeof(int64_t) * size_t(chunks), "chunk begin")) ||
       (rc = balloc(B, reinterpret_cast<void**>(&B->d_chunk_src), sizeof(int32_t) * size_t(chunks), "chunk src")) ||
       (rc = balloc(B, reinterpret_cast<void**>(&B->d_err), sizeof(uint32_t), "flag")) ||
       (rc = balloc(B, reinterpret_cast<void**>(&B->d_table_global), sizeof(GraphDesc) * size_t(count), "table")) ||
@@ -499,11 +499,12 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
   B->desc.resize(count);
   for (int32_t g = 0; g < count; ++g) {
     const layout_graph& gr = graphs[g];
-    int32_t* row = B->d_row + B->row_off[g];
+    int64_t* row = B->d_row + B->row_off[g];
     int32_t* col = B->d_col + B->edge_off[g];
     float2* Y = B->d_Y + B->node_off[g];
-    e = hipMemcpyAsync(row, gr.row_ptr, sizeof(int32_t) * (size_t(gr.n) + 1), kind, B->stream);
-    if (e == hipSuccess && B->nnz[g] > 0)
+    if ((rc = upload_row_ptr(B->stream, gr.row_ptr, gr.n, inputs_on_device != 0, row)) != LAYOUT_OK)
+      return bail(rc);
+    if (B->nnz[g] > 0)
       e = hipMemcpyAsync(col, gr.col_idx, sizeof(int32_t) * size_t(B->nnz[g]), kind, B->stream);
     if (e != hipSuccess) return bail(hip_fail(e, "copying a graph"));
     if ((rc = validate_csr(B->stream, row, col, gr.n, B->nnz[g], B->d_err)) != LAYOUT_OK) {
@@ -532,7 +533,7 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
       d.hub = B->lds_hub[g];
       int64_t nc = 0;
       if ((rc = build_chunk_table(B->stream, row, gr.n, B->nnz[g], B->lds_bundle[g], d.hub,
-                                  const_cast<int32_t*>(d.chunk_begin),
+                                  const_cast<int64_t*>(d.chunk_begin),
                                   const_cast<int32_t*>(d.chunk_src), &nc)) != LAYOUT_OK)
         return bail(rc);
       d.n_chunks = nc;

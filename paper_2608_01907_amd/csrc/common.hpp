@@ -52,22 +52,26 @@ inline int64_t chunk_bound(int64_t nnz, int32_t bundle, int32_t hub) {
 }
 
 // Preprocessing shared by every entry point (snaplayout.hip).
-int build_chunk_table(hipStream_t stream, const int32_t* d_row, int32_t n, int64_t nnz,
-                      int32_t bundle, int32_t hub, int32_t* d_chunk_begin, int32_t* d_chunk_src,
+int build_chunk_table(hipStream_t stream, const int64_t* d_row, int32_t n, int64_t nnz,
+                      int32_t bundle, int32_t hub, int64_t* d_chunk_begin, int32_t* d_chunk_src,
                       int64_t* n_chunks);
 // Integer alias table for the weights d_weights[0..n) (nullable: degrees from
 // d_row), W = their sum, 0 < W < 2^32.
-int build_alias_table(hipStream_t stream, const int32_t* d_row, const uint32_t* d_weights,
+int build_alias_table(hipStream_t stream, const int64_t* d_row, const uint32_t* d_weights,
                       int32_t n, int64_t W, uint32_t* d_thr, uint32_t* d_alias);
+// Copies an int32 row_ptr[n + 1] (host, or device when on_device) into the
+// 64-bit device row pointers every kernel reads.  Synchronises the stream.
+int upload_row_ptr(hipStream_t stream, const int32_t* row_ptr, int32_t n, bool on_device,
+                   int64_t* d_row);
 // The alias table of caller weights (host, or device when on_device; n
 // entries whose sum W must satisfy 0 < W < 2^32, else LAYOUT_E_INVALID_ARG).
 // Synchronises the stream.
-int upload_weights_and_build_alias(hipStream_t stream, const int32_t* d_row,
+int upload_weights_and_build_alias(hipStream_t stream, const int64_t* d_row,
                                    const uint32_t* weights, int32_t n, bool on_device,
                                    uint32_t* d_thr, uint32_t* d_alias);
 // Device validation of one CSR (LAYOUT_E_BAD_GRAPH with a message on failure);
 // err is a device word of scratch.
-int validate_csr(hipStream_t stream, const int32_t* d_row, const int32_t* d_col, int32_t n,
+int validate_csr(hipStream_t stream, const int64_t* d_row, const int32_t* d_col, int32_t n,
                  int64_t nnz, uint32_t* d_err);
 // Seeded uniform initial positions; dim 3 writes float4 positions through the
 // float2 pointer (n float4 = 2n float2 of storage).
@@ -78,7 +82,7 @@ void launch_init_positions(hipStream_t stream, float2* d_Y, int32_t n, uint64_t 
 // pivots x n) the hop distances; *pivots_used the pivots taken.  Synchronises
 // the stream (the scratch it allocates is freed on return).
 constexpr int32_t kDefaultPivots = 50;
-int pmds_positions(hipStream_t stream, const int32_t* d_row, const int32_t* d_col, int32_t n,
+int pmds_positions(hipStream_t stream, const int64_t* d_row, const int32_t* d_col, int32_t n,
                    int32_t pivots, uint64_t seed, float2* d_Y, int32_t* d_pivots_out,
                    int32_t* d_dist_out, int32_t* pivots_used);
 void launch_fill_zero(hipStream_t stream, float2* d_p, int64_t n);
@@ -97,7 +101,7 @@ int run_conflict_epochs(hipStream_t stream, const GraphDesc* d_table, int32_t n,
                         int64_t* stores, int64_t* conflicts, int64_t* untracked);
 // k_i and |R_i ∩ K_i| of the NP metric for host query nodes (neighbours.hip;
 // host outputs, count entries).  Synchronises the stream.
-int neighbourhood_counts(hipStream_t stream, const int32_t* d_row, const int32_t* d_col,
+int neighbourhood_counts(hipStream_t stream, const int64_t* d_row, const int32_t* d_col,
                          const float2* d_Y, int32_t n, const int32_t* nodes, int32_t count,
                          int32_t radius, int32_t* k_out, int32_t* inter_out);
 

@@ -13,9 +13,9 @@ namespace snap {
 enum : int { kStore = 0, kAtomic = 1, kJacobi = 2 };
 
 struct GraphDesc {
-  const int32_t* row_ptr;
+  const int64_t* row_ptr;
   const int32_t* col;
-  const int32_t* chunk_begin;  // first edge of each chunk; [n_chunks] = nnz
+  const int64_t* chunk_begin;  // first edge of each chunk; [n_chunks] = nnz
   const int32_t* chunk_src;    // row holding the first edge of each chunk
   float2* Y;
   float2* D;  // Jacobi accumulator (JACOBI only)

@@ -113,7 +113,7 @@ static __global__ void __launch_bounds__(256)
 // an FP64 accumulator, which bounds the rounding of any partial sum to 256
 // terms.
 static __global__ void __launch_bounds__(256)
-    pair_energy_kernel(const float2* __restrict__ Y, const int32_t* __restrict__ row_ptr,
+    pair_energy_kernel(const float2* __restrict__ Y, const int64_t* __restrict__ row_ptr,
                        int32_t n, float gamma, double* __restrict__ out) {
   __shared__ float2 ty[256];
   __shared__ float td[256];

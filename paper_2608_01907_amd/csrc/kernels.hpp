@@ -632,7 +632,7 @@ static __global__ void fill_zero_kernel(float2* __restrict__ p, int64_t n) {
 // ------------------------------------------------------------- preprocessing
 // Largest r in [0, n] with row_ptr[r] <= e (the row holding edge e when the
 // row pointers are monotone and row_ptr[n] > e).
-__device__ __forceinline__ int32_t row_of(const int32_t* __restrict__ row_ptr, int32_t n,
+__device__ __forceinline__ int32_t row_of(const int64_t* __restrict__ row_ptr, int32_t n,
                                           int64_t e) {
   int32_t lo = 0, hi = n;
   while (lo < hi) {
@@ -655,7 +655,7 @@ enum : uint32_t {
   kErrAsymmetric = 64u,   // (i, j) present without (j, i)
 };
 
-static __global__ void validate_rows_kernel(const int32_t* __restrict__ row_ptr, int32_t n, int64_t nnz,
+static __global__ void validate_rows_kernel(const int64_t* __restrict__ row_ptr, int32_t n, int64_t nnz,
                                      uint32_t* __restrict__ err) {
   const int64_t v = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (v > n) return;
@@ -666,7 +666,7 @@ static __global__ void validate_rows_kernel(const int32_t* __restrict__ row_ptr,
   if (bad) atomicOr(err, bad);
 }
 
-static __global__ void validate_edges_kernel(const int32_t* __restrict__ row_ptr,
+static __global__ void validate_edges_kernel(const int64_t* __restrict__ row_ptr,
                                       const int32_t* __restrict__ col, int32_t n, int64_t nnz,
                                       uint32_t* __restrict__ err) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -680,10 +680,10 @@ static __global__ void validate_edges_kernel(const int32_t* __restrict__ row_ptr
     if (j == i) bad |= kErrSelfLoop;
     if (e > row_ptr[i] && col[e - 1] >= j) bad |= kErrUnsorted;
     // the reverse edge (j, i) must exist: binary search row j
-    int32_t lo = row_ptr[j], hi = row_ptr[j + 1] - 1;
+    int64_t lo = row_ptr[j], hi = row_ptr[j + 1] - 1;
     bool found = false;
     while (lo <= hi) {
-      const int32_t mid = lo + ((hi - lo) >> 1);
+      const int64_t mid = lo + ((hi - lo) >> 1);
       const int32_t v = col[mid];
       if (v == i) {
         found = true;

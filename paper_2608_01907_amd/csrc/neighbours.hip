@@ -60,13 +60,13 @@ __device__ __forceinline__ void set_bit(uint32_t* bits, int32_t v) {
 }
 
 __global__ void __launch_bounds__(256)
-    ring_mark_kernel(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    ring_mark_kernel(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                      NpState* __restrict__ st, int32_t radius, uint32_t* __restrict__ bits,
                      int64_t words) {
   const int32_t q = blockIdx.y;
   const int32_t i = st[q].node;
   uint32_t* b = bits + static_cast<int64_t>(q) * words;
-  const int32_t r0 = row_ptr[i], r1 = row_ptr[i + 1];
+  const int64_t r0 = row_ptr[i], r1 = row_ptr[i + 1];
   // hop 1
   for (int64_t m = r0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; m < r1;
        m += int64_t(gridDim.x) * blockDim.x)
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(256)
   for (int64_t m = r0 + int64_t(blockIdx.x) * waves + (threadIdx.x >> 6); m < r1;
        m += int64_t(gridDim.x) * waves) {
     const int32_t j = col[m];
-    const int32_t s0 = row_ptr[j], s1 = row_ptr[j + 1];
+    const int64_t s0 = row_ptr[j], s1 = row_ptr[j + 1];
     for (int64_t e = s0 + lane; e < s1; e += 64) set_bit(b, col[e]);
   }
 }
@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(256)
 
 }  // namespace
 
-int neighbourhood_counts(hipStream_t stream, const int32_t* d_row, const int32_t* d_col,
+int neighbourhood_counts(hipStream_t stream, const int64_t* d_row, const int32_t* d_col,
                          const float2* d_Y, int32_t n, const int32_t* nodes, int32_t count,
                          int32_t radius, int32_t* k_out, int32_t* inter_out) {
   if (count <= 0) return LAYOUT_OK;

@@ -84,12 +84,12 @@ struct MaxF32 {
 
 // ---------------------------------------------------------------- pivots/BFS
 __global__ void __launch_bounds__(256)
-    degree_argmax_kernel(const int32_t* __restrict__ row, int32_t n, uint64_t* best) {
+    degree_argmax_kernel(const int64_t* __restrict__ row, int32_t n, uint64_t* best) {
   __shared__ uint64_t red[4];
   uint64_t k = 0;
   for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
        v += int64_t(gridDim.x) * blockDim.x) {
-    const uint64_t c = argmax_key(row[v + 1] - row[v], v);
+    const uint64_t c = argmax_key(static_cast<int32_t>(row[v + 1] - row[v]), v);
     k = c > k ? c : k;
   }
   k = block_reduce(k, MaxU64{}, red);
@@ -111,19 +111,19 @@ __global__ void __launch_bounds__(256)
 // same value, so no atomics are needed on dist.  flags[0]: a node was
 // discovered; flags[1]: queued long rows.
 __global__ void __launch_bounds__(256)
-    bfs_level_kernel(const int32_t* __restrict__ row, const int32_t* __restrict__ col,
+    bfs_level_kernel(const int64_t* __restrict__ row, const int32_t* __restrict__ col,
                      int32_t* dist, int32_t n, int32_t level, int32_t* flags,
                      int32_t* __restrict__ heavy) {
   bool found = false;
   for (int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
        v += int64_t(gridDim.x) * blockDim.x) {
     if (dist[v] != level) continue;
-    const int32_t b = row[v], e = row[v + 1];
+    const int64_t b = row[v], e = row[v + 1];
     if (e - b > kLightDegree) {
       heavy[atomicAdd(&flags[1], 1)] = v;
       continue;
     }
-    for (int32_t q = b; q < e; ++q) {
+    for (int64_t q = b; q < e; ++q) {
       const int32_t u = col[q];
       if (dist[u] < 0) {
         dist[u] = level + 1;
@@ -135,15 +135,15 @@ __global__ void __launch_bounds__(256)
 }
 
 __global__ void __launch_bounds__(256)
-    bfs_heavy_kernel(const int32_t* __restrict__ row, const int32_t* __restrict__ col,
+    bfs_heavy_kernel(const int64_t* __restrict__ row, const int32_t* __restrict__ col,
                      int32_t* dist, int32_t level, int32_t* flags,
                      const int32_t* __restrict__ heavy) {
   const int32_t count = flags[1];
   bool found = false;
   for (int32_t h = blockIdx.x; h < count; h += gridDim.x) {
     const int32_t v = heavy[h];
-    const int32_t e = row[v + 1];
-    for (int32_t q = row[v] + threadIdx.x; q < e; q += blockDim.x) {
+    const int64_t e = row[v + 1];
+    for (int64_t q = row[v] + threadIdx.x; q < e; q += blockDim.x) {
       const int32_t u = col[q];
       if (dist[u] < 0) {
         dist[u] = level + 1;
@@ -491,7 +491,7 @@ int grid_for(int64_t items) {
 
 }  // namespace
 
-int pmds_positions(hipStream_t stream, const int32_t* d_row, const int32_t* d_col, int32_t n,
+int pmds_positions(hipStream_t stream, const int64_t* d_row, const int32_t* d_col, int32_t n,
                    int32_t pivots, uint64_t seed, float2* d_Y, int32_t* d_pivots_out,
                    int32_t* d_dist_out, int32_t* pivots_used) {
   if (pivots_used) *pivots_used = 0;
@@ -626,10 +626,11 @@ int layout_pmds(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, int32
     if (r == hipSuccess) own.ptrs.push_back(*p);
     return r;
   };
-  int32_t *d_row = nullptr, *d_col = nullptr, *d_piv = nullptr, *d_dist = nullptr;
+  int64_t* d_row = nullptr;
+  int32_t *d_col = nullptr, *d_piv = nullptr, *d_dist = nullptr;
   float2* d_Y = nullptr;
   uint32_t* d_err = nullptr;
-  e = dev(sizeof(int32_t) * (size_t(n) + 1), reinterpret_cast<void**>(&d_row));
+  e = dev(sizeof(int64_t) * (size_t(n) + 1), reinterpret_cast<void**>(&d_row));
   if (e == hipSuccess) e = dev(sizeof(int32_t) * size_t(nnz), reinterpret_cast<void**>(&d_col));
   if (e == hipSuccess) e = dev(sizeof(int32_t) * kMaxPivots, reinterpret_cast<void**>(&d_piv));
   if (e == hipSuccess && dist_out)
@@ -638,11 +639,12 @@ int layout_pmds(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, int32
   if (e == hipSuccess) e = dev(sizeof(uint32_t), reinterpret_cast<void**>(&d_err));
   if (e != hipSuccess) return hip_fail(e, "PMDS buffers");
   const hipMemcpyKind kind = inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  e = hipMemcpyAsync(d_row, row_ptr, sizeof(int32_t) * (size_t(n) + 1), kind, stream);
-  if (e == hipSuccess && nnz > 0)
+  int rc = upload_row_ptr(stream, row_ptr, n, inputs_on_device != 0, d_row);
+  if (rc != LAYOUT_OK) return rc;
+  if (nnz > 0)
     e = hipMemcpyAsync(d_col, col_idx, sizeof(int32_t) * size_t(nnz), kind, stream);
   if (e != hipSuccess) return hip_fail(e, "copying the graph");
-  int rc = validate_csr(stream, d_row, d_col, n, nnz, d_err);
+  rc = validate_csr(stream, d_row, d_col, n, nnz, d_err);
   if (rc != LAYOUT_OK) return rc;
   int32_t used = 0;
   rc = pmds_positions(stream, d_row, d_col, n, p, seed, d_Y, d_piv, d_dist, &used);

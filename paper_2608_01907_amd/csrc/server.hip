@@ -112,8 +112,9 @@ namespace {
 
 int64_t footprint_of(const layout_server_t* S, const Job& j, int32_t bundle, int32_t hub) {
   const int64_t cap = j.nnz > 0 ? chunk_bound(j.nnz, bundle, hub) : 0;
-  // row_ptr, col, positions, chunk table, alias table (weighted negatives)
-  int64_t b = 4 * (int64_t(j.n) + 1) + 4 * j.nnz + 8 * int64_t(j.n) + 8 * cap + 4;
+  // row_ptr (64-bit), col, positions, chunk table (64-bit begin + 32-bit source),
+  // alias table (weighted negatives)
+  int64_t b = 8 * (int64_t(j.n) + 1) + 4 * j.nnz + 8 * int64_t(j.n) + 12 * cap + 8;
   if (S->opts.neg_weights != LAYOUT_NEG_UNIFORM) b += 8 * int64_t(j.n);
   return b;
 }
@@ -144,20 +145,21 @@ int jalloc(Job& j, void** p, size_t bytes, const char* what) {
 
 // Device setup of an admitted job (scheduler thread).
 int setup_job(layout_server_t* S, Job& j) {
-  int32_t *row = nullptr, *col = nullptr, *cb = nullptr, *cs = nullptr;
+  int64_t *row = nullptr, *cb = nullptr;
+  int32_t *col = nullptr, *cs = nullptr;
   float2* Y = nullptr;
   uint32_t *thr = nullptr, *alias = nullptr;
   j.chunk_cap = j.nnz > 0 ? chunk_bound(j.nnz, j.bundle, j.hub) : 0;
   int rc;
-  if ((rc = jalloc(j, reinterpret_cast<void**>(&row), 4 * (size_t(j.n) + 1), "row_ptr")) ||
+  if ((rc = jalloc(j, reinterpret_cast<void**>(&row), 8 * (size_t(j.n) + 1), "row_ptr")) ||
       (rc = jalloc(j, reinterpret_cast<void**>(&col), 4 * size_t(j.nnz), "col")) ||
       (rc = jalloc(j, reinterpret_cast<void**>(&Y), 8 * size_t(j.n), "positions")) ||
-      (rc = jalloc(j, reinterpret_cast<void**>(&cb), 4 * size_t(j.chunk_cap + 1), "chunk begin")) ||
+      (rc = jalloc(j, reinterpret_cast<void**>(&cb), 8 * size_t(j.chunk_cap + 1), "chunk begin")) ||
       (rc = jalloc(j, reinterpret_cast<void**>(&cs), 4 * size_t(j.chunk_cap), "chunk src")))
     return rc;
-  hipError_t e = hipMemcpyAsync(row, j.row.data(), 4 * (size_t(j.n) + 1), hipMemcpyHostToDevice,
-                                S->stream);
-  if (e == hipSuccess && j.nnz > 0)
+  if ((rc = upload_row_ptr(S->stream, j.row.data(), j.n, false, row)) != LAYOUT_OK) return rc;
+  hipError_t e = hipSuccess;
+  if (j.nnz > 0)
     e = hipMemcpyAsync(col, j.col.data(), 4 * size_t(j.nnz), hipMemcpyHostToDevice, S->stream);
   if (e != hipSuccess) return hip_fail(e, "copying a job");
   if ((rc = validate_csr(S->stream, row, col, j.n, j.nnz, S->d_err)) != LAYOUT_OK) return rc;

@@ -227,8 +227,8 @@ int launch_epochs(layout_t* L, int32_t count) {
 
 // Row-aligned chunk table (chunks.hpp), built on the device.  begin/src must
 // hold chunk_bound(nnz, bundle, hub) (+1 for begin) entries.
-int snap::build_chunk_table(hipStream_t stream, const int32_t* d_row, int32_t n, int64_t nnz,
-                            int32_t bundle, int32_t hub, int32_t* d_chunk_begin,
+int snap::build_chunk_table(hipStream_t stream, const int64_t* d_row, int32_t n, int64_t nnz,
+                            int32_t bundle, int32_t hub, int64_t* d_chunk_begin,
                             int32_t* d_chunk_src, int64_t* n_chunks) {
   const int64_t tiles = std::max<int64_t>(1, scan_tiles(n));
   void* tmp = nullptr;
@@ -263,7 +263,7 @@ int snap::build_chunk_table(hipStream_t stream, const int32_t* d_row, int32_t n,
 
 // Alias table for weights w_s = degree(s), W = sum w = nnz, built on the
 // device (temporary buffers freed before returning).
-int snap::build_alias_table(hipStream_t stream, const int32_t* d_row, const uint32_t* d_weights,
+int snap::build_alias_table(hipStream_t stream, const int64_t* d_row, const uint32_t* d_weights,
                             int32_t n, int64_t W, uint32_t* d_thr, uint32_t* d_alias) {
   const int64_t tiles = std::max<int64_t>(1, scan_tiles(n));
   void* tmp = nullptr;
@@ -293,7 +293,39 @@ int snap::build_alias_table(hipStream_t stream, const int32_t* d_row, const uint
   return LAYOUT_OK;
 }
 
-int snap::upload_weights_and_build_alias(hipStream_t stream, const int32_t* d_row,
+namespace {
+__global__ void widen_i32_kernel(const int32_t* __restrict__ src, int64_t* __restrict__ dst,
+                                 int64_t count) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[i];
+}
+}  // namespace
+
+int snap::upload_row_ptr(hipStream_t stream, const int32_t* row_ptr, int32_t n, bool on_device,
+                         int64_t* d_row) {
+  const size_t count = size_t(n) + 1;
+  hipError_t e = hipSuccess;
+  if (!on_device) {
+    std::vector<int64_t> h(row_ptr, row_ptr + count);
+    e = hipMemcpyAsync(d_row, h.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);  // h is read by the copy
+  } else {
+    int32_t* tmp = nullptr;
+    e = hipMalloc(&tmp, sizeof(int32_t) * count);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(tmp, row_ptr, sizeof(int32_t) * count, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(widen_i32_kernel, dim3(div_up(int64_t(count), 256)), dim3(256), 0, stream,
+                         tmp, d_row, int64_t(count));
+      e = hipStreamSynchronize(stream);
+    }
+    if (tmp) (void)hipFree(tmp);
+  }
+  if (e != hipSuccess) return hip_fail(e, "copying row_ptr");
+  return LAYOUT_OK;
+}
+
+int snap::upload_weights_and_build_alias(hipStream_t stream, const int64_t* d_row,
                                          const uint32_t* weights, int32_t n, bool on_device,
                                          uint32_t* d_thr, uint32_t* d_alias) {
   std::vector<uint32_t> w(static_cast<size_t>(n));
@@ -550,7 +582,7 @@ int snap::allow_lds(int k, int bytes, int dim) {
   });
 }
 
-int snap::validate_csr(hipStream_t stream, const int32_t* d_row, const int32_t* d_col, int32_t n,
+int snap::validate_csr(hipStream_t stream, const int64_t* d_row, const int32_t* d_col, int32_t n,
                        int64_t nnz, uint32_t* d_err) {
   hipError_t e = hipMemsetAsync(d_err, 0, sizeof(uint32_t), stream);
   if (e != hipSuccess) return hip_fail(e, "clearing the validation flag");
@@ -687,9 +719,14 @@ int layout_create(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, int
   return layout_create_ex(row_ptr, col_idx, n, dim, k, epochs, seed, &o, 0, out);
 }
 
-int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, int32_t dim,
-                     int32_t k, int32_t epochs, uint64_t seed, const layout_opts* opts,
-                     int32_t inputs_on_device, layout_t** out) {
+namespace {
+
+// Both row_ptr widths: row32 (int32 CSR) or row64 (int64 row pointers), one
+// of them non-null.
+int create_impl(const int32_t* row32, const int64_t* row64, const int32_t* col_idx, int32_t n,
+                int32_t dim, int32_t k, int32_t epochs, uint64_t seed, const layout_opts* opts,
+                int32_t inputs_on_device, layout_t** out) {
+  const void* row_ptr = row32 ? static_cast<const void*>(row32) : static_cast<const void*>(row64);
   g_last_error.clear();
   if (!out) return fail(LAYOUT_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
@@ -755,16 +792,19 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
   }
 
   // nnz from row_ptr[n]
-  int32_t nnz32 = 0;
+  int64_t nnz = 0;
   if (inputs_on_device) {
-    hipError_t e = hipMemcpy(&nnz32, row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost);
+    int32_t last32 = 0;
+    hipError_t e = row32 ? hipMemcpy(&last32, row32 + n, sizeof(int32_t), hipMemcpyDeviceToHost)
+                         : hipMemcpy(&nnz, row64 + n, sizeof(int64_t), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return bail(hip_fail(e, "reading row_ptr[n]"));
+    if (row32) nnz = last32;
   } else {
-    nnz32 = row_ptr[n];
+    nnz = row32 ? int64_t(row32[n]) : row64[n];
   }
-  if (nnz32 < 0) return bail(fail(LAYOUT_E_BAD_GRAPH, "row_ptr[n] = %d", nnz32));
-  if (nnz32 > 0 && !col_idx) return bail(fail(LAYOUT_E_INVALID_ARG, "col_idx is NULL"));
-  L->nnz = nnz32;
+  if (nnz < 0) return bail(fail(LAYOUT_E_BAD_GRAPH, "row_ptr[n] = %lld", (long long)nnz));
+  if (nnz > 0 && !col_idx) return bail(fail(LAYOUT_E_INVALID_ARG, "col_idx is NULL"));
+  L->nnz = nnz;
 
   // engine and launch shape
   const DeviceProps& dp = device_props();
@@ -821,17 +861,17 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
 
   // device buffers
   int rc;
-  int32_t* d_row = nullptr;
+  int64_t* d_row = nullptr;
   int32_t* d_col = nullptr;
   int32_t* d_chunk = nullptr;
-  int32_t* d_chunk_begin = nullptr;
+  int64_t* d_chunk_begin = nullptr;
   float2* d_Y = nullptr;
   float2* d_D = nullptr;
   uint32_t* d_err = nullptr;
-  if ((rc = alloc(L, reinterpret_cast<void**>(&d_row), sizeof(int32_t) * (size_t(n) + 1), "row_ptr")) ||
+  if ((rc = alloc(L, reinterpret_cast<void**>(&d_row), sizeof(int64_t) * (size_t(n) + 1), "row_ptr")) ||
       (rc = alloc(L, reinterpret_cast<void**>(&d_col), sizeof(int32_t) * size_t(L->nnz), "col")) ||
       (rc = alloc(L, reinterpret_cast<void**>(&d_chunk), sizeof(int32_t) * size_t(chunk_cap), "chunk src")) ||
-      (rc = alloc(L, reinterpret_cast<void**>(&d_chunk_begin), sizeof(int32_t) * size_t(chunk_cap + 1), "chunk begin")) ||
+      (rc = alloc(L, reinterpret_cast<void**>(&d_chunk_begin), sizeof(int64_t) * size_t(chunk_cap + 1), "chunk begin")) ||
       (rc = alloc(L, reinterpret_cast<void**>(&d_Y), size_t(pos_bytes) * size_t(n), "positions")) ||
       (rc = alloc(L, reinterpret_cast<void**>(&d_err), sizeof(uint32_t), "flag")) ||
       (rc = alloc(L, reinterpret_cast<void**>(&L->d_table), sizeof(GraphDesc), "table")) ||
@@ -842,7 +882,13 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
     return bail(rc);
 
   const hipMemcpyKind kind = inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  hipError_t e = hipMemcpyAsync(d_row, row_ptr, sizeof(int32_t) * (size_t(n) + 1), kind, L->stream);
+  hipError_t e = hipSuccess;
+  if (row32) {
+    if ((rc = upload_row_ptr(L->stream, row32, n, inputs_on_device != 0, d_row)) != LAYOUT_OK)
+      return bail(rc);
+  } else {
+    e = hipMemcpyAsync(d_row, row64, sizeof(int64_t) * (size_t(n) + 1), kind, L->stream);
+  }
   if (e == hipSuccess && L->nnz > 0)
     e = hipMemcpyAsync(d_col, col_idx, sizeof(int32_t) * size_t(L->nnz), kind, L->stream);
   if (e != hipSuccess) return bail(hip_fail(e, "copying the graph"));
@@ -936,6 +982,24 @@ int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, 
     return bail(rc);
   *out = L;
   return LAYOUT_OK;
+}
+
+}  // namespace
+
+int layout_create_ex(const int32_t* row_ptr, const int32_t* col_idx, int32_t n, int32_t dim,
+                     int32_t k, int32_t epochs, uint64_t seed, const layout_opts* opts,
+                     int32_t inputs_on_device, layout_t** out) {
+  if (!row_ptr) return fail(LAYOUT_E_INVALID_ARG, "row_ptr is NULL");
+  return create_impl(row_ptr, nullptr, col_idx, n, dim, k, epochs, seed, opts, inputs_on_device,
+                     out);
+}
+
+int layout_create64(const int64_t* row_ptr, const int32_t* col_idx, int32_t n, int32_t dim,
+                    int32_t k, int32_t epochs, uint64_t seed, const layout_opts* opts,
+                    int32_t inputs_on_device, layout_t** out) {
+  if (!row_ptr) return fail(LAYOUT_E_INVALID_ARG, "row_ptr is NULL");
+  return create_impl(nullptr, row_ptr, col_idx, n, dim, k, epochs, seed, opts, inputs_on_device,
+                     out);
 }
 
 int layout_epoch(layout_t* L, int32_t count) {
@@ -1313,12 +1377,12 @@ int layout_debug_draws_at(layout_t* L, int32_t epoch, const int64_t* edges, int6
   return LAYOUT_OK;
 }
 
-int layout_debug_chunks(const layout_t* L, int32_t* begin_out, int32_t* src_out) {
+int layout_debug_chunks(const layout_t* L, int64_t* begin_out, int32_t* src_out) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (!begin_out || !src_out) return fail(LAYOUT_E_INVALID_ARG, "NULL output");
   if (L->n_chunks == 0) return LAYOUT_OK;
   hipError_t e = hipMemcpyAsync(begin_out, L->host_desc.chunk_begin,
-                                sizeof(int32_t) * size_t(L->n_chunks + 1), hipMemcpyDeviceToHost,
+                                sizeof(int64_t) * size_t(L->n_chunks + 1), hipMemcpyDeviceToHost,
                                 L->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(src_out, L->host_desc.chunk_src, sizeof(int32_t) * size_t(L->n_chunks),

@@ -128,6 +128,8 @@ _SIGNATURES = {
     "layout_create": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _i32, _u64, ctypes.POINTER(_vp)]),
     "layout_create_ex": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _i32, _u64,
                                         ctypes.POINTER(layout_opts), _i32, ctypes.POINTER(_vp)]),
+    "layout_create64": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _i32, _u64,
+                                       ctypes.POINTER(layout_opts), _i32, ctypes.POINTER(_vp)]),
     "layout_epoch": (ctypes.c_int, [_vp, _i32]),
     "layout_epoch_timed": (ctypes.c_int, [_vp, _i32, _f32p]),
     "layout_get_positions": (ctypes.c_int, [_vp, _vp]),
@@ -227,22 +229,38 @@ def layout_create(row_ptr, col_idx, n, dim, k, epochs, seed):
     return h
 
 
+def _row_is_64(row_ptr):
+    return "int64" in str(getattr(row_ptr, "dtype", ""))
+
+
 def layout_create_ex(row_ptr, col_idx, n, dim, k, epochs, seed, opts=None, inputs_on_device=0):
+    """Creates a handle; an int64 row_ptr goes through layout_create64."""
     keep = []
+    wide = _row_is_64(row_ptr)
     if inputs_on_device:
         rp_p, _ = _ptr(row_ptr)
         ci_p, _ = _ptr(col_idx)
     else:
-        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64 if wide else np.int32)
         ci = np.ascontiguousarray(col_idx, dtype=np.int32)
         keep += [rp, ci]
         rp_p, ci_p = rp.ctypes.data, ci.ctypes.data
     o = opts if opts is not None else layout_opts_init()
     h = _vp()
-    _check(lib().layout_create_ex(rp_p, ci_p, n, dim, k, epochs, seed, ctypes.byref(o),
-                                  int(inputs_on_device), ctypes.byref(h)))
+    create = lib().layout_create64 if wide else lib().layout_create_ex
+    _check(create(rp_p, ci_p, n, dim, k, epochs, seed, ctypes.byref(o), int(inputs_on_device),
+                  ctypes.byref(h)))
     del keep
     return h
+
+
+def layout_create64(row_ptr, col_idx, n, dim, k, epochs, seed, opts=None, inputs_on_device=0):
+    """layout_create_ex with 64-bit row pointers (int64 numpy array or tensor)."""
+    if not hasattr(row_ptr, "data_ptr"):
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    elif not _row_is_64(row_ptr):
+        raise LayoutError(LAYOUT_E_INVALID_ARG, "layout_create64 needs an int64 row_ptr")
+    return layout_create_ex(row_ptr, col_idx, n, dim, k, epochs, seed, opts, inputs_on_device)
 
 
 def layout_epoch(h, count):
@@ -406,7 +424,7 @@ def layout_debug_draws_at(h, epoch, edges, k):
 
 def layout_debug_chunks(h):
     n_chunks = layout_get_info(h)["n_chunks"]
-    begin = np.zeros(n_chunks + 1, dtype=np.int32)
+    begin = np.zeros(n_chunks + 1, dtype=np.int64)
     src = np.zeros(max(n_chunks, 1), dtype=np.int32)
     _check(lib().layout_debug_chunks(h, begin.ctypes.data, src.ctypes.data))
     return begin, src[:n_chunks]

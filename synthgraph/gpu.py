@@ -33,15 +33,46 @@ def _powerlaw_weights(torch, n, total, tau, dmax, device):
     return dmax * ((idx + i0) / i0) ** (-expo)
 
 
+def _unique(torch, x):
+    """Sorted distinct values of x; a sort holds at most 2^31 - 1 elements, so
+    a longer x is cut into value ranges (bounds from a strided sample) and
+    each range is made unique on its own."""
+    if x.numel() < 2**31 - 1:
+        return torch.unique(x)
+    parts = 2 * (x.numel() // 2**30) + 2
+    samp = torch.sort(x[:: max(1, x.numel() // (1 << 20))]).values
+    bounds = samp[(torch.arange(1, parts, device=x.device) * samp.numel()) // parts]
+    bounds = torch.unique(bounds).tolist()
+    out = []
+    for lo, hi in zip([None] + bounds, bounds + [None]):
+        m = torch.ones_like(x, dtype=torch.bool) if lo is None else x >= lo
+        if hi is not None:
+            m &= x < hi
+        out.append(torch.unique(x[m]))
+        del m
+    return torch.cat(out)
+
+
 def chung_lu_communities_gpu(n: int, n_edges: int, tau: float, dmax: float, n_comm: int,
                              intra: float, sigma: float = 1.0, seed: int = 0,
-                             device: str = "cuda:0"):
-    """Returns (row_ptr int32 [n+1], col int32 [2*n_edges], labels int32 [n]) as
-    device tensors.  2 * n_edges must stay below 2^31 (int32 CSR)."""
+                             device: str = "cuda:0", progress: bool = False):
+    """Returns (row_ptr [n+1], col int32 [2*n_edges], labels int32 [n]) as
+    device tensors; row_ptr is int32 below 2^31 directed edges, else int64.
+    With progress, each phase is timed (after a device sync) on stderr."""
+    import sys
+    import time
+
     import torch
 
-    if 2 * n_edges >= 2**31:
-        raise ValueError("2 * n_edges must be < 2^31 for an int32 CSR")
+    t_start = time.perf_counter()
+
+    def say(what):
+        if progress:
+            if str(device).startswith("cuda"):
+                torch.cuda.synchronize(device)
+            print(f"[graph] {what} ({time.perf_counter() - t_start:.1f} s)", file=sys.stderr,
+                  flush=True)
+
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
     rng = np.random.default_rng(seed)
@@ -112,27 +143,66 @@ def chung_lu_communities_gpu(n: int, n_edges: int, tau: float, dmax: float, n_co
             b = torch.maximum(u[ok], v[ok])
             parts.append(a * n + b)
             del u, v, ok, a, b
-        keys = torch.unique(torch.cat([keys] + parts))
+        say(f"round {rounds}: drew {need} candidate pairs")
+        keys = _unique(torch, torch.cat([keys] + parts))
         del parts
-    if keys.numel() > n_edges:
+        say(f"round {rounds}: {keys.numel()} distinct edges of {n_edges}")
+    if keys.numel() > n_edges and n_edges < 2**30:
         pick = torch.randperm(keys.numel(), generator=gen, device=device)[:n_edges]
         keys = torch.sort(keys[pick]).values
         del pick
-    u = keys // n
-    v = keys - u * n
+    elif keys.numel() > n_edges:
+        # a permutation of ~2^31 keys is slow: drop a uniform random subset of
+        # the excess instead (distinct draws of indices, then a random subset
+        # of them; every subset of that size is equally likely by symmetry);
+        # the kept keys stay sorted
+        excess = keys.numel() - n_edges
+        drop = torch.zeros(0, dtype=torch.int64, device=device)
+        while drop.numel() < excess:
+            more = torch.randint(0, keys.numel(), (excess + excess // 16 + 1024,),
+                                 generator=gen, device=device)
+            drop = torch.unique(torch.cat([drop, more]))
+        drop = drop[torch.randperm(drop.numel(), generator=gen, device=device)[:excess]]
+        keep = torch.ones(keys.numel(), dtype=torch.bool, device=device)
+        keep[drop] = False
+        keys = keys[keep]
+        del drop, keep
+    # CSR of both directions without sorting the directed keys (a sort holds
+    # at most 2^31 - 1 elements): keys are sorted by (a, b) with a < b, so
+    # row i is its lower neighbours (edges (a, i), sorted by a) followed by
+    # its higher ones (edges (i, b), sorted by b).
+    a1 = keys // n
+    b1 = keys - a1 * n
     del keys
-    src = torch.cat([u, v])
-    dst = torch.cat([v, u])
-    del u, v
-    skey = torch.sort(src * n + dst).values
-    del src, dst
-    row = skey // n
-    col = (skey - row * n).to(torch.int32)
-    counts = torch.bincount(row, minlength=n)
-    del skey, row
+    say("kept a sorted sample of the edges")
+    k2 = torch.sort(b1 * n + a1).values  # (b, a) order
+    b2 = k2 // n
+    a2 = k2 - b2 * n
+    del k2
+    ids = torch.arange(n + 1, device=device)
+    c1 = torch.diff(torch.searchsorted(a1, ids))  # higher neighbours per row (a1 sorted)
+    c2 = torch.diff(torch.searchsorted(b2, ids))  # lower neighbours per row (b2 sorted)
+    del ids
     row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
-    row_ptr[1:] = torch.cumsum(counts, 0)
-    return row_ptr.to(torch.int32), col, labels
+    row_ptr[1:] = torch.cumsum(c1 + c2, 0)
+    s1 = torch.cumsum(c1, 0) - c1  # first index of each row's group in (a1, b1)
+    s2 = torch.cumsum(c2, 0) - c2
+    say("row pointers")
+    col = torch.empty(int(row_ptr[-1]), dtype=torch.int32, device=device)
+    step = 1 << 28  # bounded temporaries
+    for lo in range(0, a2.numel(), step):
+        t = torch.arange(lo, min(lo + step, a2.numel()), device=device)
+        r = b2[t]
+        col[row_ptr[r] + (t - s2[r])] = a2[t].to(torch.int32)
+    for lo in range(0, a1.numel(), step):
+        t = torch.arange(lo, min(lo + step, a1.numel()), device=device)
+        r = a1[t]
+        col[row_ptr[r] + c2[r] + (t - s1[r])] = b1[t].to(torch.int32)
+    del a1, b1, a2, b2, c1, c2, s1, s2
+    say("column indices")
+    if 2 * n_edges < 2**31:
+        row_ptr = row_ptr.to(torch.int32)
+    return row_ptr, col, labels
 
 
 def friendster_like_gpu(seed: int = 0, device: str = "cuda:0"):
@@ -144,3 +214,13 @@ def friendster_like_gpu(seed: int = 0, device: str = "cuda:0"):
     n, m = 65_608_366, 1_000_000_000
     return chung_lu_communities_gpu(n, m, tau=2.2, dmax=math.sqrt(2 * m),
                                     n_comm=n // 1300, intra=0.9, seed=seed, device=device)
+
+
+def friendster_full_gpu(seed: int = 0, device: str = "cuda:0"):
+    """The com-friendster shape of the paper's case study: 65,608,366 nodes and
+    1.8e9 undirected edges (3.6e9 directed: a 64-bit CSR), otherwise the
+    recipe of friendster_like_gpu."""
+    n, m = 65_608_366, 1_800_000_000
+    return chung_lu_communities_gpu(n, m, tau=2.2, dmax=math.sqrt(2 * m),
+                                    n_comm=n // 1300, intra=0.9, seed=seed, device=device,
+                                    progress=True)
