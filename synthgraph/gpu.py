@@ -208,7 +208,7 @@ def chung_lu_communities_gpu(n: int, n_edges: int, tau: float, dmax: float, n_co
 def friendster_like_gpu(seed: int = 0, device: str = "cuda:0"):
     """Stands in for com-friendster's node count (65,608,366 nodes: positions of
     525 MB, beyond the 256 MB last-level cache) with 1.0e9 undirected edges
-    (the int32 CSR holds < 2^31 directed edges; friendster has 1.8e9),
+    (an int32 CSR: < 2^31 directed edges; friendster_full_gpu has 1.8e9),
     tau = 2.2, top expected degree sqrt(2|E|), communities of ~1300 nodes
     (log-normal sizes), 90% intra."""
     n, m = 65_608_366, 1_000_000_000
