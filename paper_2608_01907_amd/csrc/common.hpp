@@ -47,6 +47,9 @@ inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Upper bound of the chunk count, for allocation before the exact count is
 // known: one chunk per B-bucket, one per hub segment, one after each hub.
+// Most chunks one table may hold: chunk indices and work counters are 32-bit.
+constexpr int64_t kMaxChunks = INT32_MAX - (int64_t(1) << 24);
+
 inline int64_t chunk_bound(int64_t nnz, int32_t bundle, int32_t hub) {
   return (nnz + bundle - 1) / bundle + 2 * ((nnz + hub - 1) / hub) + 2;
 }

@@ -230,6 +230,12 @@ int launch_epochs(layout_t* L, int32_t count) {
 int snap::build_chunk_table(hipStream_t stream, const int64_t* d_row, int32_t n, int64_t nnz,
                             int32_t bundle, int32_t hub, int64_t* d_chunk_begin,
                             int32_t* d_chunk_src, int64_t* n_chunks) {
+  // chunk offsets are scanned, and chunk counters advanced, in 32 bits (the
+  // margin covers the counters' overshoot past the last chunk)
+  if (chunk_bound(nnz, bundle, hub) > kMaxChunks)
+    return fail(LAYOUT_E_UNSUPPORTED,
+                "%lld edges in chunks of %d (hub rows cut every %d) need more than %lld chunks",
+                static_cast<long long>(nnz), bundle, hub, static_cast<long long>(kMaxChunks));
   const int64_t tiles = std::max<int64_t>(1, scan_tiles(n));
   void* tmp = nullptr;
   const size_t b_scan = sizeof(int32_t) * size_t(tiles + 1);
@@ -858,6 +864,12 @@ int create_impl(const int32_t* row32, const int64_t* row64, const int32_t* col_i
   if ((L->engine == LAYOUT_ENGINE_GLOBAL || L->engine == LAYOUT_ENGINE_XCD) && L->block > 256)
     return bail(fail(LAYOUT_E_UNSUPPORTED, "global engines run at most 256-thread workgroups"));
   const int64_t chunk_cap = L->nnz > 0 ? chunk_bound(L->nnz, L->bundle, L->hub) : 0;
+  if (chunk_cap > kMaxChunks)
+    return bail(fail(LAYOUT_E_UNSUPPORTED,
+                     "%lld edges in chunks of %d (hub rows cut every %d) need more than %lld chunks: "
+                     "raise bundle_edges and hub_split_edges",
+                     static_cast<long long>(L->nnz), L->bundle, L->hub,
+                     static_cast<long long>(kMaxChunks)));
 
   // device buffers
   int rc;

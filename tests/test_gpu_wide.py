@@ -84,3 +84,11 @@ def test_full_friendster_shape_draws_and_init(full):
         ms = L.run_timed(1)
         assert np.all(np.isfinite(L.positions()))
     print(f"full com-friendster shape: n={n} nnz={nnz}, one epoch {ms:.1f} ms", flush=True)
+
+
+def test_full_shape_refuses_more_chunks_than_32_bit_counters_hold(full):
+    rp_d, col_d = full
+    with pytest.raises(SL.LayoutError) as ei:  # 3.6e9 one-edge chunks
+        SL.Layout(rp_d, col_d, rp_d.numel() - 1, k=5, epochs=30, bundle_edges=1)
+    assert ei.value.code == SL.LAYOUT_E_UNSUPPORTED
+    print("refused:", ei.value, flush=True)
