@@ -17,7 +17,8 @@
  *   - Graph input is CSR with int32 indices: row_ptr[n+1], col_idx[nnz].  Each
  *     undirected edge must appear in both directions (Sec. 3.3), rows sorted
  *     strictly increasing, no self-loops, no duplicates; nnz = row_ptr[n] <
- *     2^31.  Isolated nodes are allowed (they are drawn as negatives only).
+ *     2^31 (layout_create64 takes int64 row pointers for larger graphs).
+ *     Isolated nodes are allowed (they are drawn as negatives only).
  *   - Positions are float32, row-major n x 2 (x0, y0, x1, y1, ...).
  *   - Unless stated otherwise, pointers are host pointers owned by the caller
  *     and only read during the call; the library copies what it keeps.
@@ -171,8 +172,11 @@ int layout_create_ex(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, 
  * graphs of 2^31 or more directed edges (the com-friendster shape of the
  * paper's case study: 1.8 billion undirected edges).  Internally every graph
  * uses 64-bit row pointers and chunk starts; the int32 entry points widen
- * theirs on the device.  Edge counts up to 2^31 x 16 (chunk indices stay
- * 32-bit); the degree-weighted alias table needs nnz < 2^32. */
+ * theirs on the device.  Chunk indices stay 32-bit: a graph whose chunk
+ * table (about nnz / bundle_edges + 2 nnz / hub_split_edges entries) would
+ * exceed 2^31 - 2^24 entries is refused with LAYOUT_E_UNSUPPORTED before any
+ * allocation (the defaults, 16 and 64, allow about 2.3 x 10^10 edges); the
+ * degree-weighted alias table needs nnz < 2^32. */
 int layout_create64(const int64_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t dim,
                     int32_t k, int32_t epochs, uint64_t seed, const layout_opts *opts,
                     int32_t inputs_on_device, layout_t **out);
