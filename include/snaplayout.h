@@ -117,6 +117,14 @@ typedef struct layout_opts {
                                  stream owned by the library */
     const uint32_t *neg_weight_values; /* LAYOUT_NEG_CUSTOM: n weights (host, or device when
                                  the inputs are on the device), copied at create */
+    int32_t hot_degree;       /* HOGWILD_STORE on the global engine: the update a node
+                                 receives as the far end of an edge is committed as an
+                                 atomic add of its change, not a store, when the node's
+                                 degree is at least this (concurrent stores to such nodes
+                                 collide and lose updates; Sec. 3.4 assumes they are rare).
+                                 0 = never (default: plain stores only); negative is
+                                 LAYOUT_E_INVALID_ARG.  Ignored by the other engines and
+                                 policies */
 } layout_opts;
 
 /* Fills *opts with the defaults listed above. */
@@ -224,6 +232,7 @@ typedef struct layout_info {
     int32_t n, k;
     int32_t epochs, update_mode; /* the resolved policy (never AUTO) */
     int32_t hub_split_edges;
+    int32_t hot_degree;    /* resolved hot-node threshold; 0 = no hot nodes */
 } layout_info;
 
 int layout_get_info(const layout_t *L, layout_info *info);

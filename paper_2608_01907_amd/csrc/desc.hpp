@@ -21,6 +21,11 @@ struct GraphDesc {
   float2* D;  // Jacobi accumulator (JACOBI only)
   const uint32_t* thr;    // alias table (degree-weighted negatives only)
   const uint32_t* alias;
+  // HOGWILD_STORE on the global engine: bitmap of the nodes whose updates as
+  // the far end of an edge are committed as atomic adds of the change
+  // instead of stores (nodes of high degree, where concurrent updates
+  // collide); null = none
+  const uint32_t* hot = nullptr;
   int64_t chunk_base;    // offset of this graph's slice inside one round of the launch
   int64_t slice;         // chunks of this graph per round of the launch
   int64_t chunk_offset;  // first chunk of the graph's table processed by the launch

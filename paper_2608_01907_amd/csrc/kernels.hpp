@@ -358,6 +358,9 @@ __device__ __forceinline__ void process_chunk(const Mem& mem, const GraphDesc& g
     P ys[KS];
 #pragma unroll
     for (int m = 0; m < K; ++m) ys[m] = mem.load(Y + s[m]);
+    uint32_t hot_word = 0;  // bit j & 31: j is a hot node (STORE only)
+    if constexpr (MODE == kStore)
+      if (g.hot) hot_word = *gptr(g.hot + (j >> 5));
 
     if constexpr (MODE == kJacobi) {
       {
@@ -418,7 +421,12 @@ __device__ __forceinline__ void process_chunk(const Mem& mem, const GraphDesc& g
         for (int m = 0; m < K; ++m)
           if (!dup[m] && !same_bits(ys[m], ys_old[m])) mem.add(Y + s[m], vsub(ys[m], ys_old[m]));
       } else {
-        if (!same_bits(yj, yj_old)) mem.store(Y + j, yj);
+        if (!same_bits(yj, yj_old)) {
+          if ((hot_word >> (j & 31)) & 1u)
+            mem.add(Y + j, vsub(yj, yj_old));
+          else
+            mem.store(Y + j, yj);
+        }
 #pragma unroll
         for (int m = 0; m < K; ++m)
           if (!dup[m] && !same_bits(ys[m], ys_old[m])) mem.store(Y + s[m], ys[m]);
@@ -613,6 +621,19 @@ static __global__ void __launch_bounds__(1024) epoch_lds_kernel(const GraphDesc*
     __syncthreads();
   }
   for (int32_t v = threadIdx.x; v < g.n; v += blockDim.x) gY[v] = sY[v];
+}
+
+// Bitmap of the nodes of degree >= threshold: word w covers nodes 32w..32w+31.
+static __global__ void hot_bits_kernel(const int64_t* __restrict__ row_ptr, int32_t n,
+                                       int64_t threshold, uint32_t* __restrict__ bits) {
+  const int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= (int64_t(n) + 31) / 32) return;
+  uint32_t word = 0;
+  for (int b = 0; b < 32; ++b) {
+    const int32_t v = w * 32 + b;
+    if (v < n && row_ptr[v + 1] - row_ptr[v] >= threshold) word |= 1u << b;
+  }
+  bits[w] = word;
 }
 
 // Jacobi apply: Y += D, D = 0.

@@ -125,6 +125,7 @@ struct layout {
   int32_t hub = 64;
   int32_t block = 256;
   int32_t grid = 0;
+  int32_t hot_degree = 0;  // resolved hot-node threshold (0 = no hot nodes)
   int64_t n_chunks = 0;
   bool own_stream = false;
   hipStream_t stream = nullptr;
@@ -765,6 +766,7 @@ int create_impl(const int32_t* row32, const int64_t* row64, const int32_t* col_i
     return fail(LAYOUT_E_UNSUPPORTED, "the Pivot MDS start is 2D");
   if (o.pmds_pivots < 0 || o.pmds_pivots > 64)
     return fail(LAYOUT_E_INVALID_ARG, "pmds_pivots = %d (1..64, 0 = default)", o.pmds_pivots);
+  if (o.hot_degree < 0) return fail(LAYOUT_E_INVALID_ARG, "hot_degree = %d (>= 0)", o.hot_degree);
   if (o.bundle_edges < 0 || o.block_threads < 0 || o.grid_blocks < 0 || o.hub_split_edges < 0 ||
       o.nodes_per_lane < 0)
     return fail(LAYOUT_E_INVALID_ARG, "negative launch option");
@@ -950,6 +952,21 @@ int create_impl(const int32_t* row32, const int64_t* row64, const int32_t* col_i
     }
   }
   if (d_D) launch_fill_zero(L->stream, d_D, int64_t(n) * (pos_bytes / 8));
+  // hot nodes: HOGWILD_STORE on the global engine commits updates of
+  // high-degree nodes as the far end of an edge as atomic adds
+  uint32_t* d_hot = nullptr;
+  L->hot_degree = 0;
+  if (L->engine == LAYOUT_ENGINE_GLOBAL && L->mode == LAYOUT_HOGWILD_STORE && L->nnz > 0 &&
+      o.hot_degree > 0) {
+    L->hot_degree = o.hot_degree;
+    const int64_t words = (int64_t(n) + 31) / 32;
+    if ((rc = alloc(L, reinterpret_cast<void**>(&d_hot), sizeof(uint32_t) * size_t(words),
+                    "hot nodes")) != LAYOUT_OK)
+      return bail(rc);
+    hipLaunchKernelGGL(hot_bits_kernel, dim3(div_up(words, 256)), dim3(256), 0, L->stream, d_row,
+                       n, int64_t(L->hot_degree), d_hot);
+    if ((e = hipGetLastError()) != hipSuccess) return bail(hip_fail(e, "hot nodes"));
+  }
   if (L->engine == LAYOUT_ENGINE_XCD) {
     const size_t b = sizeof(int32_t) * size_t(epochs);
     if ((rc = alloc(L, reinterpret_cast<void**>(&L->d_xcd_owner), b, "epoch owners")) ||
@@ -969,6 +986,7 @@ int create_impl(const int32_t* row32, const int64_t* row64, const int32_t* col_i
   g.D = d_D;
   g.thr = d_thr;
   g.alias = d_alias;
+  g.hot = d_hot;
   g.chunk_base = 0;
   g.slice = L->n_chunks;
   g.n_chunks = L->n_chunks;
@@ -1326,6 +1344,7 @@ int layout_get_info(const layout_t* L, layout_info* info) {
   info->epochs = L->epochs;
   info->update_mode = L->mode;
   info->hub_split_edges = L->hub;
+  info->hot_degree = L->hot_degree;
   return LAYOUT_OK;
 }
 

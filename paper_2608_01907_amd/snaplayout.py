@@ -60,7 +60,7 @@ class layout_opts(ctypes.Structure):
         ("hub_split_edges", ctypes.c_int32), ("nodes_per_lane", ctypes.c_int32),
         ("init_mode", ctypes.c_int32), ("pmds_pivots", ctypes.c_int32),
         ("init_pos", ctypes.c_void_p), ("stream", ctypes.c_void_p),
-        ("neg_weight_values", ctypes.c_void_p),
+        ("neg_weight_values", ctypes.c_void_p), ("hot_degree", ctypes.c_int32),
     ]
 
 
@@ -71,7 +71,7 @@ class layout_info(ctypes.Structure):
         ("n_chunks", ctypes.c_int64), ("nnz", ctypes.c_int64),
         ("n", ctypes.c_int32), ("k", ctypes.c_int32),
         ("epochs", ctypes.c_int32), ("update_mode", ctypes.c_int32),
-        ("hub_split_edges", ctypes.c_int32),
+        ("hub_split_edges", ctypes.c_int32), ("hot_degree", ctypes.c_int32),
     ]
 
 
@@ -611,8 +611,9 @@ class Layout:
                  alpha=0.1, beta=8.0, gamma=2.0, init_pos=None, bundle_edges=0,
                  block_threads=0, grid_blocks=0, start_epoch=0, stream=None,
                  hub_split_edges=0, nodes_per_lane=0, init_mode=LAYOUT_INIT_UNIFORM,
-                 pmds_pivots=0, neg_weight_values=None, dim=2):
+                 pmds_pivots=0, neg_weight_values=None, dim=2, hot_degree=0):
         o = layout_opts_init()
+        o.hot_degree = hot_degree
         o.init_mode, o.pmds_pivots = init_mode, pmds_pivots
         w_keep = None
         if neg_weight_values is not None:

@@ -128,6 +128,39 @@ def test_single_lane_epoch_matches_serial_oracle(d1, mode, engine, gamma):
     assert err <= 1e-3 * _diam(ref), (err, _diam(ref))
 
 
+@pytest.mark.parametrize("hot", [1, 12])
+def test_single_lane_epoch_with_hot_nodes_matches_serial_oracle(d1, hot):
+    """HOGWILD_STORE with the far-end updates of nodes of degree >= hot
+    committed as atomic adds of the change (hot = 1: every node): on one lane
+    the trajectory is still the serial one, since adding the change to the
+    value the lane itself stored differs from storing it by one rounding."""
+    seed, T = 4, 50
+    Y0 = O.init_positions(d1.n, seed).astype(np.float32)
+    ref = O.serial_run(d1.row_ptr, d1.col, d1.n, 5, T, seed, Y0=Y0.astype(np.float64),
+                       t_begin=0, t_end=1, order=O.ORDER_CSR)
+    with _layout(d1, k=5, epochs=T, seed=seed, update_mode=SL.LAYOUT_HOGWILD_STORE,
+                 engine=SL.LAYOUT_ENGINE_GLOBAL, init_pos=Y0, bundle_edges=d1.nnz,
+                 grid_blocks=1, block_threads=64, hot_degree=hot) as L:
+        assert L.info()["hot_degree"] == hot
+        L.run(1)
+        Y = L.positions().astype(np.float64)
+    err = np.abs(Y - ref).max()
+    assert err <= 1e-3 * _diam(ref), (err, _diam(ref))
+
+
+def test_hot_degree_applies_to_global_store_only(d1):
+    for mode, engine in ((SL.LAYOUT_ATOMIC, SL.LAYOUT_ENGINE_GLOBAL),
+                         (SL.LAYOUT_HOGWILD_STORE, SL.LAYOUT_ENGINE_LDS),
+                         (SL.LAYOUT_HOGWILD_STORE, SL.LAYOUT_ENGINE_XCD)):
+        with _layout(d1, k=5, epochs=5, update_mode=mode, engine=engine, hot_degree=4) as L:
+            assert L.info()["hot_degree"] == 0
+    with _layout(d1, k=5, epochs=5, hot_degree=0) as L:  # the default: plain stores only
+        assert L.info()["hot_degree"] == 0
+    with pytest.raises(SL.LayoutError) as ei:
+        _layout(d1, k=5, epochs=5, hot_degree=-1)
+    assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
+
+
 # --------------------------------------------------------- final quality
 @pytest.fixture(scope="module")
 def d1_oracle_quality(d1):
