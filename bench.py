@@ -185,6 +185,30 @@ def bench_plain(args):
         finite = bool(np.all(np.isfinite(Y)))
         SL.layout_destroy(h)
     ms_epoch = float(np.median(runs_ms))
+
+    # phases of one job, timed apart with the host clock between device
+    # synchronisations: create from HBM-resident inputs (validation, chunk
+    # table, init), the epochs, the readout to host memory, and, for the
+    # host-buffer case of the boundary, create from host arrays (PCIe copy
+    # of the CSR included; not available for the graphs generated on the
+    # device, whose CSR never lives in host memory)
+    def phases(src_rp, src_col, on_device):
+        t_a = time.perf_counter()
+        h = SL.layout_create_ex(src_rp, src_col, g.n, dim, k, T, seed, opts(), on_device)
+        SL.layout_sync(h)
+        t_b = time.perf_counter()
+        SL.layout_epoch(h, T)
+        SL.layout_sync(h)
+        t_c = time.perf_counter()
+        SL.layout_get_positions(h, g.n, dim)
+        t_d = time.perf_counter()
+        SL.layout_destroy(h)
+        return {"create_ms": round((t_b - t_a) * 1e3, 2), "epochs_ms": round((t_c - t_b) * 1e3, 2),
+                "readout_to_host_ms": round((t_d - t_c) * 1e3, 2)}
+    phase = phases(rp_d, col_d, 1)
+    if not maker.startswith("gpu:"):
+        phase["create_from_host_ms"] = phases(g.row_ptr, g.col, 0)["create_ms"]
+    log(f"[bench] phases {phase}")
     nbytes = algorithmic_bytes(g.row_ptr, g.n, k, info["hub_split_edges"], info["n_chunks"], dim)
     achieved = nbytes / (ms_epoch * 1e-3) / 1e9
     policy = {0: "store", 1: "atomic", 2: "jacobi"}[info["update_mode"]]
@@ -233,6 +257,7 @@ def bench_plain(args):
                    "grid_blocks": info["grid_blocks"]},
         "epoch_ms": round(ms_epoch, 4),
         "epoch_ms_runs": [round(x, 4) for x in runs_ms],
+        "phases": phase,
         "epoch_only_value": n_edges * (1 + k) / (ms_epoch * 1e-3),
         "positions_finite": finite,
         "roofline": roof,
