@@ -223,10 +223,28 @@ def layout_opts_init() -> layout_opts:
 def layout_create(row_ptr, col_idx, n, dim, k, epochs, seed):
     rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
     ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    _check_csr_sizes(rp, ci, n)
     h = _vp()
     _check(lib().layout_create(rp.ctypes.data, ci.ctypes.data, n, dim, k, epochs, seed,
                                ctypes.byref(h)))
     return h
+
+
+def _check_csr_sizes(row_ptr, col_idx, n):
+    """Refuses arrays shorter than the library will read: row_ptr[0..n] and
+    col_idx[0..row_ptr[n]) (the library validates the values themselves)."""
+    def count(a):
+        return int(a.numel()) if hasattr(a, "numel") else int(np.size(a))
+    if n < 0:
+        return  # reported by the library
+    if count(row_ptr) < n + 1:
+        raise LayoutError(LAYOUT_E_INVALID_ARG,
+                          f"row_ptr holds {count(row_ptr)} entries; n + 1 = {n + 1} are read")
+    last = row_ptr[n]
+    last = int(last.item()) if hasattr(last, "item") else int(last)
+    if last < 0 or last > count(col_idx):
+        raise LayoutError(LAYOUT_E_INVALID_ARG,
+                          f"row_ptr[n] = {last}, but col_idx holds {count(col_idx)} entries")
 
 
 def _row_is_64(row_ptr):
@@ -236,6 +254,7 @@ def _row_is_64(row_ptr):
 def layout_create_ex(row_ptr, col_idx, n, dim, k, epochs, seed, opts=None, inputs_on_device=0):
     """Creates a handle; an int64 row_ptr goes through layout_create64."""
     keep = []
+    _check_csr_sizes(row_ptr, col_idx, n)
     wide = _row_is_64(row_ptr)
     if inputs_on_device:
         rp_p, _ = _ptr(row_ptr)
@@ -326,6 +345,7 @@ def layout_debug_draws(h, epoch, nnz, k):
 def layout_pmds(row_ptr, col_idx, n, pivots=0, seed=0, want_detail=False):
     """Pivot MDS layout (n x 2 float32); with want_detail also the pivots and
     their hop distances (pivots x n, -1 = unreachable)."""
+    _check_csr_sizes(row_ptr, col_idx, n)
     on_device = hasattr(row_ptr, "data_ptr") and row_ptr.is_cuda
     if on_device:
         rp, ci = row_ptr.data_ptr(), col_idx.data_ptr()
@@ -456,6 +476,7 @@ def layout_batch_create(graphs, k, epochs, opts=None, inputs_on_device=0):
     arr = (layout_graph * len(graphs))()
     keep = []
     for q, g in enumerate(graphs):
+        _check_csr_sizes(g["row_ptr"], g["col_idx"], g["n"])
         if inputs_on_device:
             rp_p, ci_p = _ptr(g["row_ptr"])[0], _ptr(g["col_idx"])[0]
             ip = _ptr(g.get("init_pos"))[0]
@@ -549,6 +570,7 @@ def layout_server_create(hbm_budget_bytes=0, max_slots=64, round_edges=0, opts=N
 def layout_server_submit(h, row_ptr, col_idx, n, k, epochs, seed):
     rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
     ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    _check_csr_sizes(rp, ci, n)
     jid = _i64()
     _check(lib().layout_server_submit(h, rp.ctypes.data, ci.ctypes.data, n, k, epochs, seed,
                                       ctypes.byref(jid)))
@@ -559,6 +581,7 @@ def layout_server_submit_ex(h, row_ptr, col_idx, n, k, epochs, seed, neg_weight_
                             init_pos=None):
     rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
     ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    _check_csr_sizes(rp, ci, n)
     w = None if neg_weight_values is None else np.ascontiguousarray(neg_weight_values,
                                                                     dtype=np.uint32)
     ip = None if init_pos is None else np.ascontiguousarray(init_pos, dtype=np.float32)
