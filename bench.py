@@ -226,12 +226,21 @@ def bench_plain(args):
     traffic, tinfo = committed_traffic(args.workload) if dim == 2 else (None, None)
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": (f"epoch_global_kernel<{k},{policy}>" if info["engine"] == 1
-                       else f"epoch_lds_kernel<{k},{policy}>"),
+            "kernel": {SL.LAYOUT_ENGINE_GLOBAL: "epoch_global_kernel",
+                       SL.LAYOUT_ENGINE_LDS: "epoch_lds_kernel",
+                       SL.LAYOUT_ENGINE_XCD: "epoch_xcd_kernel"}[info["engine"]]
+                      + f"<{k},{policy}>",
             "algorithmic_bytes_per_launch": nbytes, "ms_per_launch": round(ms_epoch, 4),
             "measured_copy_GBs": round(copy_gbs, 1), "kernel_hash": kernel_hash()}
     if tinfo is not None and traffic is None:
         roof["traffic_note"] = "counter summary predates the current kernel source"
+    if info["engine"] == SL.LAYOUT_ENGINE_XCD:
+        # positions inside one XCD's L2: the ceiling is that L2's rate of
+        # random 8-byte read-modify-writes with plain loads (145 G/s measured
+        # over all eight XCDs on a 2 MB array, i.e. 18.1 G/s for one)
+        rmw = g.row_ptr[-1] * (1 + k) / (ms_epoch * 1e-3) / 1e9
+        roof["xcd_l2_rmw"] = {"achieved_G_per_s": round(float(rmw), 2), "ceiling_G_per_s": 18.1,
+                              "frac": round(float(rmw) / 18.1, 3)}
     if gather:
         roof["gather_roofline_ms"] = round(gather[policy if policy in gather else "store"], 4)
         roof["gather_roofline_frac"] = round(roof["gather_roofline_ms"] / ms_epoch, 4)
