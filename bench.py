@@ -494,8 +494,8 @@ def main():
     ap.add_argument("--budget", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding "
-              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.profile_copy:
         import torch  # noqa: F401

@@ -45,7 +45,7 @@ enum {
     LAYOUT_E_OOM = -3,         /* device memory allocation failed */
     LAYOUT_E_DEVICE = -4,      /* a HIP runtime call failed */
     LAYOUT_E_DONE = -5,        /* all epochs of the schedule have run */
-    LAYOUT_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+    LAYOUT_E_UNSUPPORTED = -6  /* valid request the library does not implement */
 };
 
 /* How concurrent position updates are committed (Sec. 3.4 lock-free scheme). */
