@@ -92,3 +92,28 @@ def test_full_shape_refuses_more_chunks_than_32_bit_counters_hold(full):
         SL.Layout(rp_d, col_d, rp_d.numel() - 1, k=5, epochs=30, bundle_edges=1)
     assert ei.value.code == SL.LAYOUT_E_UNSUPPORTED
     print("refused:", ei.value, flush=True)
+
+
+def test_full_shape_degree_alias_table_and_draws_bit_exact(full):
+    """Degree-weighted negatives on the full shape: total weight W = nnz =
+    3.6e9, past 2^31 and near the 2^32 limit of the integer alias table.
+    The whole table (65.6M entries) and the negatives of sampled edges, most
+    past offset 2^31, match the oracle bit for bit."""
+    rp_d, col_d = full
+    n = rp_d.numel() - 1
+    row_ptr = rp_d.cpu().numpy()
+    nnz = int(row_ptr[-1])
+    assert 2**31 < nnz < 2**32
+    thr_o, alias_o = O.alias_build(np.diff(row_ptr))
+    rng = np.random.default_rng(9)
+    edges = np.concatenate([rng.integers(0, nnz, 20_000), [0, nnz - 1, 2**31]]).astype(np.int64)
+    with SL.Layout(rp_d, col_d, n, k=5, epochs=30, seed=6,
+                   neg_weights=SL.LAYOUT_NEG_DEGREE) as L:
+        thr, alias = SL.layout_debug_alias(L.h, n)
+        assert np.array_equal(thr, thr_o) and np.array_equal(alias, alias_o)
+        print("alias table of 65.6M entries matches", flush=True)
+        for t in (0, 29):
+            got = SL.layout_debug_draws_at(L.h, t, edges, 5)
+            ref = O.draw_edges(row_ptr, n, 5, t, 6, edges, mode=O.NEG_DEGREE, thr=thr_o,
+                               alias=alias_o)
+            assert np.array_equal(got, ref), t
