@@ -117,3 +117,20 @@ def test_full_shape_degree_alias_table_and_draws_bit_exact(full):
             ref = O.draw_edges(row_ptr, n, 5, t, 6, edges, mode=O.NEG_DEGREE, thr=thr_o,
                                alias=alias_o)
             assert np.array_equal(got, ref), t
+
+
+def test_full_shape_atomic_epoch_conserves_centroid(full):
+    """One ATOMIC epoch over 3.6e9 directed edges: every pair update adds +v
+    and -v, so the centroid stays put up to FP32 rounding."""
+    rp_d, col_d = full
+    n = rp_d.numel() - 1
+    with SL.Layout(rp_d, col_d, n, k=5, epochs=30, seed=0, update_mode=SL.LAYOUT_ATOMIC,
+                   hub_split_edges=1 << 30) as L:
+        Y0 = L.positions().astype(np.float64)
+        ms = L.run_timed(1)
+        Y1 = L.positions().astype(np.float64)
+    extent = float(np.abs(Y0).max())
+    drift = float(np.abs(Y1.mean(0) - Y0.mean(0)).max())
+    print(f"full shape ATOMIC epoch {ms:.1f} ms, centroid drift {drift:.2e} of extent {extent:.0f}",
+          flush=True)
+    assert np.all(np.isfinite(Y1)) and drift <= 1e-4 * extent, (drift, extent)
