@@ -65,12 +65,13 @@ def algorithmic_bytes(row_ptr: np.ndarray, n: int, k: int, hub: int, n_chunks: i
     (4 B) and (1 + k) position read-modify-writes (2 x 8 B in 2D, 2 x 16 B for
     the 16-byte 3D positions); per source run (a row, or one segment of a row
     split above `hub` edges) the source read and commit (same); per chunk its
-    table entries (8 B); the row pointers (4 B per row)."""
+    table entries (an 8-byte first edge and a 4-byte source row); the 64-bit
+    row pointers the device holds (8 B per row)."""
     nnz = int(row_ptr[-1])
     rmw = 16 if dim == 2 else 32
     deg = np.diff(row_ptr.astype(np.int64))
     runs = int(np.where(deg > hub, (deg + hub - 1) // hub, (deg > 0).astype(np.int64)).sum())
-    return int(nnz * (4 + rmw * (1 + k)) + rmw * runs + 8 * n_chunks + 4 * (n + 1))
+    return int(nnz * (4 + rmw * (1 + k)) + rmw * runs + 12 * n_chunks + 8 * (n + 1))
 
 
 def committed_traffic(workload: str):
