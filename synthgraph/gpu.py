@@ -33,13 +33,21 @@ def _powerlaw_weights(torch, n, total, tau, dmax, device):
     return dmax * ((idx + i0) / i0) ** (-expo)
 
 
+# A torch sort holds at most 2^31 - 1 elements; longer unique passes are cut
+# into value ranges of about _PART_ELEMS elements.  A permutation of more
+# than _PERM_MAX keys is slow, so larger edge sets drop their excess instead.
+_SORT_MAX = 2**31 - 1
+_PART_ELEMS = 2**30
+_PERM_MAX = 2**30
+
+
 def _unique(torch, x):
-    """Sorted distinct values of x; a sort holds at most 2^31 - 1 elements, so
-    a longer x is cut into value ranges (bounds from a strided sample) and
-    each range is made unique on its own."""
-    if x.numel() < 2**31 - 1:
+    """Sorted distinct values of x; an x longer than one sort holds is cut
+    into value ranges (bounds from a strided sample) and each range is made
+    unique on its own."""
+    if x.numel() < _SORT_MAX:
         return torch.unique(x)
-    parts = 2 * (x.numel() // 2**30) + 2
+    parts = 2 * (x.numel() // _PART_ELEMS) + 2
     samp = torch.sort(x[:: max(1, x.numel() // (1 << 20))]).values
     bounds = samp[(torch.arange(1, parts, device=x.device) * samp.numel()) // parts]
     bounds = torch.unique(bounds).tolist()
@@ -147,7 +155,7 @@ def chung_lu_communities_gpu(n: int, n_edges: int, tau: float, dmax: float, n_co
         keys = _unique(torch, torch.cat([keys] + parts))
         del parts
         say(f"round {rounds}: {keys.numel()} distinct edges of {n_edges}")
-    if keys.numel() > n_edges and n_edges < 2**30:
+    if keys.numel() > n_edges and n_edges < _PERM_MAX:
         pick = torch.randperm(keys.numel(), generator=gen, device=device)[:n_edges]
         keys = torch.sort(keys[pick]).values
         del pick
