@@ -9,6 +9,7 @@ automatic launch shape).
   259k-node graph against the FP64 oracle, within 1e-5 x the output's
   diameter (eta0 = 1/d_max, the step at which a hub stays inside the layout;
   the same bar as the smaller cases);
+* the same Jacobi epoch of the 4M-node graph with 3D positions;
 * one ATOMIC epoch of the 4M-node graph conserves the centroid (every pair
   update adds +v and -v) within 1e-4 of the layout's extent.
 """
@@ -72,6 +73,25 @@ def test_full_size_jacobi_epoch(which, d3, d3_dev):
         Y = L.positions().astype(np.float64)
     err = float(np.abs(Y - ref).max())
     print(f"{which}: Jacobi epoch max error {err:.3e}, diameter {_diam(ref):.1f}", flush=True)
+    assert err <= 1e-5 * _diam(ref), (err, _diam(ref))
+
+
+def test_d3_jacobi_epoch_in_3d(d3, d3_dev):
+    """The 4M-node graph with 3D positions (16-byte positions, the benchmark's
+    --dim 3 launch): one synchronous epoch against the FP64 oracle, within
+    1e-5 x the output's diameter."""
+    rp, col = d3_dev
+    eta0 = 1.0 / float(d3.degrees().max())
+    Y0 = O.init_positions(d3.n, 0, dim=3).astype(np.float32)
+    ref = O.jacobi_epoch(d3.row_ptr, d3.col, d3.n, 5, 0, 30, 0, Y0.astype(np.float64), eta0=eta0)
+    with SL.Layout(rp, col, d3.n, k=5, epochs=30, seed=0, update_mode=SL.LAYOUT_JACOBI,
+                   eta0=eta0, init_pos=torch.from_numpy(Y0).to("cuda:0"), dim=3) as L:
+        assert L.info()["engine"] == SL.LAYOUT_ENGINE_GLOBAL
+        L.run(1)
+        Y = L.positions().astype(np.float64)
+    err = float(np.abs(Y - ref).max())
+    print(f"lj-like-4m in 3D: Jacobi epoch max error {err:.3e}, diameter {_diam(ref):.1f}",
+          flush=True)
     assert err <= 1e-5 * _diam(ref), (err, _diam(ref))
 
 
