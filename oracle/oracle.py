@@ -93,6 +93,14 @@ def lib():
             ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
             ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _u32p, _u32p, ctypes.c_int32, _f64p]
         L.oracle_serial_run.restype = ctypes.c_int
+        L.oracle_serial_run_ordered.argtypes = [
+            _i32p, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+            ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+            ctypes.c_double, ctypes.c_int32, _u32p, _u32p, ctypes.c_int32, _i64p, _f64p]
+        L.oracle_serial_run_ordered.restype = ctypes.c_int
+        L.oracle_pair_energies.argtypes = [ctypes.c_double] * 4 + [
+            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.oracle_pair_energies.restype = None
         L.oracle_jacobi_epoch.argtypes = [
             _i32p, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
             ctypes.c_uint64, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -211,6 +219,15 @@ def force_magnitudes(dist, alpha=ALPHA, beta=BETA, gamma=GAMMA):
     return fa.value, fr.value
 
 
+def pair_energies(dist, alpha=ALPHA, beta=BETA, gamma=GAMMA):
+    """(U_a, U_r) at distance dist: the pair energies whose negative gradients
+    are the Table 1 forces (Eq. (2))."""
+    ua, ur = ctypes.c_double(), ctypes.c_double()
+    lib().oracle_pair_energies(alpha, beta, gamma, float(dist), ctypes.byref(ua),
+                               ctypes.byref(ur))
+    return ua.value, ur.value
+
+
 def serial_run(row_ptr, col, n, k, T, seed, Y0=None, t_begin=0, t_end=None,
                order=ORDER_SHUFFLED, mode=NEG_UNIFORM, thr=None, alias=None,
                alpha=ALPHA, beta=BETA, gamma=GAMMA, eta0=ETA0, dim=None):
@@ -230,6 +247,28 @@ def serial_run(row_ptr, col, n, k, T, seed, Y0=None, t_begin=0, t_end=None,
                             alpha, beta, gamma, eta0, int(order), int(mode), thr, alias, int(dim),
                             Y)
     return Y[: dim * n].reshape(n, dim)
+
+
+def serial_run_ordered(row_ptr, col, n, k, T, seed, edge_order, Y0=None, t_begin=0,
+                       t_end=None, mode=NEG_UNIFORM, thr=None, alias=None, alpha=ALPHA,
+                       beta=BETA, gamma=GAMMA, eta0=ETA0):
+    """Serial Algorithm 1 (2D) visiting the directed edges in the given order
+    (a permutation of [0, nnz)); draws stay keyed by CSR position."""
+    rp, c = _csr(row_ptr, col)
+    thr, alias = _tables(n, thr, alias)
+    if t_end is None:
+        t_end = T
+    order = np.ascontiguousarray(edge_order, dtype=np.int64)
+    if order.size == 0:
+        order = np.zeros(1, dtype=np.int64)
+    Y = init_positions(n, seed) if Y0 is None else np.array(Y0, dtype=np.float64)
+    Y = np.ascontiguousarray(Y.reshape(-1))
+    rc = lib().oracle_serial_run_ordered(rp, c, int(n), int(k), int(t_begin), int(t_end), int(T),
+                                         int(seed), alpha, beta, gamma, eta0, int(mode), thr,
+                                         alias, 2, order, Y)
+    if rc != 0:
+        raise ValueError("serial_run_ordered: edge_order is not a permutation of [0, nnz)")
+    return Y[: 2 * n].reshape(n, 2)
 
 
 def jacobi_epoch(row_ptr, col, n, k, t, T, seed, Y, mode=NEG_UNIFORM, thr=None, alias=None,

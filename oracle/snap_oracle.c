@@ -387,6 +387,33 @@ static void repel_pair(const force_params *fp, double eta, int dim, double *yi, 
     }
 }
 
+/* The epochs [t_begin, t_end) of serial Algorithm 1, visiting the directed
+ * edges in the order perm[0..nnz): attraction along the edge, then the k
+ * negatives one after another, every pair force taken from the current
+ * positions and applied at once (Sec. 3.3, "immediate updates"). */
+static void serial_epochs(const int32_t *row_ptr, const int32_t *col, int32_t n, int32_t k,
+                          int64_t t_begin, int64_t t_end, int64_t T, uint64_t seed,
+                          const force_params *fp, const sampler *sp, int32_t dim,
+                          const int64_t *perm, double *Y)
+{
+    int64_t nnz = row_ptr[n];
+    int32_t *src = sources_of(row_ptr, n);
+    int32_t *neg = (int32_t *)malloc(sizeof(int32_t) * (size_t)(k > 0 ? k : 1));
+    for (int64_t t = t_begin; t < t_end; ++t) {
+        double eta = eta_at(fp, t, T);
+        for (int64_t p = 0; p < nnz; ++p) {
+            int64_t e = perm[p];
+            int32_t i = src[e], j = col[e];
+            attract_pair(fp, eta, dim, Y + (int64_t)dim * i, Y + (int64_t)dim * j);
+            draw_negatives(sp, seed, e, t, i, k, neg);
+            for (int32_t m = 0; m < k; ++m)
+                repel_pair(fp, eta, dim, Y + (int64_t)dim * i, Y + (int64_t)dim * neg[m]);
+        }
+    }
+    free(neg);
+    free(src);
+}
+
 /* Serial Algorithm 1 in FP64 over epochs [t_begin, t_end) of a T-epoch
  * schedule.  order = ORDER_SHUFFLED: the directed edges are shuffled once
  * (Algorithm 1, first step) by a seeded permutation; ORDER_CSR: rows in index
@@ -401,7 +428,6 @@ int oracle_serial_run(const int32_t *row_ptr, const int32_t *col, int32_t n, int
     int64_t nnz = row_ptr[n];
     force_params fp = {alpha, beta, gamma, eta0};
     sampler sp = {n, mode, thr, alias};
-    int32_t *src = sources_of(row_ptr, n);
     int64_t *perm = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nnz > 0 ? nnz : 1));
     if (order == ORDER_SHUFFLED) {
         perm_item *items = (perm_item *)malloc(sizeof(perm_item) * (size_t)(nnz > 0 ? nnz : 1));
@@ -418,21 +444,35 @@ int oracle_serial_run(const int32_t *row_ptr, const int32_t *col, int32_t n, int
     } else {
         for (int64_t p = 0; p < nnz; ++p) perm[p] = p;
     }
-    int32_t *neg = (int32_t *)malloc(sizeof(int32_t) * (size_t)(k > 0 ? k : 1));
-    for (int64_t t = t_begin; t < t_end; ++t) {
-        double eta = eta_at(&fp, t, T);
-        for (int64_t p = 0; p < nnz; ++p) {
-            int64_t e = perm[p];
-            int32_t i = src[e], j = col[e];
-            attract_pair(&fp, eta, dim, Y + (int64_t)dim * i, Y + (int64_t)dim * j);
-            draw_negatives(&sp, seed, e, t, i, k, neg);
-            for (int32_t m = 0; m < k; ++m)
-                repel_pair(&fp, eta, dim, Y + (int64_t)dim * i, Y + (int64_t)dim * neg[m]);
-        }
-    }
-    free(neg);
+    serial_epochs(row_ptr, col, n, k, t_begin, t_end, T, seed, &fp, &sp, dim, perm, Y);
     free(perm);
-    free(src);
+    return 0;
+}
+
+/* Serial Algorithm 1 with the directed edges visited in a caller-given order
+ * edge_order[0..nnz), which must be a permutation of [0, nnz) (checked; -1
+ * otherwise).  Draws stay keyed by CSR position, so only the order of the
+ * immediate updates changes. */
+int oracle_serial_run_ordered(const int32_t *row_ptr, const int32_t *col, int32_t n, int32_t k,
+                              int64_t t_begin, int64_t t_end, int64_t T, uint64_t seed,
+                              double alpha, double beta, double gamma, double eta0, int32_t mode,
+                              const uint32_t *thr, const uint32_t *alias, int32_t dim,
+                              const int64_t *edge_order, double *Y)
+{
+    int64_t nnz = row_ptr[n];
+    unsigned char *seen = (unsigned char *)calloc((size_t)(nnz > 0 ? nnz : 1), 1);
+    for (int64_t p = 0; p < nnz; ++p) {
+        int64_t e = edge_order[p];
+        if (e < 0 || e >= nnz || seen[e]) {
+            free(seen);
+            return -1;
+        }
+        seen[e] = 1;
+    }
+    free(seen);
+    force_params fp = {alpha, beta, gamma, eta0};
+    sampler sp = {n, mode, thr, alias};
+    serial_epochs(row_ptr, col, n, k, t_begin, t_end, T, seed, &fp, &sp, dim, edge_order, Y);
     return 0;
 }
 
@@ -518,6 +558,16 @@ static double energy_attr(const force_params *fp, double q)
 static double energy_rep(const force_params *fp, double q)
 {
     return pow(1.0 + q, 1.0 - fp->gamma) / (2.0 * (fp->gamma - 1.0));
+}
+
+/* The two pair energies at distance dist, for the pins of Eq. (2). */
+void oracle_pair_energies(double alpha, double beta, double gamma, double dist, double *ua,
+                          double *ur)
+{
+    force_params fp = {alpha, beta, gamma, 1.0};
+    double q = dist * dist;
+    *ua = energy_attr(&fp, q);
+    *ur = energy_rep(&fp, q);
 }
 
 /* Energy actually sampled in epoch t at fixed Y: the sum over directed edges of

@@ -2,10 +2,13 @@
 
 Each test checks the oracle against something it does not compute the same way:
 an independent library implementation of the generator (numpy's Philox4x64-10),
-closed forms of the Table 1 t-forces, the expectation identity of Sec. 3.3
-evaluated by O(n^2) brute force, a scalar recursion for the two-node graph,
-exact rational reconstruction of the alias table, invariants of pair updates,
-and chi-square tests of the samplers.
+closed forms of the Table 1 t-forces (at gamma = 2 and at other exponents),
+the expectation identity of Sec. 3.3 evaluated by O(n^2) brute force, a scalar
+recursion for the two-node graph, exact rational reconstruction of the alias
+table, invariants of pair updates, chi-square tests of the samplers, the
+threaded bundle scheme of Sec. 3.4 against serial Algorithm 1 in the bundle
+order that numpy's generator gives, and the energies against the forces by
+central differences (Eq. (2)).
 """
 from fractions import Fraction
 import math
@@ -541,3 +544,207 @@ def test_jacobi_attraction_is_exact_double_sum_3d():
     ref = np.zeros_like(Y)
     np.add.at(ref, src, -2 * eta * A)
     assert np.allclose(Yo - Y, ref, rtol=1e-12, atol=1e-12)
+
+
+# --------------------------------------- the threaded bundle scheme (Sec. 3.4)
+def _numpy_row_order(seed, n):
+    """The bundle order of the threaded scheme, computed from numpy's own
+    Philox4x64-10 (not the oracle's): rows sorted by the first word of block
+    (i, 1, 0, 3), ties by row index."""
+    keys = np.array([_numpy_block(seed, i, 1, 0, 3)[0] for i in range(n)], dtype=np.uint64)
+    return np.lexsort((np.arange(n), keys))
+
+
+@pytest.mark.parametrize("seed,t_begin,t_end,T,k", [(1, 0, 6, 6, 5), (4, 3, 7, 9, 3), (7, 0, 2, 2, 0)])
+def test_threaded_single_thread_is_serial_in_bundle_order(seed, t_begin, t_end, T, k):
+    """On one thread the lock-free bundle scheme is serial Algorithm 1 with the
+    directed edges visited bundle by bundle (all out-edges of one source, CSR
+    order) in the seeded bundle order: same eta schedule, same draws, the
+    source re-read before every pair step.  Bit for bit."""
+    g = S.small_sbm(400, 4, 8.0, seed)
+    rows = _numpy_row_order(seed, g.n)
+    edge_order = np.concatenate([np.arange(g.row_ptr[i], g.row_ptr[i + 1]) for i in rows])
+    Y0 = O.init_positions(g.n, seed)
+    ref = O.serial_run_ordered(g.row_ptr, g.col, g.n, k, T, seed, edge_order, Y0=Y0,
+                               t_begin=t_begin, t_end=t_end)
+    got = O.threaded_run(g.row_ptr, g.col, g.n, k, T, seed, nthreads=1, Y0=Y0,
+                         t_begin=t_begin, t_end=t_end)
+    assert np.array_equal(got, ref)
+    # and the order matters: the plain CSR order gives another trajectory
+    csr = O.serial_run_ordered(g.row_ptr, g.col, g.n, k, T, seed, np.arange(g.nnz), Y0=Y0,
+                               t_begin=t_begin, t_end=t_end)
+    assert not np.array_equal(csr, ref)
+
+
+def test_threaded_single_thread_two_nodes_closed_form():
+    """Two nodes, one edge: the threaded scheme follows the scalar recursion
+    of the separation, independent of any order (compare the serial pin)."""
+    rp, col = S.csr_from_pairs(np.array([0]), np.array([1]), 2)
+    k, T = 2, 15
+    Y0 = np.array([[1.5, 0.5], [-0.5, 2.0]])
+    Y = O.threaded_run(rp, col, 2, k, T, 3, nthreads=1, Y0=Y0)
+    d = Y0[0] - Y0[1]
+    for t in range(T):
+        eta = 1.0 - t / T
+        for _ in range(2):
+            d = d * (1 - 2 * eta * ALPHA * (1 + BETA / (1 + d @ d)))
+            for _ in range(k):
+                d = d * (1 + 2 * eta / (1 + d @ d) ** 2)
+    assert np.allclose(Y[0] - Y[1], d, rtol=1e-10, atol=1e-12)
+
+
+def test_serial_run_ordered_refuses_non_permutation():
+    g = S.small_sbm(60, 2, 6.0, 0)
+    bad = np.arange(g.nnz)
+    bad[1] = bad[0]
+    with pytest.raises(ValueError):
+        O.serial_run_ordered(g.row_ptr, g.col, g.n, 5, 2, 0, bad)
+
+
+# ------------------------------------------------------- general gamma
+@pytest.mark.parametrize("gamma,d,fr", [
+    (1.5, 1.0, 2.0 ** -1.5),                      # 1 / 2^1.5
+    (1.5, math.sqrt(3.0), math.sqrt(3.0) / 8.0),  # sqrt3 / 4^1.5
+    (3.0, 1.0, 0.125),                            # 1 / 2^3
+    (3.0, 2.0, 2.0 / 125.0),                      # 2 / 5^3
+    (1.0, 3.0, 0.3),                              # 3 / 10
+    (4.0, 0.5, 0.5 / 1.25 ** 4),
+])
+def test_tforce_repulsion_general_gamma_closed_form(gamma, d, fr):
+    """Table 1, t-FDP row with a free exponent: |R| = d / (1 + d^2)^gamma;
+    the attraction does not depend on gamma."""
+    a, r = O.force_magnitudes(d, gamma=gamma)
+    assert r == pytest.approx(fr, rel=1e-13, abs=1e-15)
+    assert a == pytest.approx(O.force_magnitudes(d, gamma=2.0)[0], rel=1e-15)
+
+
+@pytest.mark.parametrize("gamma", [1.5, 3.0])
+def test_tforce_repulsion_peak_general_gamma(gamma):
+    """d (1+d^2)^-gamma peaks where 1 + d^2 = 2 gamma d^2, i.e. d = 1/sqrt(2 gamma - 1),
+    with value (2 gamma - 1)^(gamma - 1/2) / (2 gamma)^gamma."""
+    d0 = 1.0 / math.sqrt(2 * gamma - 1)
+    peak = (2 * gamma - 1) ** (gamma - 0.5) / (2 * gamma) ** gamma
+    r0 = O.force_magnitudes(d0, gamma=gamma)[1]
+    assert r0 == pytest.approx(peak, rel=1e-13)
+    for eps in (1e-3, -1e-3):
+        assert O.force_magnitudes(d0 + eps, gamma=gamma)[1] < r0
+
+
+@pytest.mark.parametrize("gamma", [1.5, 3.0])
+def test_two_node_trajectory_general_gamma(gamma):
+    """The two-node recursion with x <- x(1 + 2 eta / (1+x^2)^gamma) per
+    negative, through the serial run and through one synchronous epoch."""
+    rp, col = S.csr_from_pairs(np.array([0]), np.array([1]), 2)
+    k, T = 2, 12
+    Y0 = np.array([[0.75, -0.25], [-0.5, 0.5]])
+    Y = O.serial_run(rp, col, 2, k, T, 5, Y0=Y0, order=O.ORDER_CSR, gamma=gamma)
+    d = Y0[0] - Y0[1]
+    for t in range(T):
+        eta = 1.0 - t / T
+        for _ in range(2):
+            d = d * (1 - 2 * eta * ALPHA * (1 + BETA / (1 + d @ d)))
+            for _ in range(k):
+                d = d * (1 + 2 * eta / (1 + d @ d) ** gamma)
+    assert np.allclose(Y[0] - Y[1], d, rtol=1e-10, atol=1e-12)
+    # one synchronous epoch at t = 0 (eta = 1): every pair force from Y0;
+    # node 0 moves by -2A(d) + 2k R(d) with d = y0 - y1 (both directions)
+    Yj = O.jacobi_epoch(rp, col, 2, k, 0, T, 5, Y0, gamma=gamma)
+    d0 = Y0[0] - Y0[1]
+    q = d0 @ d0
+    move = -2 * ALPHA * (1 + BETA / (1 + q)) * d0 + 2 * k * d0 / (1 + q) ** gamma
+    assert np.allclose(Yj[0] - Y0[0], move, rtol=1e-12, atol=1e-14)
+    assert np.allclose(Yj[1] - Y0[1], -move, rtol=1e-12, atol=1e-14)
+
+
+# ------------------------------------------- energies and forces (Eq. (2))
+@pytest.mark.parametrize("gamma", [1.5, 2.0, 3.0])
+@pytest.mark.parametrize("d", [0.05, 0.4, 1.0, 1.7, 6.0])
+def test_pair_energies_are_force_potentials(gamma, d):
+    """F = -grad U (Eq. (2)): the distance derivative of U_a is the attraction
+    magnitude and minus that of U_r the repulsion magnitude of Table 1, by
+    central differences."""
+    h = 1e-5 * max(d, 1.0)
+    ua_p, ur_p = O.pair_energies(d + h, gamma=gamma)
+    ua_m, ur_m = O.pair_energies(d - h, gamma=gamma)
+    fa, fr = O.force_magnitudes(d, gamma=gamma)
+    assert (ua_p - ua_m) / (2 * h) == pytest.approx(fa, rel=1e-8)
+    assert -(ur_p - ur_m) / (2 * h) == pytest.approx(fr, rel=1e-8)
+
+
+def test_pair_energies_values():
+    """U_a(1) = alpha (1/2 + (beta/2) ln 2); U_r(d) = 1/(2(1+d^2)) at gamma = 2 and
+    (1+d^2)^-2/4 at gamma = 3; at d = 0, U_a = 0 and U_r = 1/(2(gamma-1))."""
+    ua, ur = O.pair_energies(1.0)
+    assert ua == pytest.approx(0.1 * (0.5 + 4.0 * math.log(2.0)), rel=1e-14)
+    assert ur == pytest.approx(0.25, rel=1e-14)
+    assert O.pair_energies(2.0, gamma=3.0)[1] == pytest.approx(1.0 / 100.0, rel=1e-14)
+    ua0, ur0 = O.pair_energies(0.0, gamma=1.5)
+    assert ua0 == 0.0 and ur0 == pytest.approx(1.0, rel=1e-14)
+
+
+@pytest.mark.parametrize("gamma", [1.5, 2.0, 3.0])
+def test_jacobi_step_is_gradient_step_on_sampled_energy(gamma):
+    """With the draws of epoch t fixed, the synchronous epoch moves every node by
+    -eta times the gradient of that epoch's sampled energy (Eq. (2) summed over
+    the sampled pairs): the energies and the forces of the oracle, written
+    separately, agree through central differences in every coordinate."""
+    g = S.small_sbm(24, 2, 5.0, 11)
+    k, t, T, seed = 3, 2, 8, 19
+    Y = O.init_positions(g.n, 6) * 0.35
+    Yj = O.jacobi_epoch(g.row_ptr, g.col, g.n, k, t, T, seed, Y, gamma=gamma)
+    eta = 1.0 - t / T
+    grad = np.zeros_like(Y)
+    h = 1e-6
+    for i in range(g.n):
+        for c in range(2):
+            Yp = Y.copy()
+            Ym = Y.copy()
+            Yp[i, c] += h
+            Ym[i, c] -= h
+            ep = O.sampled_energy(g.row_ptr, g.col, g.n, k, t, seed, Yp, gamma=gamma)
+            em = O.sampled_energy(g.row_ptr, g.col, g.n, k, t, seed, Ym, gamma=gamma)
+            grad[i, c] = (ep - em) / (2 * h)
+    move = Yj - Y
+    scale = np.abs(move).max()
+    assert scale > 0
+    assert np.abs(move + eta * grad).max() <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("gamma", [1.5, 2.0, 3.0])
+def test_effective_energy_gradient_is_expected_force(gamma):
+    """-grad U_eff equals the expected synchronous force: attraction
+    -2 sum_{j in N(i)} A(y_i - y_j) and weighted repulsion
+    (k/(n-1)) sum_j (d_i + d_j) R(y_i - y_j) (Sec. 3.3, Eq. (4)), the weight
+    that the brute-force expectation pin reconstructs from the draws."""
+    g = S.small_sbm(20, 2, 4.0, 12)
+    k = 5
+    n = g.n
+    Y = O.init_positions(n, 2) * 0.4
+    deg = np.diff(g.row_ptr).astype(np.float64)
+    h = 1e-6
+    grad = np.zeros_like(Y)
+    for i in range(n):
+        for c in range(2):
+            Yp = Y.copy()
+            Ym = Y.copy()
+            Yp[i, c] += h
+            Ym[i, c] -= h
+            grad[i, c] = (O.effective_energy(g.row_ptr, g.col, n, k, Yp, gamma=gamma)
+                          - O.effective_energy(g.row_ptr, g.col, n, k, Ym, gamma=gamma)) / (2 * h)
+    # expected force from the closed-form magnitudes, pair by pair
+    force = np.zeros_like(Y)
+    for i in range(n):
+        for e in range(g.row_ptr[i], g.row_ptr[i + 1]):
+            j = g.col[e]
+            d = Y[i] - Y[j]
+            dist = float(np.linalg.norm(d))
+            fa, _ = O.force_magnitudes(dist, gamma=gamma)
+            force[i] -= 2 * fa * d / dist
+        for j in range(n):
+            if j == i:
+                continue
+            d = Y[i] - Y[j]
+            dist = float(np.linalg.norm(d))
+            _, fr = O.force_magnitudes(dist, gamma=gamma)
+            force[i] += k / (n - 1) * (deg[i] + deg[j]) * fr * d / dist
+    assert np.abs(force + grad).max() <= 1e-6 * np.abs(force).max()
