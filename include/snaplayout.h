@@ -66,7 +66,9 @@ enum {
 /* Distribution of the negatives. */
 enum {
     LAYOUT_NEG_UNIFORM = 0, /* uniform over V \ {i}: the paper's method (Algorithm 1) */
-    LAYOUT_NEG_DEGREE = 1,  /* proportional to degree via an alias table (control) */
+    LAYOUT_NEG_DEGREE = 1,  /* proportional to degree via an alias table (control);
+                               needs nnz < 2^32 (the table's capacity W = nnz), else
+                               LAYOUT_E_UNSUPPORTED */
     LAYOUT_NEG_CUSTOM = 2   /* proportional to the caller's integer weights w (opts
                                neg_weight_values, 0 < sum w < 2^32), drawn like DEGREE: an
                                alias table over w, a draw equal to the source rejected;
@@ -499,7 +501,12 @@ typedef struct layout_server_stats {
  * runs the remaining epochs of every job that fits LDS, an epoch slice of
  * every job whose positions fit one XCD's L2 on XCD-local bins (engine AUTO
  * or XCD, HOGWILD_STORE, automatic launch shape), and an
- * epoch slice of every other job in one all-CU launch. */
+ * epoch slice of every other job in one all-CU launch.
+ * opts->update_mode = LAYOUT_JACOBI (engine AUTO or GLOBAL) serves the
+ * synchronous test mode of layout_create_ex: every job runs on the global
+ * engine, its pair forces of one epoch summed (over the epoch's slices) into
+ * a per-job accumulator before the positions move, so that a served job's
+ * result is the plain path's Jacobi result up to FP32 summation order. */
 int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t round_edges,
                          const layout_opts *opts, layout_server_t **out);
 
@@ -541,6 +548,23 @@ int layout_server_wait(layout_server_t *S, int64_t job_id, double timeout_s);
 int layout_server_take(layout_server_t *S, int64_t job_id, float *host_out, double *latency_s);
 
 int layout_server_get_stats(layout_server_t *S, layout_server_stats *stats);
+
+/* hold != 0: the scheduler keeps admitting queued jobs and setting up their
+ * device state (copy, validation, chunk and alias tables, initial positions)
+ * but runs no round until hold = 0; running jobs pause between rounds.
+ * Thread-safe. */
+int layout_server_hold(layout_server_t *S, int32_t hold);
+
+/* Test support: the k negatives that a queued or running job draws in epoch
+ * `epoch` for each of its nnz directed edges, host_out[e*k + m] (caller-owned,
+ * nnz*k int32), computed on the device from the job's own device state (its
+ * seed, size and alias table) by the scheduler between rounds.  Blocks until
+ * the job has been admitted and the request answered; with the server held
+ * (layout_server_hold) the answer precedes the job's first epoch.  A job
+ * that has already ended: LAYOUT_E_DONE.  Thread-safe (Algorithm 1; the draw
+ * definition of layout_debug_draws). */
+int layout_server_debug_draws(layout_server_t *S, int64_t job_id, int32_t epoch,
+                              int32_t *host_out);
 
 /* Stops the scheduler after the running jobs' current round, frees every
  * job.  NULL is ignored. */

@@ -89,6 +89,8 @@ int pmds_positions(hipStream_t stream, const int64_t* d_row, const int32_t* d_co
                    int32_t pivots, uint64_t seed, float2* d_Y, int32_t* d_pivots_out,
                    int32_t* d_dist_out, int32_t* pivots_used);
 void launch_fill_zero(hipStream_t stream, float2* d_p, int64_t n);
+// Jacobi apply of one 2D graph: Y += D, then D = 0.
+void launch_jacobi_apply(hipStream_t stream, float2* d_Y, float2* d_D, int32_t n);
 // CQ of the positions (cluster.hip): k-means (k-means++ start from seed, or
 // init_centers, host K x 2) and the ARI against host labels[n].  Outputs
 // (nullable but ari_out) on the host.  Synchronises the stream.

@@ -14,6 +14,13 @@
 //      slices share the round's edge budget);
 //   3. waits, advances epoch counters, and retires finished jobs (positions to
 //      host, device memory freed, latency recorded) and cancelled ones.
+// In JACOBI mode (the synchronous test mode) every job runs on the global
+// engine with its own accumulator D; the epoch's slices add into D and the
+// job's positions move (Y += D) once its last slice of the epoch has run.
+// While the server is held (layout_server_hold) jobs are still admitted and
+// set up, but no round runs; per-job debug requests (the negatives a job
+// draws) are answered by the scheduler between rounds, on the job's own
+// device state.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -68,8 +75,20 @@ struct Job {
   int32_t lanes = 0;  // LDS engine: working lanes of the workgroup
   int64_t chunk_cap = 0, n_chunks = 0;
   GraphDesc desc{};
+  float2* D = nullptr;    // JACOBI: the epoch's accumulated displacement
   int32_t t = 0;          // epochs completed
   int64_t chunk_pos = 0;  // chunks of the current epoch already processed
+};
+
+// A caller's request for the negatives a running job draws in one epoch,
+// answered by the scheduler thread.
+struct DrawRequest {
+  int64_t job = 0;
+  int32_t epoch = 0;
+  int32_t* out = nullptr;  // host, nnz * k
+  bool done = false;
+  int rc = LAYOUT_OK;
+  std::string msg;
 };
 
 }  // namespace
@@ -81,6 +100,8 @@ struct layout_server {
   std::unordered_map<int64_t, Job*> jobs;
   std::vector<Job*> active;  // scheduler thread only
   bool stop = false;
+  bool hold = false;  // admit and set up jobs, but run no round
+  std::deque<DrawRequest*> draw_requests;
   bool dead = false;  // a device error stopped the scheduler
   std::string dead_msg;
   std::thread thr;
@@ -116,6 +137,7 @@ int64_t footprint_of(const layout_server_t* S, const Job& j, int32_t bundle, int
   // alias table (weighted negatives)
   int64_t b = 8 * (int64_t(j.n) + 1) + 4 * j.nnz + 8 * int64_t(j.n) + 12 * cap + 8;
   if (S->opts.neg_weights != LAYOUT_NEG_UNIFORM) b += 8 * int64_t(j.n);
+  if (S->mode_global == LAYOUT_JACOBI) b += 8 * int64_t(j.n);  // accumulator D
   return b;
 }
 
@@ -176,6 +198,11 @@ int setup_job(layout_server_t* S, Job& j) {
              : build_alias_table(S->stream, row, nullptr, j.n, j.nnz, thr, alias);
     if (rc != LAYOUT_OK) return rc;
   }
+  if (S->mode_global == LAYOUT_JACOBI) {
+    if ((rc = jalloc(j, reinterpret_cast<void**>(&j.D), 8 * size_t(j.n), "jacobi delta")))
+      return rc;
+    launch_fill_zero(S->stream, j.D, j.n);
+  }
   if (!j.init.empty()) {
     e = hipMemcpyAsync(Y, j.init.data(), 8 * size_t(j.n), hipMemcpyHostToDevice, S->stream);
     if (e != hipSuccess) return hip_fail(e, "copying init_pos");
@@ -195,6 +222,7 @@ int setup_job(layout_server_t* S, Job& j) {
   d.chunk_begin = cb;
   d.chunk_src = cs;
   d.Y = Y;
+  d.D = j.D;
   d.thr = thr;
   d.alias = alias;
   d.nnz = j.nnz;
@@ -387,6 +415,11 @@ int run_round(layout_server_t* S) {
     rc = launch_global_epochs(S->stream, gg, 0, 1);
     if (rc != LAYOUT_OK) return rc;
   }
+  // JACOBI: a job whose epoch ended in this round moves by its summed D
+  if (S->mode_global == LAYOUT_JACOBI)
+    for (size_t q = 0; q < glob_jobs.size(); ++q)
+      if (glob_jobs[q]->chunk_pos + slice[q] >= glob_jobs[q]->n_chunks)
+        launch_jacobi_apply(S->stream, glob_jobs[q]->desc.Y, glob_jobs[q]->D, glob_jobs[q]->n);
   e = hipStreamSynchronize(S->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(S->side);
   if (e != hipSuccess) return hip_fail(e, "running a round");
@@ -402,13 +435,71 @@ int run_round(layout_server_t* S) {
   return LAYOUT_OK;
 }
 
+// Answers the pending draw requests of jobs whose device state is set up
+// (scheduler thread); requests of queued jobs wait for their admission, and
+// those of jobs that ended before it are refused.
+void serve_draw_requests(layout_server_t* S) {
+  std::vector<DrawRequest*> todo;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (DrawRequest* r : S->draw_requests) todo.push_back(r);
+  }
+  if (todo.empty()) return;
+  std::vector<DrawRequest*> answered;
+  for (DrawRequest* r : todo) {
+    Job* j = nullptr;
+    for (Job* a : S->active)
+      if (a->id == r->job) j = a;
+    if (!j) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      auto it = S->jobs.find(r->job);
+      const bool waiting = it != S->jobs.end() && it->second->state == LAYOUT_JOB_QUEUED;
+      if (waiting) continue;
+      r->rc = LAYOUT_E_DONE;
+      r->msg = "the job is no longer on the device";
+      answered.push_back(r);
+      continue;
+    }
+    g_last_error.clear();
+    const size_t count = size_t(j->nnz) * size_t(j->k);
+    int32_t* d_out = nullptr;
+    int rc = LAYOUT_OK;
+    if (count > 0) {
+      hipError_t e = hipMalloc(&d_out, sizeof(int32_t) * count);
+      if (e != hipSuccess) rc = hip_fail(e, "debug draws buffer");
+      if (rc == LAYOUT_OK)
+        rc = launch_dump_draws(S->stream, j->k, S->opts.neg_weights != LAYOUT_NEG_UNIFORM,
+                               j->desc, r->epoch, d_out);
+      if (rc == LAYOUT_OK) {
+        e = hipMemcpyAsync(r->out, d_out, sizeof(int32_t) * count, hipMemcpyDeviceToHost,
+                           S->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+        if (e != hipSuccess) rc = hip_fail(e, "reading debug draws");
+      }
+      if (d_out) (void)hipFree(d_out);
+    }
+    r->rc = rc;
+    r->msg = g_last_error;
+    answered.push_back(r);
+  }
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (DrawRequest* r : answered) {
+    r->done = true;
+    S->draw_requests.erase(std::find(S->draw_requests.begin(), S->draw_requests.end(), r));
+  }
+  if (!answered.empty()) S->cv_done.notify_all();
+}
+
 void scheduler(layout_server_t* S) {
   (void)hipSetDevice(S->dev);
   for (;;) {
     std::vector<Job*> admit;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->active.empty(); });
+      S->cv_work.wait(lk, [&] {
+        return S->stop || !S->queue.empty() || !S->draw_requests.empty() ||
+               (!S->active.empty() && !S->hold);
+      });
       if (S->stop) break;
       while (!S->queue.empty() &&
              int64_t(S->active.size() + admit.size()) < int64_t(S->max_slots)) {
@@ -440,7 +531,19 @@ void scheduler(layout_server_t* S) {
       S->active.push_back(j);
     }
     if (S->dead) break;
-    if (S->active.empty()) continue;
+    serve_draw_requests(S);
+    bool held;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      held = S->hold;
+    }
+    if (S->active.empty() || held) {
+      // held: sleep until a submission, a request or the release (polling
+      // slowly, since a request may wait for a job queued behind full slots)
+      std::unique_lock<std::mutex> lk(S->mu);
+      if (!S->stop && S->hold) S->cv_work.wait_for(lk, std::chrono::milliseconds(50));
+      continue;
+    }
     g_last_error.clear();
     int rc = run_round(S);
     if (rc != LAYOUT_OK) {
@@ -480,6 +583,12 @@ void scheduler(layout_server_t* S) {
   for (Job* j : S->active) finish_job(S, j, LAYOUT_E_DEVICE, S->dead ? S->dead_msg : "server stopped");
   S->active.clear();
   std::lock_guard<std::mutex> lk(S->mu);
+  for (DrawRequest* r : S->draw_requests) {
+    r->rc = LAYOUT_E_DEVICE;
+    r->msg = S->dead ? S->dead_msg : "server stopped";
+    r->done = true;
+  }
+  S->draw_requests.clear();
   for (Job* j : S->queue) {
     j->state = LAYOUT_JOB_FAILED;
     j->err_code = LAYOUT_E_DEVICE;
@@ -507,8 +616,9 @@ int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t ro
     layout_opts_init(&o);
   if (o.update_mode < 0 || o.update_mode > 3)
     return fail(LAYOUT_E_INVALID_ARG, "update_mode = %d", o.update_mode);
-  if (o.update_mode == LAYOUT_JACOBI)
-    return fail(LAYOUT_E_UNSUPPORTED, "the server runs the lock-free policies only");
+  if (o.update_mode == LAYOUT_JACOBI && o.engine != LAYOUT_ENGINE_AUTO &&
+      o.engine != LAYOUT_ENGINE_GLOBAL)
+    return fail(LAYOUT_E_UNSUPPORTED, "JACOBI jobs run on the global engine only");
   if (o.neg_weights != LAYOUT_NEG_UNIFORM && o.neg_weights != LAYOUT_NEG_DEGREE &&
       o.neg_weights != LAYOUT_NEG_CUSTOM)
     return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
@@ -532,7 +642,10 @@ int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t ro
   S->max_slots = max_slots;
   S->round_edges = round_edges ? round_edges : kDefaultRoundEdges;
   (void)hipGetDevice(&S->dev);
-  S->lds_cap = o.engine == LAYOUT_ENGINE_GLOBAL ? 0 : device_props().lds_per_block;
+  // the LDS engine has no Jacobi mode: JACOBI servers run every job globally
+  S->lds_cap = (o.engine == LAYOUT_ENGINE_GLOBAL || o.update_mode == LAYOUT_JACOBI)
+                   ? 0
+                   : device_props().lds_per_block;
   hipError_t e = hipSuccess;
   if (hbm_budget_bytes == 0) {
     size_t free_b = 0, total_b = 0;
@@ -650,6 +763,37 @@ int layout_server_cancel(layout_server_t* S, int64_t job_id) {
     return LAYOUT_OK;
   }
   return fail(LAYOUT_E_INVALID_ARG, "job %lld has already ended", (long long)job_id);
+}
+
+int layout_server_hold(layout_server_t* S, int32_t hold) {
+  if (!S) return fail(LAYOUT_E_INVALID_ARG, "NULL server");
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->hold = hold != 0;
+  S->cv_work.notify_all();
+  return LAYOUT_OK;
+}
+
+int layout_server_debug_draws(layout_server_t* S, int64_t job_id, int32_t epoch,
+                              int32_t* host_out) {
+  if (!S) return fail(LAYOUT_E_INVALID_ARG, "NULL server");
+  if (epoch < 0) return fail(LAYOUT_E_INVALID_ARG, "epoch = %d", epoch);
+  DrawRequest r;
+  r.job = job_id;
+  r.epoch = epoch;
+  r.out = host_out;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->jobs.find(job_id);
+  if (it == S->jobs.end()) return fail(LAYOUT_E_INVALID_ARG, "unknown job %lld", (long long)job_id);
+  Job* j = it->second;
+  if (j->state != LAYOUT_JOB_QUEUED && j->state != LAYOUT_JOB_RUNNING)
+    return fail(LAYOUT_E_DONE, "job %lld is no longer on the device", (long long)job_id);
+  if (j->nnz > 0 && j->k > 0 && !host_out) return fail(LAYOUT_E_INVALID_ARG, "host_out is NULL");
+  if (S->dead) return fail(LAYOUT_E_DEVICE, "server stopped: %s", S->dead_msg.c_str());
+  S->draw_requests.push_back(&r);
+  S->cv_work.notify_all();
+  S->cv_done.wait(lk, [&] { return r.done; });
+  if (r.rc != LAYOUT_OK) return fail(r.rc, "%s", r.msg.c_str());
+  return LAYOUT_OK;
 }
 
 int layout_server_poll(layout_server_t* S, int64_t job_id, int32_t* state) {

@@ -272,6 +272,10 @@ int snap::build_chunk_table(hipStream_t stream, const int64_t* d_row, int32_t n,
 // device (temporary buffers freed before returning).
 int snap::build_alias_table(hipStream_t stream, const int64_t* d_row, const uint32_t* d_weights,
                             int32_t n, int64_t W, uint32_t* d_thr, uint32_t* d_alias) {
+  // thresholds are own * 2^32 / W with own < W: W must fit 32 bits
+  if (W <= 0 || W >= (int64_t(1) << 32))
+    return fail(LAYOUT_E_UNSUPPORTED, "alias table: total weight %lld (need 0 < W < 2^32)",
+                static_cast<long long>(W));
   const int64_t tiles = std::max<int64_t>(1, scan_tiles(n));
   void* tmp = nullptr;
   const size_t b_sums = sizeof(AliasScanItem) * size_t(tiles + 1);
@@ -529,10 +533,13 @@ int snap::launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t
             hipLaunchKernelGGL((epoch_global_kernel<K, MODE, DEG, GlobalMem, DIM>), dim3(grid),
                                dim3(g.block), 0, stream, g.d_table, g.G, index, g.round_size,
                                dt + ep);
+            // JACOBI: apply after every epoch when the group owns one contiguous
+            // Y/D (a caller that applies per graph itself passes no nodes)
             if constexpr (MODE == kJacobi) {
-              hipLaunchKernelGGL(jacobi_apply_kernel<P>, dim3(div_up(g.jacobi_nodes, 256)),
-                                 dim3(256), 0, stream, reinterpret_cast<P*>(g.jacobi_Y),
-                                 reinterpret_cast<P*>(g.jacobi_D), g.jacobi_nodes);
+              if (g.jacobi_nodes > 0)
+                hipLaunchKernelGGL(jacobi_apply_kernel<P>, dim3(div_up(g.jacobi_nodes, 256)),
+                                   dim3(256), 0, stream, reinterpret_cast<P*>(g.jacobi_Y),
+                                   reinterpret_cast<P*>(g.jacobi_D), g.jacobi_nodes);
             }
           }
           hipError_t e = hipGetLastError();
@@ -650,6 +657,12 @@ int snap::launch_dump_draws(hipStream_t stream, int k, bool degree, const GraphD
 void snap::launch_fill_zero(hipStream_t stream, float2* d_p, int64_t n) {
   if (n <= 0) return;
   hipLaunchKernelGGL(fill_zero_kernel, dim3(div_up(n, 256)), dim3(256), 0, stream, d_p, n);
+}
+
+void snap::launch_jacobi_apply(hipStream_t stream, float2* d_Y, float2* d_D, int32_t n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(jacobi_apply_kernel<float2>, dim3(div_up(n, 256)), dim3(256), 0, stream, d_Y,
+                     d_D, n);
 }
 
 namespace {
@@ -774,6 +787,15 @@ int create_impl(const int32_t* row32, const int64_t* row64, const int32_t* col_i
     return fail(LAYOUT_E_INVALID_ARG, "block_threads = %d (multiple of 64, <= 1024)",
                 o.block_threads);
   if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g (must be > 1)", o.gamma);
+  // degree-weighted negatives: the alias table's bin capacity W = nnz must stay
+  // below 2^32 (checked here for host inputs, before any device work; device
+  // inputs are checked when the table is built)
+  if (!inputs_on_device && o.neg_weights == LAYOUT_NEG_DEGREE && n > 0) {
+    const int64_t nnz_host = row32 ? int64_t(row32[n]) : row64[n];
+    if (nnz_host >= (int64_t(1) << 32))
+      return fail(LAYOUT_E_UNSUPPORTED,
+                  "degree-weighted negatives need nnz < 2^32 (nnz = %lld)", (long long)nnz_host);
+  }
 
   layout_t* L = new (std::nothrow) layout_t();
   if (!L) return fail(LAYOUT_E_OOM, "host allocation");

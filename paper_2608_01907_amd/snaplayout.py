@@ -187,6 +187,8 @@ _SIGNATURES = {
     "layout_server_take": (ctypes.c_int, [_vp, _i64, _vp, ctypes.POINTER(ctypes.c_double)]),
     "layout_server_get_stats": (ctypes.c_int, [_vp, ctypes.POINTER(layout_server_stats)]),
     "layout_server_destroy": (ctypes.c_int, [_vp]),
+    "layout_server_hold": (ctypes.c_int, [_vp, _i32]),
+    "layout_server_debug_draws": (ctypes.c_int, [_vp, _i64, _i32, _vp]),
 }
 
 
@@ -618,6 +620,17 @@ def layout_server_get_stats(h) -> dict:
     st = layout_server_stats()
     _check(lib().layout_server_get_stats(h, ctypes.byref(st)))
     return {f: getattr(st, f) for f, _ in layout_server_stats._fields_}
+
+
+def layout_server_hold(h, hold=True):
+    _check(lib().layout_server_hold(h, int(bool(hold))))
+
+
+def layout_server_debug_draws(h, job, epoch, nnz, k):
+    """Negatives of a queued or running job in one epoch, (nnz, k) int32."""
+    out = np.zeros(max(int(nnz) * int(k), 1), dtype=np.int32)
+    _check(lib().layout_server_debug_draws(h, _i64(job), int(epoch), out.ctypes.data))
+    return out[: int(nnz) * int(k)].reshape(int(nnz), int(k))
 
 
 def layout_server_destroy(h):

@@ -357,9 +357,12 @@ def _member_job(args):
 
 
 def many_graphs(kind: str, count: int, seed: int = 0, workers: int | None = None,
-                cache_dir: str | None = None, **kw) -> list[Graph]:
+                cache_dir: str | None = None, progress: bool = True, **kw) -> list[Graph]:
     """Generates `count` members of a workload in a process pool (cached as one
-    .npz per member)."""
+    .npz per member).  With progress=True a line goes to stderr every 32
+    members generated, so that a long generation is never silent."""
+    import sys
+    import time
     from concurrent.futures import ProcessPoolExecutor
 
     cache_dir = cache_dir or os.environ.get("SNAP_GRAPH_CACHE", "/tmp/snap_graphs")
@@ -369,12 +372,16 @@ def many_graphs(kind: str, count: int, seed: int = 0, workers: int | None = None
     todo = [q for q in range(count) if not os.path.exists(paths[q])]
     if todo:
         workers = workers or max(1, min(16, os.cpu_count() or 1))
+        t0 = time.time()
         with ProcessPoolExecutor(workers) as ex:
-            for q, (rp, col, n, lab, name) in zip(
-                    todo, ex.map(_member_job, [(kind, q, seed, kw) for q in todo])):
+            for done, (q, (rp, col, n, lab, name)) in enumerate(zip(
+                    todo, ex.map(_member_job, [(kind, q, seed, kw) for q in todo])), 1):
                 tmp = paths[q] + ".tmp.npz"
                 np.savez(tmp, row_ptr=rp, col=col, n=np.int64(n), labels=lab)
                 os.replace(tmp, paths[q])
+                if progress and (done % 32 == 0 or done == len(todo)):
+                    print(f"[synthgraph] {kind}: {done}/{len(todo)} members generated "
+                          f"({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
     out = []
     for q in range(count):
         z = np.load(paths[q], allow_pickle=False)

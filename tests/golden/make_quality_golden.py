@@ -8,8 +8,8 @@ and both for the 259k-node graph (the "-lockfree" entries).
 The "-pmds" entries start from the oracle's Pivot MDS layout (the initial
 layout of Sec. 4.1, oracle/pmds.py, 50 pivots) instead of the seeded uniform
 draws.  NP and SI are measured on seeded node samples; the GPU tests use the
-same samples.  The 4M-node entries hold five seeds, as the paper averages five
-runs of each stochastic method (Sec. 5.1).  Usage:  python tests/golden/make_quality_golden.py [name ...]
+same samples.  Every entry holds five seeds, as the paper averages five runs
+of each stochastic method (Sec. 4.1).  Usage:  python tests/golden/make_quality_golden.py [name ...]
 """
 import json
 import os
@@ -27,16 +27,18 @@ from oracle import pmds as P  # noqa: E402
 
 PLAN = {
     # name: (graph, maker, k, T, runner, seeds, init)
-    "orkut-like-259k": ("orkut-like-259k", "orkut_like", 5, 30, "serial", (0, 1), "uniform"),
+    "orkut-like-259k": ("orkut-like-259k", "orkut_like", 5, 30, "serial", (0, 1, 2, 3, 4),
+                        "uniform"),
     "lj-like-4m": ("lj-like-4m", "lj_like", 5, 30, "threaded", (0, 1, 2, 3, 4), "uniform"),
-    "orkut-like-259k-pmds": ("orkut-like-259k", "orkut_like", 5, 30, "serial", (0, 1), "pmds"),
+    "orkut-like-259k-pmds": ("orkut-like-259k", "orkut_like", 5, 30, "serial", (0, 1, 2, 3, 4),
+                             "pmds"),
     "lj-like-4m-pmds": ("lj-like-4m", "lj_like", 5, 30, "threaded", (0, 1, 2, 3, 4), "pmds"),
     # the paper's lock-free scheme (Sec. 3.4) on the 259k-node graph: the
     # reference for lock-free layouts, next to serial Algorithm 1 above
-    "orkut-like-259k-lockfree": ("orkut-like-259k", "orkut_like", 5, 30, "threaded", (0, 1, 2),
-                                 "uniform"),
+    "orkut-like-259k-lockfree": ("orkut-like-259k", "orkut_like", 5, 30, "threaded",
+                                 (0, 1, 2, 3, 4), "uniform"),
     "orkut-like-259k-pmds-lockfree": ("orkut-like-259k", "orkut_like", 5, 30, "threaded",
-                                      (0, 1, 2), "pmds"),
+                                      (0, 1, 2, 3, 4), "pmds"),
 }
 NP_SAMPLE, SI_SAMPLE, METRIC_SEED = 2000, 10000, 12345
 

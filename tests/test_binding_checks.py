@@ -33,3 +33,22 @@ def test_other_entry_points_refuse_short_arrays():
     graphs = [{"row_ptr": rp, "col_idx": col, "n": 2, "seed": 0}]
     assert _code(SL.layout_batch_create, graphs, 5, 3)[0] == SL.LAYOUT_E_INVALID_ARG
     assert _code(SL.layout_server_submit, None, rp, col, 2, 5, 3, 0)[0] == SL.LAYOUT_E_INVALID_ARG
+
+
+def test_degree_negatives_refuse_nnz_past_2_32():
+    """Degree-weighted negatives build an alias table whose capacity W = nnz
+    must stay below 2^32 (thresholds are own * 2^32 / W).  A host CSR with
+    row_ptr[n] = 2^32 is refused before any device work; the library only reads
+    row_ptr[n] for the check, so a short col array is safe here (the raw C
+    entry point is called, bypassing the binding's length check)."""
+    import ctypes
+    lib = SL.lib()
+    o = SL.layout_opts_init()
+    o.neg_weights = SL.LAYOUT_NEG_DEGREE
+    rp = np.array([0, 1 << 32], np.int64)
+    col = np.zeros(1, np.int32)
+    h = ctypes.c_void_p()
+    rc = lib.layout_create64(rp.ctypes.data, col.ctypes.data, 1, 2, 5, 3, 0, ctypes.byref(o), 0,
+                             ctypes.byref(h))
+    assert rc == SL.LAYOUT_E_UNSUPPORTED and not h.value
+    assert b"nnz < 2^32" in lib.layout_last_error()

@@ -2,10 +2,13 @@
 the same alone and in the mix, within the stated tolerances.
 
 * draws in the mix are bit-identical to the oracle's for that graph alone;
-* synchronous (Jacobi) epochs: batch vs single-graph path within 1e-5 x
-  diameter, per graph;
+* synchronous (Jacobi) epochs: every graph of the batch after T epochs within
+  1e-5 x diameter of T chained synchronous epochs of the FP64 oracle from the
+  same seeded start (and of the single-graph path);
 * lock-free epochs: NP and SI of each graph within 0.01 of the same graph laid
-  out alone (the single-graph path).
+  out alone (the single-graph path), as means over paired seeds;
+* the 512-graph batched workload: sampled members' NP and SI against the
+  oracle's lock-free scheme on the same graphs and seeds.
 """
 import numpy as np
 import pytest
@@ -61,17 +64,35 @@ def test_batch_groups_and_draws_bit_exact(mix):
                 assert np.array_equal(B.draws(q, t), ref), (q, t)
 
 
-def test_batch_jacobi_equals_single_graph(mix):
+def _oracle_jacobi_chain(g, k, T, seed, eta0):
+    """T chained synchronous epochs of the FP64 oracle from the seeded start."""
+    Y = O.init_positions(g.n, seed)
+    for t in range(T):
+        Y = O.jacobi_epoch(g.row_ptr, g.col, g.n, k, t, T, seed, Y, eta0=eta0)
+    return Y
+
+
+def test_batch_jacobi_matches_oracle(mix):
+    """Algorithm 1's pairs and draws, taken synchronously: every member of the
+    batch (LDS-sized and larger alike, all on the multi-graph global engine in
+    this mode) against T chained oracle epochs, and against the single-graph
+    path."""
     T, eta0 = 3, 0.05
     with SL.BatchLayout(_desc(mix), k=4, epochs=T, update_mode=SL.LAYOUT_JACOBI, eta0=eta0) as B:
         B.run()
         got = [B.positions(q) for q in range(len(mix))]
     for q, g in enumerate(mix):
+        if g.n == 0:
+            continue
+        ref = _oracle_jacobi_chain(g, 4, T, 100 + q, eta0)
+        tol = 1e-5 * max(_diam(ref), 1e-6)
+        err = float(np.abs(got[q] - ref).max())
+        print(f"batch jacobi graph {q} (n {g.n}): max error {err:.3e}, tol {tol:.3e}", flush=True)
+        assert err <= tol, (q, err, tol)
         with SL.Layout(g.row_ptr, g.col, g.n, k=4, epochs=T, seed=100 + q,
                        update_mode=SL.LAYOUT_JACOBI, eta0=eta0) as L:
             L.run()
             alone = L.positions()
-        tol = 1e-5 * max(_diam(alone), 1e-6)
         assert np.abs(got[q] - alone).max() <= tol, q
 
 
@@ -204,3 +225,52 @@ def test_batch_pmds_start_equals_single_graph_pmds(mix):
         ref = SL.layout_pmds(g.row_ptr, g.col, g.n, 0, 100 + q)
         tol = 1e-5 * max(_diam(ref), 1e-6)
         assert np.abs(got[q] - ref).max() <= tol, q
+
+
+# ------------------------------------------------- the 512-graph workload
+def _d4_sample(gs, count=8, max_nnz=1_000_000):
+    """Members of both engine classes (positions within one workgroup's LDS,
+    and beyond it), spread over sizes, small enough for the oracle: half of
+    each class, evenly spaced in node count."""
+    lds = sorted((g.n, q) for q, g in enumerate(gs) if g.n * 8 <= 160 * 1024 and 0 < g.nnz)
+    big = sorted((g.n, q) for q, g in enumerate(gs)
+                 if g.n * 8 > 160 * 1024 and g.nnz <= max_nnz)
+    pick = []
+    for group in (lds, big):
+        idx = np.linspace(0, len(group) - 1, count // 2).round().astype(int)
+        pick += [group[i][1] for i in idx]
+    return pick
+
+
+def test_batched_512_members_match_oracle_quality():
+    """The batched workload itself (512 block-model and Chung-Lu graphs,
+    k = 5, 50 epochs, one HIP-graph replay): for sampled members of both
+    engine classes, NP and SI of the batched layout against the oracle's
+    lock-free bundle scheme (Sec. 3.4) on the same graph, seed and seeded
+    start; mean over members and three seed sets within 0.01."""
+    import os
+    gs = S.many_graphs("batch", 512, 0)
+    pick = _d4_sample(gs)
+    k, T = 5, 50
+    threads = max(1, min(16, os.cpu_count() or 1))
+    diffs = {"np": [], "si": []}
+    for s0 in (0, 1000, 2000):
+        with SL.BatchLayout(_desc(gs, s0), k=k, epochs=T) as B:
+            B.run()
+            got = {q: B.positions(q) for q in pick}
+        for q in pick:
+            g = gs[q]
+            ref = O.threaded_run(g.row_ptr, g.col, g.n, k, T, s0 + q, threads)
+            qg = M.quality(g.row_ptr, g.col, got[q], g.labels, sample=2000)
+            qo = M.quality(g.row_ptr, g.col, ref, g.labels, sample=2000)
+            print(f"batched-512 member {q} (n {g.n}, nnz {g.nnz}) seed {s0 + q}: "
+                  f"gpu np {qg['np']:.4f} si {qg['si']:.4f}, oracle np {qo['np']:.4f} "
+                  f"si {qo['si']:.4f}", flush=True)
+            assert np.all(np.isfinite(got[q]))
+            for key in diffs:
+                diffs[key].append(qg[key] - qo[key])
+    for key, d in diffs.items():
+        d = np.array(d)
+        print(f"batched-512 {key}: mean difference {d.mean():+.4f} "
+              f"(se {d.std(ddof=1) / np.sqrt(d.size):.4f}, {d.size} pairs)", flush=True)
+        assert abs(d.mean()) <= 0.01, (key, d)

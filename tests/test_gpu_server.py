@@ -1,7 +1,9 @@
 """Served layouts (continuous batching): jobs submitted while others run are
 admitted as slots and memory free up; each job's result is the same alone
-and in the mix (NP and SI of the single-graph path, paired over seeds:
-within 0.01, or 2.5 standard errors where the seed spread is larger);
+and in the mix (NP and SI of the single-graph path, mean over eight paired
+seeds within 0.01); every served job draws the oracle's negatives, whatever
+engine serves it; in the synchronous mode a served job's positions after T
+epochs are the oracle's T chained synchronous epochs within 1e-5 x diameter;
 admission respects the HBM budget; a malformed job fails alone."""
 import threading
 import time
@@ -38,7 +40,7 @@ def test_server_results_same_alone_and_in_mix(pool):
     srv = SL.layout_server_create(0, 16, 1 << 20)
     try:
         ids = []
-        for q, g in enumerate(pool * 5):  # each graph five times, submitted back to back
+        for q, g in enumerate(pool * 8):  # each graph eight times, submitted back to back
             ids.append((q % len(pool), 300 + q,
                         SL.layout_server_submit(srv, g.row_ptr, g.col, g.n, 5, T, 300 + q)))
         results = {}
@@ -53,7 +55,7 @@ def test_server_results_same_alone_and_in_mix(pool):
     finally:
         SL.layout_server_destroy(srv)
     # lock-free runs are not bit-reproducible: paired comparison over the
-    # five seeds of each graph, alone and in the mix
+    # eight seeds of each graph, alone and in the mix
     for gi, g in enumerate(pool):
         seeds = sorted(seed for (gj, seed) in results if gj == gi)
         qa = [M.quality(g.row_ptr, g.col, _alone(g, sd, T), g.labels, sample=4000) for sd in seeds]
@@ -257,5 +259,114 @@ def test_server_cancel(pool):
         assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
         st = SL.layout_server_get_stats(srv)
         assert st["cancelled"] == 2 and st["completed"] == 2 and st["hbm_in_use"] == 0
+    finally:
+        SL.layout_server_destroy(srv)
+
+
+# ------------------------------------------- served output against the oracle
+def _oracle_jacobi_chain(g, k, T, seed, eta0):
+    Y = O.init_positions(g.n, seed)
+    for t in range(T):
+        Y = O.jacobi_epoch(g.row_ptr, g.col, g.n, k, t, T, seed, Y, eta0=eta0)
+    return Y
+
+
+def test_server_jacobi_matches_oracle(pool):
+    """Synchronous mode through the server: every job (small and large, all on
+    the global engine in this mode; the large ones cut into several epoch
+    slices per epoch by a small round budget) ends within 1e-5 x diameter of T
+    chained synchronous oracle epochs (Algorithm 1's pairs and draws, Sec. 3.3
+    forces) from the same seeded start."""
+    T, k, eta0 = 3, 4, 0.05
+    srv = _server_jacobi(eta0)
+    try:
+        jobs = [(gi, 60 + gi, SL.layout_server_submit(srv, g.row_ptr, g.col, g.n, k, T, 60 + gi))
+                for gi, g in enumerate(pool)]
+        for gi, seed, jid in jobs:
+            SL.layout_server_wait(srv, jid, 120.0)
+            Y, _ = SL.layout_server_take(srv, jid, pool[gi].n)
+            ref = _oracle_jacobi_chain(pool[gi], k, T, seed, eta0)
+            diam = float(np.linalg.norm(ref.max(0) - ref.min(0)))
+            err = float(np.abs(Y - ref).max())
+            print(f"served jacobi job {gi} (n {pool[gi].n}): max error {err:.3e}, "
+                  f"tol {1e-5 * diam:.3e}", flush=True)
+            assert err <= 1e-5 * diam, (gi, err, diam)
+        assert SL.layout_server_get_stats(srv)["rounds"] > T  # slices were taken
+    finally:
+        SL.layout_server_destroy(srv)
+
+
+def _server_jacobi(eta0):
+    o = SL.layout_opts_init()
+    o.update_mode = SL.LAYOUT_JACOBI
+    o.eta0 = eta0
+    return SL.layout_server_create(0, 16, 1 << 18, o)
+
+
+def test_server_jacobi_refuses_other_engines():
+    o = SL.layout_opts_init()
+    o.update_mode = SL.LAYOUT_JACOBI
+    o.engine = SL.LAYOUT_ENGINE_LDS
+    with pytest.raises(SL.LayoutError) as ei:
+        SL.layout_server_create(0, 4, 0, o)
+    assert ei.value.code == SL.LAYOUT_E_UNSUPPORTED
+
+
+@pytest.fixture(scope="module")
+def wide_graph():
+    """Positions beyond one XCD's L2 (400k nodes x 8 B > 3 MiB): the all-CU
+    engine serves it."""
+    return S.chung_lu_communities(400_000, 1_200_000, tau=2.2, dmax=1000.0, n_comm=300,
+                                  intra=0.9, seed=77)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_server_draws_match_oracle_on_every_engine(pool, wide_graph, weighted):
+    """Held server: jobs of all three classes (LDS-sized SBMs, XCD-bin graphs,
+    and a graph served by the all-CU engine) are admitted and set up; the
+    negatives each draws in its first and last epoch, computed from its own
+    device state, are the oracle's bit for bit (uniform, and caller weights
+    through each job's own alias table).  Released, every job completes."""
+    T, k = 6, 5
+    graphs = list(pool) + [wide_graph]
+    o = SL.layout_opts_init()
+    if weighted:
+        o.neg_weights = SL.LAYOUT_NEG_CUSTOM
+    srv = SL.layout_server_create(0, 16, 1 << 20, o)
+    try:
+        SL.layout_server_hold(srv, True)
+        jobs = []
+        for gi, g in enumerate(graphs):
+            w = None
+            if weighted:
+                w = (np.random.default_rng(gi).integers(0, 40, g.n) + (np.arange(g.n) % 7 == 0)
+                     ).astype(np.uint32)
+            jid = SL.layout_server_submit_ex(srv, g.row_ptr, g.col, g.n, k, T, 900 + gi,
+                                             neg_weight_values=w)
+            jobs.append((gi, 900 + gi, w, jid))
+        for gi, seed, w, jid in jobs:
+            g = graphs[gi]
+            kw = {}
+            if weighted:
+                thr, alias = O.alias_build(w.astype(np.int64))
+                kw = {"mode": O.NEG_DEGREE, "thr": thr, "alias": alias}
+            for t in (0, T - 1):
+                got = SL.layout_server_debug_draws(srv, jid, t, g.nnz, k)
+                ref = O.draw_negatives(g.row_ptr, g.col, g.n, k, t, seed, **kw)
+                assert np.array_equal(got, ref), (gi, t)
+            assert SL.layout_server_poll(srv, jid) == SL.LAYOUT_JOB_RUNNING
+        st = SL.layout_server_get_stats(srv)
+        assert st["rounds"] == 0 and st["running"] == len(jobs)  # held: no epoch ran yet
+        SL.layout_server_hold(srv, False)
+        for gi, seed, w, jid in jobs:
+            SL.layout_server_wait(srv, jid, 120.0)
+            with pytest.raises(SL.LayoutError) as ei:  # done: no longer on the device
+                SL.layout_server_debug_draws(srv, jid, 0, graphs[gi].nnz, k)
+            assert ei.value.code == SL.LAYOUT_E_DONE
+            Y, _ = SL.layout_server_take(srv, jid, graphs[gi].n)
+            assert np.all(np.isfinite(Y))
+            with pytest.raises(SL.LayoutError) as ei:  # forgotten after take
+                SL.layout_server_debug_draws(srv, jid, 0, graphs[gi].nnz, k)
+            assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
     finally:
         SL.layout_server_destroy(srv)
