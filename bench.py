@@ -11,7 +11,9 @@ The JSON line also carries
   roofline      -- the dominant kernel (the epoch kernel): algorithmic bytes per
                    launch / mean launch time (HIP events on the handle's
                    stream) against the 8 TB/s HBM peak; the measured
-                   random-gather roofline of the same graph; HBM traffic from
+                   random-gather ceiling of the same graph (the epoch's
+                   position reads alone, gather_roofline_frac = its time over
+                   the epoch's, at most 1); HBM traffic from
                    the committed rocprofv3 counter summary when it was taken on
                    the current kernel source (else null);
   cpu_baseline  -- the FP64 oracle's threaded bundle scheme timed on this
@@ -213,13 +215,40 @@ def bench_plain(args):
     nbytes = algorithmic_bytes(g.row_ptr, g.n, k, info["hub_split_edges"], info["n_chunks"], dim)
     achieved = nbytes / (ms_epoch * 1e-3) / 1e9
     policy = {0: "store", 1: "atomic", 2: "jacobi"}[info["update_mode"]]
+    # random-gather ceiling: the epoch's reads alone (col stream, 1 + k random
+    # 8-byte device-scope position reads per directed edge, the source per
+    # chunk) at the epoch's launch shape; the epoch makes the same reads and
+    # more, so it cannot beat this time.  The read-modify-write patterns
+    # (every touched position written back, by plain stores or by atomics)
+    # are reported beside it.
     gather = {}
+    cache_probe = {}
     if info["engine"] == SL.LAYOUT_ENGINE_GLOBAL and dim == 2:
         h = SL.layout_create_ex(rp_d, col_d, g.n, 2, k, T, seed, opts(), 1)
-        for name, m in (("store", SL.LAYOUT_HOGWILD_STORE), ("atomic", SL.LAYOUT_ATOMIC)):
+        for name, m in (("read", SL.LAYOUT_GATHER_READ), ("store", SL.LAYOUT_HOGWILD_STORE),
+                        ("atomic", SL.LAYOUT_ATOMIC)):
             SL.layout_bench_gather(h, m, 2)
             gather[name] = SL.layout_bench_gather(h, m, 5)
         SL.layout_destroy(h)
+    if args.cache_probe and dim == 2:
+        # the gather pattern with each cache policy of the position accesses
+        # (device-scope as in the epoch, plain, non-temporal), reads alone and
+        # read-modify-writes, on a global-engine layout of the same graph
+        o = opts()
+        o.engine = SL.LAYOUT_ENGINE_GLOBAL
+        h = SL.layout_create_ex(rp_d, col_d, g.n, 2, k, T, seed, o, 1)
+        per_launch = g.row_ptr[-1] * (1 + k)
+        for cname, cbits in (("device", 0), ("plain", SL.LAYOUT_GATHER_PLAIN),
+                             ("nontemporal", SL.LAYOUT_GATHER_NONTEMPORAL)):
+            for kname, kbits in (("read", SL.LAYOUT_GATHER_READ),
+                                 ("rmw", SL.LAYOUT_HOGWILD_STORE)):
+                SL.layout_bench_gather(h, kbits | cbits, 1)
+                ms = SL.layout_bench_gather(h, kbits | cbits, 5)
+                cache_probe[f"{kname}_{cname}"] = {
+                    "ms": round(ms, 4),
+                    "G_accesses_per_s": round(float(per_launch) / (ms * 1e-3) / 1e9, 2)}
+        SL.layout_destroy(h)
+        log(f"[bench] cache probe {cache_probe}")
     copy_ms = SL.layout_bench_copy(1 << 30, 5)
     copy_gbs = 2 * (1 << 30) / (copy_ms * 1e-3) / 1e9
     log(f"[bench] epoch {ms_epoch:.3f} ms, {achieved:.1f} GB/s algorithmic, gather {gather}, "
@@ -243,9 +272,11 @@ def bench_plain(args):
         roof["xcd_l2_rmw"] = {"achieved_G_per_s": round(float(rmw), 2), "ceiling_G_per_s": 18.1,
                               "frac": round(float(rmw) / 18.1, 3)}
     if gather:
-        roof["gather_roofline_ms"] = round(gather[policy if policy in gather else "store"], 4)
-        roof["gather_roofline_frac"] = round(roof["gather_roofline_ms"] / ms_epoch, 4)
-        roof["gather_roofline_ms_by_policy"] = {k_: round(v, 4) for k_, v in gather.items()}
+        roof["gather_roofline_ms"] = round(gather["read"], 4)
+        roof["gather_roofline_frac"] = round(gather["read"] / ms_epoch, 4)
+        roof["gather_pattern_ms"] = {k_: round(v, 4) for k_, v in gather.items()}
+    if cache_probe:
+        roof["cache_probe"] = cache_probe
     cpu = None
     if not args.no_cpu and maker.startswith("gpu:"):
         log("[bench] no CPU baseline for a device-generated workload (headline workload only)")
@@ -487,6 +518,8 @@ def main():
     ap.add_argument("--bundle", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cache-probe", action="store_true",
+                    help="also time the gather pattern under each cache policy")
     ap.add_argument("--profile-epochs", type=int, default=0,
                     help="only run this many epochs on one handle (for profilers)")
     ap.add_argument("--profile-copy", action="store_true",

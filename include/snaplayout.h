@@ -355,11 +355,24 @@ int layout_debug_chunks(const layout_t *L, int64_t *begin_out, int32_t *src_out)
 /* Copies the alias table (n entries each) used by LAYOUT_NEG_DEGREE. */
 int layout_debug_alias(const layout_t *L, uint32_t *thr_out, uint32_t *alias_out);
 
+/* Modes of layout_bench_gather beyond LAYOUT_HOGWILD_STORE / LAYOUT_ATOMIC
+ * (read-modify-writes): the reads alone, and (OR-ed in) the cache bits of
+ * every position access instead of the epoch's device-scope ones. */
+enum {
+    LAYOUT_GATHER_READ = 4,          /* the 1 + k random reads, no write */
+    LAYOUT_GATHER_PLAIN = 0x10,      /* plain (L2-cached, not device-coherent) */
+    LAYOUT_GATHER_NONTEMPORAL = 0x20 /* non-temporal */
+};
+
 /* Random-gather roofline of the handle's graph: the memory pattern of one
- * epoch (stream col, one read-modify-write at col[e] and k at hashed uniform
- * nodes per directed edge) without force arithmetic or generator.  mode:
- * LAYOUT_HOGWILD_STORE or LAYOUT_ATOMIC.  Runs reps launches, reports the
- * mean launch time in *ms.  Perturbs the positions slightly (use on a scratch
+ * epoch (stream col; per directed edge one position access at col[e] and k
+ * at hashed uniform nodes; the source per chunk) without force arithmetic or
+ * generator, at the epoch's launch shape.  mode: LAYOUT_HOGWILD_STORE or
+ * LAYOUT_ATOMIC (read-modify-writes, every touched position written), or
+ * LAYOUT_GATHER_READ (the same reads, nothing written: a lower bound on the
+ * epoch's time), optionally OR LAYOUT_GATHER_PLAIN / _NONTEMPORAL (not with
+ * ATOMIC).  Runs reps launches, reports the mean launch time in *ms.  The
+ * read-modify-write modes perturb the positions slightly (use on a scratch
  * job).  Global-engine layouts only (E_UNSUPPORTED otherwise). */
 int layout_bench_gather(layout_t *L, int32_t mode, int32_t reps, float *ms);
 

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "desc.hpp"
+#include "snaplayout.h"
 #include "rng.hpp"
 
 namespace snap {
@@ -89,6 +90,34 @@ int pmds_positions(hipStream_t stream, const int64_t* d_row, const int32_t* d_co
                    int32_t pivots, uint64_t seed, float2* d_Y, int32_t* d_pivots_out,
                    int32_t* d_dist_out, int32_t* pivots_used);
 void launch_fill_zero(hipStream_t stream, float2* d_p, int64_t n);
+// Silhouette monitor (the SI metric of Sec. 4.1, exact): host side (clusters
+// 0..C-1 in order of label value, nodes counting-sorted by cluster) ...
+struct SilhouetteInput {
+  int32_t C = 0;
+  std::vector<int32_t> order, cs, cstart;
+};
+int silhouette_input(const int32_t* labels, int32_t n, const double* si_out,
+                     SilhouetteInput& in);
+// ... and device side: node order (n), cluster of each sorted node (n),
+// cluster starts (C + 1), sorted positions (n), two FP64 sums.
+struct SilhouetteBuffers {
+  int32_t *order = nullptr, *cs = nullptr, *cstart = nullptr;
+  float2* Ys = nullptr;
+  double* acc = nullptr;
+};
+// Copies the inputs into b, runs the gather and the exact silhouette kernel on
+// the positions d_Y and writes the mean to *si_out (synchronises stream).
+int silhouette_run(hipStream_t stream, const float2* d_Y, int32_t n, const SilhouetteInput& in,
+                   const SilhouetteBuffers& b, double* si_out);
+// What other translation units may read of a layout handle: its size,
+// device, stream and device positions.  LAYOUT_E_INVALID_ARG for NULL.
+struct HandleView {
+  int32_t n = 0, dim = 2;
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  float2* Y = nullptr;
+};
+int handle_view(const layout_t* L, HandleView* v);
 // Jacobi apply of one 2D graph: Y += D, then D = 0.
 void launch_jacobi_apply(hipStream_t stream, float2* d_Y, float2* d_D, int32_t n);
 // CQ of the positions (cluster.hip): k-means (k-means++ start from seed, or

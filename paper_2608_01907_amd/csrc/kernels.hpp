@@ -787,9 +787,16 @@ static __global__ void copy_kernel(const float4* __restrict__ src, float4* __res
 }
 
 // The memory pattern of an epoch without the force arithmetic or the
-// generator: per directed edge one read-modify-write at col[e] and k at
+// generator: per directed edge the col stream, one access at col[e] and k at
 // hashed uniform nodes, plus the source per chunk (random-gather roofline).
-template <int K, int MODE, class M>
+// KIND kGatherStore / kGatherAtomic: read-modify-writes (plain stores of
+// every touched position, or float atomic adds); kGatherRead: the reads
+// alone (a lower bound on the epoch's time, which makes the same reads and
+// more).  The loaded values feed a per-lane sum that is written back only on
+// a bit pattern no sum of finite positions takes, so no load is dropped.
+enum : int { kGatherStore = 0, kGatherAtomic = 1, kGatherRead = 2 };
+
+template <int K, int KIND, class M>
 __device__ __forceinline__ void gather_rmw_chunk(const M& mem, const GraphDesc& g, int64_t c) {
   const int64_t e0 = *gptr(g.chunk_begin + c);
   const int64_t e_end = *gptr(g.chunk_begin + c + 1);
@@ -811,33 +818,40 @@ __device__ __forceinline__ void gather_rmw_chunk(const M& mem, const GraphDesc& 
 #pragma unroll
     for (int m = 0; m < K; ++m) ys[m] = mem.load(g.Y + s[m]);
     yi.x += 1e-7f * yj.x;
-    if constexpr (MODE == kAtomic) {
+    if constexpr (KIND == kGatherAtomic) {
       mem.add(g.Y + j, make_float2(1e-7f * yj.y, 0.f));
 #pragma unroll
       for (int m = 0; m < K; ++m) mem.add(g.Y + s[m], make_float2(1e-7f * ys[m].y, 0.f));
-    } else {
+    } else if constexpr (KIND == kGatherStore) {
       mem.store(g.Y + j, make_float2(yj.x + 1e-7f * yj.y, yj.y));
 #pragma unroll
       for (int m = 0; m < K; ++m)
         mem.store(g.Y + s[m], make_float2(ys[m].x + 1e-7f * ys[m].y, ys[m].y));
+    } else {
+#pragma unroll
+      for (int m = 0; m < K; ++m) yi.y += ys[m].y;
     }
   }
-  mem.store(g.Y + i, yi);
+  if constexpr (KIND == kGatherRead) {
+    if (__float_as_uint(yi.x) == 0x7FC00001u) mem.store(g.Y + i, yi);  // never (a NaN payload)
+  } else {
+    mem.store(g.Y + i, yi);
+  }
 }
 
-// Same memory path as the single-graph epoch: BufferMem when the positions
-// fit 32-bit offsets, else Mem.
-template <int K, int MODE, class Mem>
+// Same memory path as the single-graph epoch: BufferMem (cache bits AUX, 16 =
+// device scope as in the epoch) when the positions fit 32-bit offsets, else Mem.
+template <int K, int KIND, class Mem, int AUX = 16>
 static __global__ void __launch_bounds__(256) gather_rmw_kernel(const GraphDesc* __restrict__ table,
                                                          int64_t total_chunks) {
   const GraphDesc& g = table[0];
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   const int64_t first = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (int64_t(g.n) * 8 < (int64_t(1) << 32)) {
-    const BufferMem<float2> mem(g.Y, g.n);
-    for (int64_t c = first; c < total_chunks; c += stride) gather_rmw_chunk<K, MODE>(mem, g, c);
+    const BufferMem<float2, AUX> mem(g.Y, g.n);
+    for (int64_t c = first; c < total_chunks; c += stride) gather_rmw_chunk<K, KIND>(mem, g, c);
   } else {
-    for (int64_t c = first; c < total_chunks; c += stride) gather_rmw_chunk<K, MODE>(Mem{}, g, c);
+    for (int64_t c = first; c < total_chunks; c += stride) gather_rmw_chunk<K, KIND>(Mem{}, g, c);
   }
 }
 

@@ -659,6 +659,71 @@ void snap::launch_fill_zero(hipStream_t stream, float2* d_p, int64_t n) {
   hipLaunchKernelGGL(fill_zero_kernel, dim3(div_up(n, 256)), dim3(256), 0, stream, d_p, n);
 }
 
+int snap::silhouette_input(const int32_t* labels, int32_t n, const double* si_out,
+                           SilhouetteInput& in) {
+  if (!labels || !si_out) return fail(LAYOUT_E_INVALID_ARG, "NULL labels or si_out");
+  if (n < 2) return fail(LAYOUT_E_INVALID_ARG, "silhouette needs at least 2 nodes");
+  std::vector<int32_t> lv(labels, labels + n);
+  std::vector<int32_t> uniq(lv);
+  std::sort(uniq.begin(), uniq.end());
+  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+  in.C = static_cast<int32_t>(uniq.size());
+  if (in.C < 2) return fail(LAYOUT_E_INVALID_ARG, "silhouette needs at least 2 clusters");
+  std::vector<int32_t> cid(n);
+  in.cstart.assign(size_t(in.C) + 1, 0);
+  in.order.resize(n);
+  in.cs.resize(n);
+  for (int32_t v = 0; v < n; ++v) {
+    cid[v] = static_cast<int32_t>(std::lower_bound(uniq.begin(), uniq.end(), lv[v]) - uniq.begin());
+    ++in.cstart[size_t(cid[v]) + 1];
+  }
+  for (int32_t c = 0; c < in.C; ++c) in.cstart[size_t(c) + 1] += in.cstart[c];
+  std::vector<int32_t> fill(in.cstart.begin(), in.cstart.end() - 1);
+  for (int32_t v = 0; v < n; ++v) {
+    const int32_t q = fill[cid[v]]++;
+    in.order[q] = v;
+    in.cs[q] = cid[v];
+  }
+  return LAYOUT_OK;
+}
+
+namespace {
+static __global__ void zero_f64_kernel(double* __restrict__ p, int32_t count) {
+  const int32_t i = int32_t(blockIdx.x) * blockDim.x + int32_t(threadIdx.x);
+  if (i < count) p[i] = 0.0;
+}
+}  // namespace
+
+int snap::silhouette_run(hipStream_t stream, const float2* d_Y, int32_t n,
+                         const SilhouetteInput& in, const SilhouetteBuffers& b, double* si_out) {
+  hipError_t e = hipMemcpyAsync(b.order, in.order.data(), sizeof(int32_t) * size_t(n),
+                                hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.cs, in.cs.data(), sizeof(int32_t) * size_t(n), hipMemcpyHostToDevice,
+                       stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.cstart, in.cstart.data(), sizeof(int32_t) * (size_t(in.C) + 1),
+                       hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) {
+    // cleared by a kernel rather than a memset node, so that the sequence may
+    // sit in a captured graph
+    hipLaunchKernelGGL(zero_f64_kernel, dim3(1), dim3(64), 0, stream, b.acc, 2);
+    const int grid = static_cast<int>(div_up(n, 256));
+    hipLaunchKernelGGL(gather_positions_kernel, dim3(grid), dim3(256), 0, stream, d_Y, b.order, n,
+                       b.Ys);
+    hipLaunchKernelGGL(silhouette_kernel, dim3(grid), dim3(256), 0, stream, b.Ys, b.cs, b.cstart,
+                       n, b.acc);
+    e = hipGetLastError();
+  }
+  double out[2] = {0.0, 0.0};
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, b.acc, 2 * sizeof(double), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "silhouette");
+  *si_out = out[0] / double(n);
+  return LAYOUT_OK;
+}
+
 void snap::launch_jacobi_apply(hipStream_t stream, float2* d_Y, float2* d_D, int32_t n) {
   if (n <= 0) return;
   hipLaunchKernelGGL(jacobi_apply_kernel<float2>, dim3(div_up(n, 256)), dim3(256), 0, stream, d_Y,
@@ -676,6 +741,16 @@ bool check_handle(const layout_t* L) {
 }
 
 }  // namespace
+
+int snap::handle_view(const layout_t* L, HandleView* v) {
+  if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
+  v->n = L->n;
+  v->dim = L->dim;
+  v->dev = L->dev;
+  v->stream = L->stream;
+  v->Y = L->host_desc.Y;
+  return LAYOUT_OK;
+}
 
 // --------------------------------------------------------------------- ABI
 // ---------------------------------------------------------- energy monitors
@@ -1218,67 +1293,25 @@ int layout_effective_energy(layout_t* L, double* attr_out, double* rep_out) {
 int layout_silhouette(layout_t* L, const int32_t* labels, double* si_out) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (L->dim != 2) return fail(LAYOUT_E_UNSUPPORTED, "the silhouette monitor is 2D");
-  if (!labels || !si_out) return fail(LAYOUT_E_INVALID_ARG, "NULL labels or si_out");
-  const int32_t n = L->n;
-  if (n < 2) return fail(LAYOUT_E_INVALID_ARG, "silhouette needs at least 2 nodes");
-  // clusters 0..C-1 in order of label value; nodes counting-sorted by cluster
-  std::vector<int32_t> lv(labels, labels + n);
-  std::vector<int32_t> uniq(lv);
-  std::sort(uniq.begin(), uniq.end());
-  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
-  const int32_t C = static_cast<int32_t>(uniq.size());
-  if (C < 2) return fail(LAYOUT_E_INVALID_ARG, "silhouette needs at least 2 clusters");
-  std::vector<int32_t> cid(n), cstart(size_t(C) + 1, 0), order(n), cs(n);
-  for (int32_t v = 0; v < n; ++v) {
-    cid[v] = static_cast<int32_t>(std::lower_bound(uniq.begin(), uniq.end(), lv[v]) - uniq.begin());
-    ++cstart[size_t(cid[v]) + 1];
-  }
-  for (int32_t c = 0; c < C; ++c) cstart[size_t(c) + 1] += cstart[c];
-  {
-    std::vector<int32_t> fill(cstart.begin(), cstart.end() - 1);
-    for (int32_t v = 0; v < n; ++v) {
-      const int32_t q = fill[cid[v]]++;
-      order[q] = v;
-      cs[q] = cid[v];
-    }
-  }
-  int rc = energy_buffer(L);
+  SilhouetteInput in;
+  int rc = silhouette_input(labels, L->n, si_out, in);
   if (rc != LAYOUT_OK) return rc;
-  int32_t *d_order = nullptr, *d_cs = nullptr, *d_cstart = nullptr;
-  float2* d_Ys = nullptr;
-  hipError_t e = hipMalloc(&d_order, sizeof(int32_t) * size_t(n));
-  if (e == hipSuccess) e = hipMalloc(&d_cs, sizeof(int32_t) * size_t(n));
-  if (e == hipSuccess) e = hipMalloc(&d_cstart, sizeof(int32_t) * (size_t(C) + 1));
-  if (e == hipSuccess) e = hipMalloc(&d_Ys, sizeof(float2) * size_t(n));
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(d_order, order.data(), sizeof(int32_t) * size_t(n), hipMemcpyHostToDevice,
-                       L->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(d_cs, cs.data(), sizeof(int32_t) * size_t(n), hipMemcpyHostToDevice,
-                       L->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(d_cstart, cstart.data(), sizeof(int32_t) * (size_t(C) + 1),
-                       hipMemcpyHostToDevice, L->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(L->d_energy, 0, 2 * sizeof(double), L->stream);
-  if (e == hipSuccess) {
-    const int grid = static_cast<int>(div_up(n, 256));
-    hipLaunchKernelGGL(gather_positions_kernel, dim3(grid), dim3(256), 0, L->stream,
-                       L->host_desc.Y, d_order, n, d_Ys);
-    hipLaunchKernelGGL(silhouette_kernel, dim3(grid), dim3(256), 0, L->stream, d_Ys, d_cs,
-                       d_cstart, n, L->d_energy);
-    e = hipGetLastError();
-  }
-  double out[2] = {0.0, 0.0};
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(out, L->d_energy, 2 * sizeof(double), hipMemcpyDeviceToHost, L->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
-  if (d_order) (void)hipFree(d_order);
-  if (d_cs) (void)hipFree(d_cs);
-  if (d_cstart) (void)hipFree(d_cstart);
-  if (d_Ys) (void)hipFree(d_Ys);
-  if (e != hipSuccess) return hip_fail(e, "silhouette");
-  *si_out = out[0] / double(n);
-  return LAYOUT_OK;
+  rc = energy_buffer(L);
+  if (rc != LAYOUT_OK) return rc;
+  const int32_t n = L->n;
+  SilhouetteBuffers b;
+  b.acc = L->d_energy;
+  hipError_t e = hipMalloc(&b.order, sizeof(int32_t) * size_t(n));
+  if (e == hipSuccess) e = hipMalloc(&b.cs, sizeof(int32_t) * size_t(n));
+  if (e == hipSuccess) e = hipMalloc(&b.cstart, sizeof(int32_t) * (size_t(in.C) + 1));
+  if (e == hipSuccess) e = hipMalloc(&b.Ys, sizeof(float2) * size_t(n));
+  rc = e == hipSuccess ? silhouette_run(L->stream, L->host_desc.Y, n, in, b, si_out)
+                       : hip_fail(e, "silhouette buffers");
+  if (b.order) (void)hipFree(b.order);
+  if (b.cs) (void)hipFree(b.cs);
+  if (b.cstart) (void)hipFree(b.cstart);
+  if (b.Ys) (void)hipFree(b.Ys);
+  return rc;
 }
 
 int layout_neighbourhood(layout_t* L, const int32_t* nodes, int32_t count, int32_t radius,
@@ -1463,41 +1496,58 @@ int layout_bench_gather(layout_t* L, int32_t mode, int32_t reps, float* ms) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (L->dim != 2) return fail(LAYOUT_E_UNSUPPORTED, "the gather roofline is 2D");
   if (!ms || reps < 1) return fail(LAYOUT_E_INVALID_ARG, "ms NULL or reps < 1");
-  if (mode != kStore && mode != kAtomic) return fail(LAYOUT_E_INVALID_ARG, "mode %d", mode);
+  const int32_t kind_bits = mode & 0xF, cache_bits = mode & ~0xF;
+  if (kind_bits != LAYOUT_HOGWILD_STORE && kind_bits != LAYOUT_ATOMIC &&
+      kind_bits != LAYOUT_GATHER_READ)
+    return fail(LAYOUT_E_INVALID_ARG, "mode %d", mode);
+  if (cache_bits != 0 && cache_bits != LAYOUT_GATHER_PLAIN && cache_bits != LAYOUT_GATHER_NONTEMPORAL)
+    return fail(LAYOUT_E_INVALID_ARG, "mode %d: unknown cache bits", mode);
+  if (kind_bits == LAYOUT_ATOMIC && cache_bits != 0)
+    return fail(LAYOUT_E_INVALID_ARG, "atomic gathers take the device-scope accesses only");
   if (L->nnz == 0) {
     *ms = 0.f;
     return LAYOUT_OK;
   }
   if (L->engine != LAYOUT_ENGINE_GLOBAL)
     return fail(LAYOUT_E_UNSUPPORTED, "gather roofline runs on the global engine layout");
+  const int kind = kind_bits == LAYOUT_ATOMIC ? kGatherAtomic
+                   : kind_bits == LAYOUT_GATHER_READ ? kGatherRead
+                                                     : kGatherStore;
+  const int aux = cache_bits == LAYOUT_GATHER_PLAIN ? 0
+                  : cache_bits == LAYOUT_GATHER_NONTEMPORAL ? 2
+                                                            : 16;
   hipEvent_t a, b;
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
   if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  const GlobalGroup gg = global_group_of(L);
+  const int grid = global_grid(gg);
+  auto launch = [&](auto kernel) -> int {
+    hipError_t ee = hipEventRecord(a, L->stream);
+    for (int r = 0; r < reps && ee == hipSuccess; ++r) {
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(gg.block), 0, L->stream, L->d_table,
+                         L->n_chunks);
+      ee = hipGetLastError();
+    }
+    if (ee == hipSuccess) ee = hipEventRecord(b, L->stream);
+    if (ee == hipSuccess) ee = hipEventSynchronize(b);
+    float t = 0.f;
+    if (ee == hipSuccess) ee = hipEventElapsedTime(&t, a, b);
+    if (ee != hipSuccess) return hip_fail(ee, "gather benchmark");
+    *ms = t / reps;
+    return LAYOUT_OK;
+  };
   int rc = with_k(L->k, [&](auto kc) -> int {
     constexpr int K = decltype(kc)::value;
-    return with_mode(mode, [&](auto mc) -> int {
-      constexpr int MODE = decltype(mc)::value;
-      if constexpr (MODE == kJacobi) {
-        return LAYOUT_E_INVALID_ARG;
-      } else {
-        GlobalGroup gg = global_group_of(L);
-        gg.mode = MODE;
-        const int grid = global_grid(gg);
-        hipError_t ee = hipEventRecord(a, L->stream);
-        for (int r = 0; r < reps && ee == hipSuccess; ++r) {
-          hipLaunchKernelGGL((gather_rmw_kernel<K, MODE, GlobalMem>), dim3(grid), dim3(gg.block),
-                             0, L->stream, L->d_table, L->n_chunks);
-        }
-        if (ee == hipSuccess) ee = hipEventRecord(b, L->stream);
-        if (ee == hipSuccess) ee = hipEventSynchronize(b);
-        float t = 0.f;
-        if (ee == hipSuccess) ee = hipEventElapsedTime(&t, a, b);
-        if (ee != hipSuccess) return hip_fail(ee, "gather benchmark");
-        *ms = t / reps;
-        return LAYOUT_OK;
-      }
-    });
+    if (kind == kGatherAtomic) return launch(gather_rmw_kernel<K, kGatherAtomic, GlobalMem, 16>);
+    auto by_cache = [&](auto kind_c) -> int {
+      constexpr int KIND = decltype(kind_c)::value;
+      if (aux == 0) return launch(gather_rmw_kernel<K, KIND, GlobalMem, 0>);
+      if (aux == 2) return launch(gather_rmw_kernel<K, KIND, GlobalMem, 2>);
+      return launch(gather_rmw_kernel<K, KIND, GlobalMem, 16>);
+    };
+    if (kind == kGatherRead) return by_cache(std::integral_constant<int, kGatherRead>{});
+    return by_cache(std::integral_constant<int, kGatherStore>{});
   });
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);

@@ -35,6 +35,9 @@ LAYOUT_ENGINE_AUTO = 0
 LAYOUT_ENGINE_GLOBAL = 1
 LAYOUT_ENGINE_LDS = 2
 LAYOUT_ENGINE_XCD = 3
+LAYOUT_GATHER_READ = 4
+LAYOUT_GATHER_PLAIN = 0x10
+LAYOUT_GATHER_NONTEMPORAL = 0x20
 
 _NAMES = {
     LAYOUT_E_INVALID_ARG: "LAYOUT_E_INVALID_ARG", LAYOUT_E_BAD_GRAPH: "LAYOUT_E_BAD_GRAPH",

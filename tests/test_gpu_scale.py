@@ -28,7 +28,8 @@ def big():
     from synthgraph import gpu as G
     if not torch.cuda.is_available():
         pytest.skip("needs the GPU")
-    rp, col, labels = G.friendster_like_gpu(seed=0)
+    from conftest import generate_on_device
+    rp, col, labels = generate_on_device(G.friendster_like_gpu, seed=0)
     torch.cuda.synchronize()
     yield rp, col, labels
     del rp, col, labels

@@ -46,8 +46,9 @@ def test_create64_equals_int32_entry():
 def full():
     import time
     from synthgraph import gpu as G
+    from conftest import generate_on_device
     t0 = time.perf_counter()
-    rp, col, labels = G.friendster_full_gpu(seed=0)
+    rp, col, labels = generate_on_device(G.friendster_full_gpu, seed=0)
     del labels
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
