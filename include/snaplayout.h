@@ -273,6 +273,20 @@ int layout_effective_energy(layout_t *L, double *attr_out, double *rep_out);
  * Allocates and frees temporary device memory. */
 int layout_silhouette(layout_t *L, const int32_t *labels, double *si_out);
 
+/* Largest node count layout_silhouette_noalloc takes. */
+#define LAYOUT_NOALLOC_MAX_NODES (1 << 18)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * silhouette of layout_silhouette, the same kernels and result, with its
+ * working memory (5 MiB) in a fixed device array that each GPU holds for the
+ * life of the process instead of temporary allocations; it allocates no
+ * device memory.  n <= LAYOUT_NOALLOC_MAX_NODES, else LAYOUT_E_UNSUPPORTED.
+ * Calls that overlap on one GPU (other threads or streams) share the array
+ * and race; each call clears what must start at zero.  Synchronises the
+ * handle's stream.  Other errors as layout_silhouette. */
+int layout_silhouette_noalloc(layout_t *L, const int32_t *labels, double *si_out);
+
 /* Neighbourhood preservation of the current positions at the listed query
  * nodes (the NP metric of Sec. 4.1, exact for each query rather than through
  * a spatial index).  For query i: R_i = the nodes at hop distance 1..radius

@@ -35,6 +35,7 @@ LAYOUT_ENGINE_AUTO = 0
 LAYOUT_ENGINE_GLOBAL = 1
 LAYOUT_ENGINE_LDS = 2
 LAYOUT_ENGINE_XCD = 3
+LAYOUT_NOALLOC_MAX_NODES = 1 << 18
 LAYOUT_GATHER_READ = 4
 LAYOUT_GATHER_PLAIN = 0x10
 LAYOUT_GATHER_NONTEMPORAL = 0x20
@@ -145,6 +146,7 @@ _SIGNATURES = {
     "layout_get_info": (ctypes.c_int, [_vp, ctypes.POINTER(layout_info)]),
     "layout_debug_draws": (ctypes.c_int, [_vp, _i32, _vp]),
     "layout_silhouette": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "layout_silhouette_noalloc": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_double)]),
     "layout_neighbourhood": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp,
                                             ctypes.POINTER(ctypes.c_double)]),
     "layout_cluster_quality": (ctypes.c_int, [_vp, _vp, _i32, _u64, _i32, _vp,
@@ -379,6 +381,15 @@ def layout_silhouette(h, labels):
     lab = np.ascontiguousarray(labels, dtype=np.int32)
     out = ctypes.c_double()
     _check(lib().layout_silhouette(h, lab.ctypes.data, ctypes.byref(out)))
+    return out.value
+
+
+def layout_silhouette_noalloc(h, labels):
+    """As layout_silhouette, with the library's fixed device scratch array
+    instead of temporary allocations (at most 2^18 nodes)."""
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    out = ctypes.c_double()
+    _check(lib().layout_silhouette_noalloc(h, lab.ctypes.data, ctypes.byref(out)))
     return out.value
 
 
