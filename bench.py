@@ -122,6 +122,8 @@ def bench_plain(args):
         from synthgraph import gpu as G
         make = G.friendster_full_gpu if maker == "gpu:friendster_full" else G.friendster_like_gpu
         rp_d, col_d, labels_d = make(seed=0)
+        if args.relabel != "none":
+            rp_d, col_d, labels_d = G.relabel_gpu(rp_d, col_d, labels_d, args.relabel)
         del labels_d
         torch.cuda.empty_cache()
         row_ptr = rp_d.cpu().numpy()
@@ -129,9 +131,14 @@ def bench_plain(args):
         nnz = int(row_ptr[-1])
     else:
         g = S.cached(args.workload, getattr(S, maker))
+        if args.relabel != "none":
+            g = S.relabel(g, args.relabel)
         rp_d = torch.from_numpy(g.row_ptr).to(dev)
         col_d = torch.from_numpy(g.col).to(dev)
         nnz = g.nnz
+    if args.relabel != "none":
+        log(f"[bench] nodes relabelled in {args.relabel} order (input preprocessing; the "
+            f"draws are those of the relabelled graph)")
     n_edges = nnz // 2
     log(f"[bench] graph {g.name}: n={g.n} |E|={n_edges} nnz={nnz} "
         f"dmax={int(np.diff(g.row_ptr).max())} ({time.perf_counter() - t0:.1f}s)")
@@ -253,7 +260,8 @@ def bench_plain(args):
     copy_gbs = 2 * (1 << 30) / (copy_ms * 1e-3) / 1e9
     log(f"[bench] epoch {ms_epoch:.3f} ms, {achieved:.1f} GB/s algorithmic, gather {gather}, "
         f"copy {copy_gbs:.0f} GB/s")
-    traffic, tinfo = committed_traffic(args.workload) if dim == 2 else (None, None)
+    traffic, tinfo = (committed_traffic(args.workload) if dim == 2 and args.relabel == "none"
+                      else (None, None))
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": {SL.LAYOUT_ENGINE_GLOBAL: "epoch_global_kernel",
@@ -291,7 +299,8 @@ def bench_plain(args):
         "value": value, "unit": "edge-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": g.name, "n": g.n, "edges": n_edges, "k": k, "epochs": T,
+        "config": {"workload": g.name, "relabel": args.relabel, "n": g.n, "edges": n_edges,
+                   "k": k, "epochs": T,
                    "dim": dim, "update_mode": policy, "engine": info["engine"],
                    "bundle_edges": info["bundle_edges"],
                    "hub_split_edges": info["hub_split_edges"],
@@ -518,6 +527,9 @@ def main():
     ap.add_argument("--bundle", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--relabel", default="none", choices=["none", "degree", "community"],
+                    help="plain workloads: renumber the nodes before the run (descending "
+                         "degree, or by community then degree) to measure locality")
     ap.add_argument("--cache-probe", action="store_true",
                     help="also time the gather pattern under each cache policy")
     ap.add_argument("--profile-epochs", type=int, default=0,

@@ -349,6 +349,9 @@ __device__ __forceinline__ void process_chunk(const Mem& mem, const GraphDesc& g
       yi_start = yi;
       acc = vzero<P>();
     }
+    // the generator work sits between the col load and the gathers, so that
+    // it hides the col load's latency (and that of the previous edge's
+    // stores, which the same memory counter tracks)
     const int32_t j = __builtin_nontemporal_load(gptr(g.col + e));
     uint32_t s[KS];
     draw_k<K, DEGREE>(g, e, static_cast<uint32_t>(t), static_cast<uint32_t>(i), s);

@@ -387,3 +387,33 @@ def many_graphs(kind: str, count: int, seed: int = 0, workers: int | None = None
         z = np.load(paths[q], allow_pickle=False)
         out.append(Graph(z["row_ptr"], z["col"], int(z["n"]), z["labels"], f"{kind}{seed}-{q}"))
     return out
+
+
+# ------------------------------------------------------------ relabelling
+def relabel_order(deg: np.ndarray, labels: np.ndarray | None, order: str) -> np.ndarray:
+    """New-to-old node permutation: 'degree' puts nodes in descending degree
+    (ties by old id); 'community' groups nodes by planted community, each
+    community in descending degree."""
+    idx = np.arange(deg.size)
+    if order == "degree":
+        return np.lexsort((idx, -deg.astype(np.int64)))
+    if order == "community":
+        return np.lexsort((idx, -deg.astype(np.int64), labels))
+    raise ValueError(f"unknown order {order!r}")
+
+
+def relabel(g: Graph, order: str) -> Graph:
+    """The same graph with nodes renumbered by relabel_order (input
+    preprocessing: rows and neighbour lists stay sorted)."""
+    deg = np.diff(g.row_ptr.astype(np.int64))
+    perm = relabel_order(deg, g.labels, order)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.size)
+    deg_new = deg[perm]
+    rp = np.zeros(g.n + 1, np.int64)
+    np.cumsum(deg_new, out=rp[1:])
+    row_of = np.repeat(np.arange(g.n, dtype=np.int64), deg_new)
+    old_e = g.row_ptr.astype(np.int64)[perm][row_of] + (np.arange(rp[-1]) - rp[row_of])
+    col = inv[g.col[old_e]].astype(np.int64)
+    col = col[np.lexsort((col, row_of))].astype(np.int32)
+    return Graph(rp.astype(g.row_ptr.dtype), col, g.n, g.labels[perm], f"{g.name}-{order}")

@@ -232,3 +232,44 @@ def friendster_full_gpu(seed: int = 0, device: str = "cuda:0"):
     return chung_lu_communities_gpu(n, m, tau=2.2, dmax=math.sqrt(2 * m),
                                     n_comm=n // 1300, intra=0.9, seed=seed, device=device,
                                     progress=True)
+
+
+def relabel_gpu(rp, col, labels, order: str):
+    """Device version of synthgraph.relabel for graphs generated here (torch
+    tensors; int64 row pointers, int32 columns; at most 2^31 - 1 directed
+    edges, the limit of one torch sort)."""
+    import torch
+
+    n = rp.numel() - 1
+    nnz = int(rp[-1])
+    if nnz >= 2**31 - 1:
+        raise ValueError("relabel_gpu sorts the edges at once: nnz < 2^31 - 1")
+    dev = rp.device
+    deg = (rp[1:] - rp[:-1]).to(torch.int64)
+    dmax = int(deg.max()) if n else 0
+    if order == "degree":
+        key = dmax - deg
+    elif order == "community":
+        key = labels.to(torch.int64) * (dmax + 1) + (dmax - deg)
+    else:
+        raise ValueError(f"unknown order {order!r}")
+    perm = torch.sort(key, stable=True).indices
+    del key
+    inv = torch.empty_like(perm)
+    inv[perm] = torch.arange(n, device=dev)
+    deg_new = deg[perm]
+    rp_new = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    torch.cumsum(deg_new, 0, out=rp_new[1:])
+    row_of = torch.repeat_interleave(torch.arange(n, device=dev), deg_new)
+    old_e = rp.to(torch.int64)[perm][row_of]
+    old_e += torch.arange(nnz, device=dev)
+    old_e -= rp_new[row_of]
+    c = inv[col[old_e].to(torch.int64)]
+    del old_e
+    c += row_of * n
+    del row_of
+    c = torch.sort(c).values
+    c -= torch.div(c, n, rounding_mode="floor") * n
+    col_new = c.to(torch.int32)
+    del c
+    return rp_new, col_new, labels[perm]
