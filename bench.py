@@ -17,7 +17,12 @@ The JSON line also carries
                    the committed rocprofv3 counter summary when it was taken on
                    the current kernel source (else null);
   cpu_baseline  -- the FP64 oracle's threaded bundle scheme timed on this
-                   host's cores on a bounded sample (a few epochs).
+                   host's cores on a bounded sample (a few epochs);
+  batched_and_served -- short runs of the other two workloads (default run
+                   only; --no-extra skips them): the 512-graph batch against
+                   one graph per launch (plain time from every 8th graph), and
+                   200 served jobs at 0.8 of the plain capacity, p50/p99
+                   against FIFO one job at a time.
 Other workloads (--workload): batched-512 (512 graphs in one HIP-graph
 replay, against one graph per launch) and served (a Poisson stream through
 the continuous-batching server, against FIFO one job at a time).
@@ -369,9 +374,14 @@ def bench_batched(args):
     replay_ms = SL.layout_batch_run_timed(hb)
     SL.layout_batch_destroy(hb)
     log(f"[bench] batched {dt * 1e3:.1f} ms/step, replay {replay_ms:.1f} ms; timing the plain path")
-    # plain path: one graph per launch sequence, same graphs
+    # plain path: one graph per launch sequence, same graphs; with a sample
+    # stride s > 1 only every s-th graph runs and the total is s times the
+    # sample's (graph sizes are drawn independently of the index)
+    stride = max(1, args.plain_stride)
     t0 = time.perf_counter()
     for q, g in enumerate([] if args.no_plain else gs):
+        if q % stride:
+            continue
         hp = SL.layout_create_ex(rps[q], cols[q], g.n, 2, k, T, q, SL.layout_opts_init(), 1)
         SL.layout_epoch(hp, T)
         SL.layout_sync(hp)
@@ -380,7 +390,7 @@ def bench_batched(args):
             log(f"[bench] plain path: {q + 1}/{len(gs)} graphs, "
                 f"{time.perf_counter() - t0:.1f}s")
     torch.cuda.synchronize()
-    plain_s = time.perf_counter() - t0
+    plain_s = (time.perf_counter() - t0) * stride
     plain_value = edges * (1 + k) * T / plain_s if not args.no_plain else None
     log(f"[bench] batched {dt * 1e3:.1f} ms/step (replay {replay_ms:.1f} ms), plain "
         f"{plain_s * 1e3:.1f} ms")
@@ -394,7 +404,8 @@ def bench_batched(args):
                    "global_graphs": info["global_graphs"], "autotune": tune},
         "replay_ms": round(replay_ms, 3),
         "plain_one_graph_per_launch": (None if args.no_plain else
-                                       {"value": plain_value, "seconds": round(plain_s, 3)}),
+                                       {"value": plain_value, "seconds": round(plain_s, 3),
+                                        "sampled_one_in": stride}),
         "speedup_vs_plain": value / plain_value if plain_value else None,
     }
 
@@ -539,6 +550,10 @@ def main():
     ap.add_argument("--graphs", type=int, default=512)
     ap.add_argument("--no-plain", action="store_true",
                     help="batched workload: skip timing the one-graph-at-a-time path")
+    ap.add_argument("--plain-stride", type=int, default=1,
+                    help="batched workload: time every n-th graph on the plain path only")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default workload: skip the short batched and served runs")
     ap.add_argument("--pool", type=int, default=48)
     ap.add_argument("--jobs", type=int, default=200)
     ap.add_argument("--rho", type=float, nargs="+", default=[0.5, 0.8])
@@ -562,8 +577,38 @@ def main():
         line = bench_served(args)
     else:
         line = bench_plain(args)
+        if line is not None and args.workload == "lj-like-4m" and not args.no_extra:
+            line["batched_and_served"] = extra_workloads(args)
     if line is not None:
         print(json.dumps(line), flush=True)
+
+
+def extra_workloads(args):
+    """Short runs of the batched and served workloads next to the headline
+    one, so that one default run reports all three (the full-length runs are
+    --workload batched-512 and --workload served)."""
+    out = {}
+    b = argparse.Namespace(**vars(args))
+    b.steps, b.warmup, b.graphs, b.no_plain, b.plain_stride = 2, 1, 512, False, 8
+    try:
+        r = bench_batched(b)
+        out["batched-512"] = {
+            "value": r["value"], "unit": r["unit"], "ms_per_step": r["ms_per_step"],
+            "replay_ms": r["replay_ms"], "config": r["config"],
+            "plain_one_graph_per_launch": r["plain_one_graph_per_launch"],
+            "speedup_vs_plain": r["speedup_vs_plain"]}
+    except Exception as exc:  # reported, never hides the headline line
+        out["batched-512"] = {"error": f"{type(exc).__name__}: {exc}"}
+    v = argparse.Namespace(**vars(args))
+    v.jobs, v.pool, v.rho = 200, 48, [0.8]
+    try:
+        r = bench_served(v)
+        out["served"] = {"value": r["value"], "unit": r["unit"], "config": r["config"],
+                         "plain_mean_service_s": r["plain_mean_service_s"],
+                         "by_load": r["by_load"], "saturation": r["saturation"]}
+    except Exception as exc:
+        out["served"] = {"error": f"{type(exc).__name__}: {exc}"}
+    return out
 
 
 if __name__ == "__main__":

@@ -63,6 +63,12 @@ enum {
     LAYOUT_INIT_PMDS = 1     /* Pivot MDS (Sec. 4.1), see layout_pmds */
 };
 
+/* Kernel of the forces (layout_opts.force_kernel). */
+enum {
+    LAYOUT_FORCE_T = 0,       /* Table 1, t-FDP row (Student-t kernel): the paper's method */
+    LAYOUT_FORCE_GAUSSIAN = 1 /* Gaussian kernel variant (future work in the conclusion) */
+};
+
 /* Distribution of the negatives. */
 enum {
     LAYOUT_NEG_UNIFORM = 0, /* uniform over V \ {i}: the paper's method (Algorithm 1) */
@@ -90,7 +96,8 @@ enum {
 typedef struct layout layout_t;
 
 typedef struct layout_opts {
-    float alpha, beta, gamma; /* t-force parameters, defaults 0.1, 8, 2 (Table 1) */
+    float alpha, beta, gamma; /* t-force parameters, defaults 0.1, 8, 2 (Table 1); gamma > 1
+                                 (> 0 with LAYOUT_FORCE_GAUSSIAN) */
     float eta0;               /* initial step; eta_t = eta0 * (1 - t / epochs); default 1 */
     int32_t update_mode;      /* LAYOUT_UPDATE_AUTO (default) / LAYOUT_HOGWILD_STORE /
                                  LAYOUT_ATOMIC / LAYOUT_JACOBI */
@@ -127,6 +134,12 @@ typedef struct layout_opts {
                                  0 = never (default: plain stores only); negative is
                                  LAYOUT_E_INVALID_ARG.  Ignored by the other engines and
                                  policies */
+    int32_t force_kernel;     /* LAYOUT_FORCE_T (default): Table 1's t-FDP forces;
+                                 LAYOUT_FORCE_GAUSSIAN: the same forces with the Gaussian
+                                 kernel exp(-|d|^2/2) in place of 1/(1+|d|^2) (the conclusion's
+                                 Gaussian-based forces): A(d) = alpha (1 + beta exp(-|d|^2/2))
+                                 d, R(d) = exp(-gamma |d|^2 / 2) d, gamma > 0.  The energy
+                                 monitors take the t-FDP forces only (E_UNSUPPORTED) */
 } layout_opts;
 
 /* Fills *opts with the defaults listed above. */

@@ -33,6 +33,8 @@ ORDER_SHUFFLED = 0
 ORDER_CSR = 1
 
 ALPHA, BETA, GAMMA, ETA0 = 0.1, 8.0, 2.0, 1.0
+FORCE_T = 0         # Table 1, t-FDP row (Student-t kernel 1/(1+q))
+FORCE_GAUSSIAN = 1  # the Gaussian kernel exp(-q/2) in place of 1/(1+q) (see snap_oracle.c)
 KEY_DOMAIN = 0x534E41502D744644  # second key word of every draw ("SNAP-tFD")
 
 _lib = None
@@ -101,6 +103,8 @@ def lib():
         L.oracle_pair_energies.argtypes = [ctypes.c_double] * 4 + [
             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.oracle_pair_energies.restype = None
+        L.oracle_set_force_kernel.argtypes = [ctypes.c_int32]
+        L.oracle_set_force_kernel.restype = None
         L.oracle_jacobi_epoch.argtypes = [
             _i32p, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
             ctypes.c_uint64, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -140,6 +144,13 @@ def _tables(n, thr, alias):
         alias = np.zeros(max(n, 1), dtype=np.uint32)
     return (np.ascontiguousarray(thr, dtype=np.uint32),
             np.ascontiguousarray(alias, dtype=np.uint32))
+
+
+def _kernel(kernel):
+    """Selects the force kernel for the next oracle call."""
+    if kernel not in (FORCE_T, FORCE_GAUSSIAN):
+        raise ValueError(f"unknown force kernel {kernel}")
+    lib().oracle_set_force_kernel(int(kernel))
 
 
 # -------------------------------------------------------------------- API
@@ -212,16 +223,18 @@ def draw_negatives(row_ptr, col, n, k, t, seed, mode=NEG_UNIFORM, thr=None, alia
     return out[: nnz * k].reshape(nnz, k)
 
 
-def force_magnitudes(dist, alpha=ALPHA, beta=BETA, gamma=GAMMA):
+def force_magnitudes(dist, alpha=ALPHA, beta=BETA, gamma=GAMMA, kernel=FORCE_T):
+    _kernel(kernel)
     fa, fr = ctypes.c_double(), ctypes.c_double()
     lib().oracle_force_magnitudes(alpha, beta, gamma, float(dist), ctypes.byref(fa),
                                   ctypes.byref(fr))
     return fa.value, fr.value
 
 
-def pair_energies(dist, alpha=ALPHA, beta=BETA, gamma=GAMMA):
+def pair_energies(dist, alpha=ALPHA, beta=BETA, gamma=GAMMA, kernel=FORCE_T):
     """(U_a, U_r) at distance dist: the pair energies whose negative gradients
     are the Table 1 forces (Eq. (2))."""
+    _kernel(kernel)
     ua, ur = ctypes.c_double(), ctypes.c_double()
     lib().oracle_pair_energies(alpha, beta, gamma, float(dist), ctypes.byref(ua),
                                ctypes.byref(ur))
@@ -230,9 +243,10 @@ def pair_energies(dist, alpha=ALPHA, beta=BETA, gamma=GAMMA):
 
 def serial_run(row_ptr, col, n, k, T, seed, Y0=None, t_begin=0, t_end=None,
                order=ORDER_SHUFFLED, mode=NEG_UNIFORM, thr=None, alias=None,
-               alpha=ALPHA, beta=BETA, gamma=GAMMA, eta0=ETA0, dim=None):
+               alpha=ALPHA, beta=BETA, gamma=GAMMA, kernel=FORCE_T, eta0=ETA0, dim=None):
     """Serial Algorithm 1 in FP64 over epochs [t_begin, t_end) of a T-epoch run;
     dim (2 or 3) defaults to the width of Y0, else 2."""
+    _kernel(kernel)
     rp, c = _csr(row_ptr, col)
     thr, alias = _tables(n, thr, alias)
     if t_end is None:
@@ -251,9 +265,10 @@ def serial_run(row_ptr, col, n, k, T, seed, Y0=None, t_begin=0, t_end=None,
 
 def serial_run_ordered(row_ptr, col, n, k, T, seed, edge_order, Y0=None, t_begin=0,
                        t_end=None, mode=NEG_UNIFORM, thr=None, alias=None, alpha=ALPHA,
-                       beta=BETA, gamma=GAMMA, eta0=ETA0):
+                       beta=BETA, gamma=GAMMA, kernel=FORCE_T, eta0=ETA0):
     """Serial Algorithm 1 (2D) visiting the directed edges in the given order
     (a permutation of [0, nnz)); draws stay keyed by CSR position."""
+    _kernel(kernel)
     rp, c = _csr(row_ptr, col)
     thr, alias = _tables(n, thr, alias)
     if t_end is None:
@@ -272,10 +287,11 @@ def serial_run_ordered(row_ptr, col, n, k, T, seed, edge_order, Y0=None, t_begin
 
 
 def jacobi_epoch(row_ptr, col, n, k, t, T, seed, Y, mode=NEG_UNIFORM, thr=None, alias=None,
-                 use_attr=True, use_rep=True, alpha=ALPHA, beta=BETA, gamma=GAMMA, eta0=ETA0,
+                 use_attr=True, use_rep=True, alpha=ALPHA, beta=BETA, gamma=GAMMA, kernel=FORCE_T, eta0=ETA0,
                  want_abs=False):
     """One synchronous epoch from Y (n x 2 or n x 3); returns Y_out (and the
     |contribution| sums)."""
+    _kernel(kernel)
     rp, c = _csr(row_ptr, col)
     thr, alias = _tables(n, thr, alias)
     dim = int(np.asarray(Y).reshape(n, -1).shape[1]) if n else 2
@@ -292,9 +308,10 @@ def jacobi_epoch(row_ptr, col, n, k, t, T, seed, Y, mode=NEG_UNIFORM, thr=None, 
 
 
 def sampled_energy(row_ptr, col, n, k, t, seed, Y, mode=NEG_UNIFORM, thr=None, alias=None,
-                   alpha=ALPHA, beta=BETA, gamma=GAMMA, parts=False):
+                   alpha=ALPHA, beta=BETA, gamma=GAMMA, kernel=FORCE_T, parts=False):
     """Energy seen by the samples of epoch t at fixed Y (Sec. 3.3); with
     parts=True the pair (attraction, repulsion)."""
+    _kernel(kernel)
     rp, c = _csr(row_ptr, col)
     thr, alias = _tables(n, thr, alias)
     Yin = np.ascontiguousarray(np.asarray(Y, dtype=np.float64).reshape(-1))
@@ -304,9 +321,10 @@ def sampled_energy(row_ptr, col, n, k, t, seed, Y, mode=NEG_UNIFORM, thr=None, a
     return (float(out[0]), float(out[1])) if parts else total
 
 
-def effective_energy(row_ptr, col, n, k, Y, alpha=ALPHA, beta=BETA, gamma=GAMMA, parts=False):
+def effective_energy(row_ptr, col, n, k, Y, alpha=ALPHA, beta=BETA, gamma=GAMMA, kernel=FORCE_T, parts=False):
     """Degree-weighted objective of Eq. (4) with the weight of Sec. 3.3; with
     parts=True the pair (attraction, weighted repulsion)."""
+    _kernel(kernel)
     rp, c = _csr(row_ptr, col)
     Yin = np.ascontiguousarray(np.asarray(Y, dtype=np.float64).reshape(-1))
     out = np.zeros(2, dtype=np.float64)
@@ -315,9 +333,10 @@ def effective_energy(row_ptr, col, n, k, Y, alpha=ALPHA, beta=BETA, gamma=GAMMA,
 
 
 def threaded_run(row_ptr, col, n, k, T, seed, nthreads, Y0=None, t_begin=0, t_end=None,
-                 mode=NEG_UNIFORM, thr=None, alias=None, alpha=ALPHA, beta=BETA, gamma=GAMMA,
+                 mode=NEG_UNIFORM, thr=None, alias=None, alpha=ALPHA, beta=BETA, gamma=GAMMA, kernel=FORCE_T,
                  eta0=ETA0):
     """The paper's lock-free bundle scheme on host threads (FP64)."""
+    _kernel(kernel)
     rp, c = _csr(row_ptr, col)
     thr, alias = _tables(n, thr, alias)
     if t_end is None:

@@ -304,19 +304,36 @@ int oracle_draw_edges(int32_t n, int32_t k, int64_t t, uint64_t seed, int32_t mo
 }
 
 /* ------------------------------------------------------------------ forces */
+/* Kernel of the forces.  FORCE_T is Table 1's t-FDP row, built on the
+ * Student-t kernel 1/(1+q).  FORCE_GAUSSIAN is the Gaussian-based variant the
+ * conclusion names as future work without defining it; the reading taken
+ * keeps the t-FDP structure and puts the Gaussian kernel exp(-q/2) in place of
+ * 1/(1+q) in both forces:
+ *   A(d) = alpha * (1 + beta * exp(-q/2)) * d,   R(d) = exp(-gamma*q/2) * d. */
+enum { FORCE_T = 0, FORCE_GAUSSIAN = 1 };
+
+/* The kernel used by every following call (set by the Python wrapper before
+ * each call). */
+static int32_t g_force_kernel = FORCE_T;
+
+void oracle_set_force_kernel(int32_t kernel) { g_force_kernel = kernel; }
+
 typedef struct {
     double alpha, beta, gamma, eta0;
+    int32_t kernel;
 } force_params;
 
 /* attraction coefficient: A(d) = coef * d (Table 1, t-FDP attractive force) */
 static double attr_coef(const force_params *fp, double q)
 {
+    if (fp->kernel == FORCE_GAUSSIAN) return fp->alpha * (1.0 + fp->beta * exp(-0.5 * q));
     return fp->alpha * (1.0 + fp->beta / (1.0 + q));
 }
 
 /* repulsion coefficient: R(d) = coef * d (Table 1, t-FDP repulsive force) */
 static double rep_coef(const force_params *fp, double q)
 {
+    if (fp->kernel == FORCE_GAUSSIAN) return exp(-0.5 * fp->gamma * q);
     return pow(1.0 + q, -fp->gamma);
 }
 
@@ -324,7 +341,7 @@ static double rep_coef(const force_params *fp, double q)
 void oracle_force_magnitudes(double alpha, double beta, double gamma, double dist, double *fa,
                              double *fr)
 {
-    force_params fp = {alpha, beta, gamma, 1.0};
+    force_params fp = {alpha, beta, gamma, 1.0, g_force_kernel};
     double q = dist * dist;
     *fa = attr_coef(&fp, q) * dist;
     *fr = rep_coef(&fp, q) * dist;
@@ -426,7 +443,7 @@ int oracle_serial_run(const int32_t *row_ptr, const int32_t *col, int32_t n, int
                       const uint32_t *thr, const uint32_t *alias, int32_t dim, double *Y)
 {
     int64_t nnz = row_ptr[n];
-    force_params fp = {alpha, beta, gamma, eta0};
+    force_params fp = {alpha, beta, gamma, eta0, g_force_kernel};
     sampler sp = {n, mode, thr, alias};
     int64_t *perm = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nnz > 0 ? nnz : 1));
     if (order == ORDER_SHUFFLED) {
@@ -470,7 +487,7 @@ int oracle_serial_run_ordered(const int32_t *row_ptr, const int32_t *col, int32_
         seen[e] = 1;
     }
     free(seen);
-    force_params fp = {alpha, beta, gamma, eta0};
+    force_params fp = {alpha, beta, gamma, eta0, g_force_kernel};
     sampler sp = {n, mode, thr, alias};
     serial_epochs(row_ptr, col, n, k, t_begin, t_end, T, seed, &fp, &sp, dim, edge_order, Y);
     return 0;
@@ -504,7 +521,7 @@ int oracle_jacobi_epoch(const int32_t *row_ptr, const int32_t *col, int32_t n, i
                         const uint32_t *alias, int32_t use_attr, int32_t use_rep, int32_t dim,
                         const double *Y, double *Y_out, double *abs_out)
 {
-    force_params fp = {alpha, beta, gamma, eta0};
+    force_params fp = {alpha, beta, gamma, eta0, g_force_kernel};
     sampler sp = {n, mode, thr, alias};
     double eta = eta_at(&fp, t, T);
     double *D = (double *)calloc((size_t)n * (size_t)dim + 3, sizeof(double));
@@ -546,17 +563,21 @@ int oracle_jacobi_epoch(const int32_t *row_ptr, const int32_t *col, int32_t n, i
 }
 
 /* ----------------------------------------------------------------- energies */
-/* Pair energies whose negative gradients are the Table 1 t-forces
- * (Eq. (2): F = -grad U):
- *   U_a(q) = alpha * (q/2 + (beta/2) ln(1+q))
- *   U_r(q) = (1+q)^(1-gamma) / (2(gamma-1))          (gamma != 1)   */
+/* Pair energies whose negative gradients are the forces (Eq. (2):
+ * F = -grad U), as functions of q = |d|^2 (grad q = 2d):
+ *   t-FDP:    U_a(q) = alpha * (q/2 + (beta/2) ln(1+q))
+ *             U_r(q) = (1+q)^(1-gamma) / (2(gamma-1))      (gamma != 1)
+ *   Gaussian: U_a(q) = alpha * (q/2 + beta (1 - exp(-q/2)))
+ *             U_r(q) = exp(-gamma q/2) / gamma                           */
 static double energy_attr(const force_params *fp, double q)
 {
+    if (fp->kernel == FORCE_GAUSSIAN) return fp->alpha * (0.5 * q + fp->beta * -expm1(-0.5 * q));
     return fp->alpha * (0.5 * q + 0.5 * fp->beta * log1p(q));
 }
 
 static double energy_rep(const force_params *fp, double q)
 {
+    if (fp->kernel == FORCE_GAUSSIAN) return exp(-0.5 * fp->gamma * q) / fp->gamma;
     return pow(1.0 + q, 1.0 - fp->gamma) / (2.0 * (fp->gamma - 1.0));
 }
 
@@ -564,7 +585,7 @@ static double energy_rep(const force_params *fp, double q)
 void oracle_pair_energies(double alpha, double beta, double gamma, double dist, double *ua,
                           double *ur)
 {
-    force_params fp = {alpha, beta, gamma, 1.0};
+    force_params fp = {alpha, beta, gamma, 1.0, g_force_kernel};
     double q = dist * dist;
     *ua = energy_attr(&fp, q);
     *ur = energy_rep(&fp, q);
@@ -579,7 +600,7 @@ double oracle_sampled_energy(const int32_t *row_ptr, const int32_t *col, int32_t
                              int32_t mode, const uint32_t *thr, const uint32_t *alias,
                              const double *Y, double *parts)
 {
-    force_params fp = {alpha, beta, gamma, 1.0};
+    force_params fp = {alpha, beta, gamma, 1.0, g_force_kernel};
     sampler sp = {n, mode, thr, alias};
     int32_t *neg = (int32_t *)malloc(sizeof(int32_t) * (size_t)(k > 0 ? k : 1));
     double ea = 0.0, er = 0.0;
@@ -613,7 +634,7 @@ double oracle_effective_energy(const int32_t *row_ptr, const int32_t *col, int32
                                double alpha, double beta, double gamma, const double *Y,
                                double *parts)
 {
-    force_params fp = {alpha, beta, gamma, 1.0};
+    force_params fp = {alpha, beta, gamma, 1.0, g_force_kernel};
     double ea = 0.0, er = 0.0;
     for (int32_t i = 0; i < n; ++i)
         for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
@@ -745,7 +766,7 @@ int oracle_threaded_run(const int32_t *row_ptr, const int32_t *col, int32_t n, i
     job.t_end = t_end;
     job.T = T;
     job.seed = seed;
-    job.fp = (force_params){alpha, beta, gamma, eta0};
+    job.fp = (force_params){alpha, beta, gamma, eta0, g_force_kernel};
     job.sp = (sampler){n, mode, thr, alias};
     job.order = order;
     job.Y = Y;

@@ -344,7 +344,11 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
   if (o.bundle_edges < 0 || o.block_threads < 0 || o.grid_blocks < 0 || o.hub_split_edges < 0 ||
       o.nodes_per_lane < 0 || o.block_threads > 1024 || (o.block_threads % 64) != 0)
     return fail(LAYOUT_E_INVALID_ARG, "bad launch option");
-  if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g (must be > 1)", o.gamma);
+  if (o.force_kernel != LAYOUT_FORCE_T && o.force_kernel != LAYOUT_FORCE_GAUSSIAN)
+    return fail(LAYOUT_E_INVALID_ARG, "force_kernel = %d", o.force_kernel);
+  if (!(o.gamma > (o.force_kernel == LAYOUT_FORCE_T ? 1.0f : 0.0f)))
+    return fail(LAYOUT_E_INVALID_ARG, "gamma = %g (must be > 1, > 0 for Gaussian forces)",
+                o.gamma);
   if (o.init_mode != LAYOUT_INIT_UNIFORM && o.init_mode != LAYOUT_INIT_PMDS)
     return fail(LAYOUT_E_INVALID_ARG, "init_mode = %d", o.init_mode);
   if (o.pmds_pivots < 0 || o.pmds_pivots > 64)
@@ -527,6 +531,7 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
     d.alpha = o.alpha;
     d.beta = o.beta;
     d.gamma = o.gamma;
+    d.force = o.force_kernel;
     d.sc = sampler_consts(gr.n);
     d.lanes = B->in_lds[g] ? B->lds_block[g] : 0;
     if (B->in_lds[g] && B->nnz[g] > 0) {

@@ -12,6 +12,9 @@ namespace snap {
 // Update policies (Sec. 3.4 lock-free scheme; see kernels.hpp).
 enum : int { kStore = 0, kAtomic = 1, kJacobi = 2 };
 
+// Kernels of the forces (the values of layout_opts.force_kernel).
+enum : int { kForceT = 0, kForceGaussian = 1 };
+
 struct GraphDesc {
   const int64_t* row_ptr;
   const int32_t* col;
@@ -36,7 +39,7 @@ struct GraphDesc {
   int32_t t0;      // epoch index at launch offset 0
   int32_t T;       // epochs in the step-size schedule
   int32_t lanes;   // LDS engine: lanes of the workgroup that work (0 = all)
-  int32_t pad0;
+  int32_t force;   // kernel of the forces: kForceT (Table 1, t-FDP) or kForceGaussian
   uint64_t seed;
   float eta0, alpha, beta, gamma;
   SamplerConsts sc;

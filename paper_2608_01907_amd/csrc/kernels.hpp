@@ -247,13 +247,23 @@ template <> __device__ __forceinline__ float4 vzero<float4>() { return make_floa
 // ------------------------------------------------------------------- forces
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// attraction coefficient: A(d) = coef * d
-__device__ __forceinline__ float attr_coef(float q, float alpha, float beta) {
-  return alpha * (1.0f + beta * fast_rcp(1.0f + q));
+// The kernel of the forces at q = |d|^2: Table 1's t-FDP forces use the
+// Student-t kernel 1/(1+q); the Gaussian variant puts exp(-q/2) in its place
+// (the conclusion names Gaussian-based forces as future work; this reading
+// keeps the t-FDP structure).  `force` is uniform over a launch.
+constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
+
+template <int FORCE>
+__device__ __forceinline__ float force_kernel(float q) {
+  if constexpr (FORCE == kForceGaussian) return __builtin_amdgcn_exp2f(-kHalfLog2e * q);
+  return fast_rcp(1.0f + q);
 }
 
-// repulsion coefficient: R(d) = coef * d = d / (1+q)^gamma
+// repulsion coefficient: R(d) = coef * d = kernel(q)^gamma d
+// (t-FDP: d / (1+q)^gamma; Gaussian: d exp(-gamma q / 2))
+template <int FORCE>
 __device__ __forceinline__ float rep_coef(float q, float gamma) {
+  if constexpr (FORCE == kForceGaussian) return __builtin_amdgcn_exp2f(-kHalfLog2e * gamma * q);
   const float r = fast_rcp(1.0f + q);
   if (gamma == 2.0f) return r * r;
   return __builtin_amdgcn_exp2f(gamma * __builtin_amdgcn_logf(r));
@@ -264,20 +274,40 @@ __device__ __forceinline__ float eta_of(const GraphDesc& g, int32_t t) {
 }
 
 // --------------------------------------------------------------- one chunk
+// What the draws of one graph read, copied out of its descriptor once per
+// chunk (fields read through a reference into the table would be re-read
+// after every store).
+struct Sampler {
+  uint64_t seed;
+  SamplerConsts sc;
+  const uint32_t* thr;
+  const uint32_t* alias;
+};
+
+__device__ __forceinline__ Sampler sampler_of(const GraphDesc& g) {
+  return Sampler{g.seed, g.sc, g.thr, g.alias};
+}
+
 template <int K, bool DEGREE>
-__device__ __forceinline__ void draw_k(const GraphDesc& g, int64_t e, uint32_t t, uint32_t i,
+__device__ __forceinline__ void draw_k(const Sampler& sp, int64_t e, uint32_t t, uint32_t i,
                                        uint32_t (&s)[K > 0 ? K : 1]) {
   if constexpr (K > 0) {
     WordStream ws;
-    ws.open(g.seed, static_cast<uint64_t>(e), t, kTagNeg);
+    ws.open(sp.seed, static_cast<uint64_t>(e), t, kTagNeg);
 #pragma unroll
     for (int m = 0; m < K; ++m) {
       if constexpr (DEGREE)
-        s[m] = draw_alias(ws, g.sc, i, g.thr, g.alias);
+        s[m] = draw_alias(ws, sp.sc, i, sp.thr, sp.alias);
       else
-        s[m] = draw_uniform(ws, g.sc, i);
+        s[m] = draw_uniform(ws, sp.sc, i);
     }
   }
+}
+
+template <int K, bool DEGREE>
+__device__ __forceinline__ void draw_k(const GraphDesc& g, int64_t e, uint32_t t, uint32_t i,
+                                       uint32_t (&s)[K > 0 ? K : 1]) {
+  draw_k<K, DEGREE>(sampler_of(g), e, t, i, s);
 }
 
 // Commit of the source at the end of its run inside a chunk.  A whole row
@@ -318,21 +348,29 @@ __device__ __forceinline__ int32_t row_segments(int64_t row_begin, int64_t row_e
 }
 
 // mem: the memory operations (load, store, add on positions); the stateless
-// kinds are passed as empty objects.
-template <int K, int MODE, bool DEGREE, class Mem, class P>
-__device__ __forceinline__ void process_chunk(const Mem& mem, const GraphDesc& g,
-                                              P* __restrict__ Y, P* __restrict__ D, int64_t lc,
-                                              int32_t t, float eta) {
+// kinds are passed as empty objects.  FORCE: the kernel of the forces.
+template <int K, int MODE, bool DEGREE, int FORCE, class Mem, class P>
+__device__ __forceinline__ void process_chunk_with(const Mem& mem, const GraphDesc& g,
+                                                   P* __restrict__ Y, P* __restrict__ D,
+                                                   int64_t lc, int32_t t, float eta) {
   constexpr int KS = K > 0 ? K : 1;
+  // the descriptor fields the loop reads, read once (a reference into the
+  // table is re-read after every store otherwise)
+  const int64_t* __restrict__ row_ptr = g.row_ptr;
+  const int32_t* __restrict__ col = g.col;
+  const uint32_t* __restrict__ hot = g.hot;
+  const int32_t hub = g.hub;
+  const Sampler sp = sampler_of(g);
+  const float beta = g.beta, gamma = g.gamma;
+  const float ca = eta * g.alpha;
   const int64_t e0 = *gptr(g.chunk_begin + lc);
   const int64_t e_end = *gptr(g.chunk_begin + lc + 1);
   int32_t i = *gptr(g.chunk_src + lc);
-  int64_t row_end = *gptr(g.row_ptr + i + 1);
-  int32_t segs = row_segments(*gptr(g.row_ptr + i), row_end, g.hub);
+  int64_t row_end = *gptr(row_ptr + i + 1);
+  int32_t segs = row_segments(*gptr(row_ptr + i), row_end, hub);
   P yi = mem.load(Y + i);
   P yi_start = yi;       // value at the start of the run
   P acc = vzero<P>();    // JACOBI: source contributions
-  const float ca = eta * g.alpha;
 
   for (int64_t e = e0; e < e_end; ++e) {
     if (e >= row_end) {
@@ -342,9 +380,9 @@ __device__ __forceinline__ void process_chunk(const Mem& mem, const GraphDesc& g
       do {
         ++i;
         row_begin = row_end;
-        row_end = *gptr(g.row_ptr + i + 1);
+        row_end = *gptr(row_ptr + i + 1);
       } while (e >= row_end);
-      segs = row_segments(row_begin, row_end, g.hub);
+      segs = row_segments(row_begin, row_end, hub);
       yi = mem.load(Y + i);
       yi_start = yi;
       acc = vzero<P>();
@@ -352,9 +390,9 @@ __device__ __forceinline__ void process_chunk(const Mem& mem, const GraphDesc& g
     // the generator work sits between the col load and the gathers, so that
     // it hides the col load's latency (and that of the previous edge's
     // stores, which the same memory counter tracks)
-    const int32_t j = __builtin_nontemporal_load(gptr(g.col + e));
+    const int32_t j = __builtin_nontemporal_load(gptr(col + e));
     uint32_t s[KS];
-    draw_k<K, DEGREE>(g, e, static_cast<uint32_t>(t), static_cast<uint32_t>(i), s);
+    draw_k<K, DEGREE>(sp, e, static_cast<uint32_t>(t), static_cast<uint32_t>(i), s);
 
     // issue every gather of the edge before any arithmetic
     P yj = mem.load(Y + j);
@@ -363,19 +401,19 @@ __device__ __forceinline__ void process_chunk(const Mem& mem, const GraphDesc& g
     for (int m = 0; m < K; ++m) ys[m] = mem.load(Y + s[m]);
     uint32_t hot_word = 0;  // bit j & 31: j is a hot node (STORE only)
     if constexpr (MODE == kStore)
-      if (g.hot) hot_word = *gptr(g.hot + (j >> 5));
+      if (hot) hot_word = *gptr(hot + (j >> 5));
 
     if constexpr (MODE == kJacobi) {
       {
         const P d = vsub(yi, yj);
-        const float c = ca * (1.0f + g.beta * fast_rcp(1.0f + vnorm2(d)));
+        const float c = ca * (1.0f + beta * force_kernel<FORCE>(vnorm2(d)));
         acc = vaxpy(acc, -c, d);
         mem.add(D + j, vscale(c, d));
       }
 #pragma unroll
       for (int m = 0; m < K; ++m) {
         const P d = vsub(yi, ys[m]);
-        const float h = eta * rep_coef(vnorm2(d), g.gamma);
+        const float h = eta * rep_coef<FORCE>(vnorm2(d), gamma);
         acc = vaxpy(acc, h, d);
         mem.add(D + s[m], vscale(-h, d));
       }
@@ -388,7 +426,7 @@ __device__ __forceinline__ void process_chunk(const Mem& mem, const GraphDesc& g
       for (int m = 0; m < K; ++m) ys_old[m] = ys[m];
       {
         const P d = vsub(yi, yj);
-        const float c = ca * (1.0f + g.beta * fast_rcp(1.0f + vnorm2(d)));
+        const float c = ca * (1.0f + beta * force_kernel<FORCE>(vnorm2(d)));
         yi = vaxpy(yi, -c, d);
         yj = vaxpy(yj, c, d);
       }
@@ -410,7 +448,7 @@ __device__ __forceinline__ void process_chunk(const Mem& mem, const GraphDesc& g
         }
         dup[m] = dm;
         const P d = vsub(yi, cur);
-        const float h = eta * rep_coef(vnorm2(d), g.gamma);
+        const float h = eta * rep_coef<FORCE>(vnorm2(d), gamma);
         yi = vaxpy(yi, h, d);
         cur = vaxpy(cur, -h, d);
         ys[m] = cur;
@@ -438,6 +476,18 @@ __device__ __forceinline__ void process_chunk(const Mem& mem, const GraphDesc& g
   }
   // commit the last source of the chunk
   commit_source<MODE>(mem, Y, D, i, yi, yi_start, acc, segs);
+}
+
+// One chunk with the graph's force kernel (one uniform branch per chunk; the
+// pair loop is specialised for each kernel).
+template <int K, int MODE, bool DEGREE, class Mem, class P>
+__device__ __forceinline__ void process_chunk(const Mem& mem, const GraphDesc& g,
+                                              P* __restrict__ Y, P* __restrict__ D, int64_t lc,
+                                              int32_t t, float eta) {
+  if (g.force == kForceGaussian)
+    process_chunk_with<K, MODE, DEGREE, kForceGaussian>(mem, g, Y, D, lc, t, eta);
+  else
+    process_chunk_with<K, MODE, DEGREE, kForceT>(mem, g, Y, D, lc, t, eta);
 }
 
 // The graph's positions (and Jacobi accumulator) as 2D or 3D positions.

@@ -234,6 +234,7 @@ int setup_job(layout_server_t* S, Job& j) {
   d.alpha = S->opts.alpha;
   d.beta = S->opts.beta;
   d.gamma = S->opts.gamma;
+  d.force = S->opts.force_kernel;
   d.sc = sampler_consts(j.n);
   d.lanes = j.lds ? j.lanes : 0;
   e = hipStreamSynchronize(S->stream);
@@ -623,7 +624,10 @@ int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t ro
       o.neg_weights != LAYOUT_NEG_CUSTOM)
     return fail(LAYOUT_E_INVALID_ARG, "neg_weights = %d", o.neg_weights);
   if (o.engine < 0 || o.engine > 3) return fail(LAYOUT_E_INVALID_ARG, "engine = %d", o.engine);
-  if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g", o.gamma);
+  if (o.force_kernel != LAYOUT_FORCE_T && o.force_kernel != LAYOUT_FORCE_GAUSSIAN)
+    return fail(LAYOUT_E_INVALID_ARG, "force_kernel = %d", o.force_kernel);
+  if (!(o.gamma > (o.force_kernel == LAYOUT_FORCE_T ? 1.0f : 0.0f)))
+    return fail(LAYOUT_E_INVALID_ARG, "gamma = %g", o.gamma);
   if (o.init_mode != LAYOUT_INIT_UNIFORM && o.init_mode != LAYOUT_INIT_PMDS)
     return fail(LAYOUT_E_INVALID_ARG, "init_mode = %d", o.init_mode);
   if (o.pmds_pivots < 0 || o.pmds_pivots > 64)

@@ -861,7 +861,11 @@ int create_impl(const int32_t* row32, const int64_t* row64, const int32_t* col_i
   if (o.block_threads > 1024 || (o.block_threads % 64) != 0)
     return fail(LAYOUT_E_INVALID_ARG, "block_threads = %d (multiple of 64, <= 1024)",
                 o.block_threads);
-  if (!(o.gamma > 1.0f)) return fail(LAYOUT_E_INVALID_ARG, "gamma = %g (must be > 1)", o.gamma);
+  if (o.force_kernel != LAYOUT_FORCE_T && o.force_kernel != LAYOUT_FORCE_GAUSSIAN)
+    return fail(LAYOUT_E_INVALID_ARG, "force_kernel = %d", o.force_kernel);
+  if (!(o.gamma > (o.force_kernel == LAYOUT_FORCE_T ? 1.0f : 0.0f)))
+    return fail(LAYOUT_E_INVALID_ARG, "gamma = %g (must be > 1, > 0 for Gaussian forces)",
+                o.gamma);
   // degree-weighted negatives: the alias table's bin capacity W = nnz must stay
   // below 2^32 (checked here for host inputs, before any device work; device
   // inputs are checked when the table is built)
@@ -1097,6 +1101,7 @@ int create_impl(const int32_t* row32, const int64_t* row64, const int32_t* col_i
   g.alpha = o.alpha;
   g.beta = o.beta;
   g.gamma = o.gamma;
+  g.force = o.force_kernel;
   g.sc = sampler_consts(n);
   const int32_t zero = 0;
   e = hipMemcpyAsync(L->d_table, &g, sizeof g, hipMemcpyHostToDevice, L->stream);
@@ -1246,6 +1251,8 @@ void layout_destroy(layout_t* L) {
 int layout_sampled_energy(layout_t* L, int32_t epoch, double* attr_out, double* rep_out) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (L->dim != 2) return fail(LAYOUT_E_UNSUPPORTED, "energy monitors are 2D");
+  if (L->opts.force_kernel != LAYOUT_FORCE_T)
+    return fail(LAYOUT_E_UNSUPPORTED, "energy monitors take the t-FDP forces");
   if (!attr_out || !rep_out) return fail(LAYOUT_E_INVALID_ARG, "NULL output");
   if (epoch < 0) return fail(LAYOUT_E_INVALID_ARG, "epoch = %d", epoch);
   int rc = energy_buffer(L);
@@ -1265,6 +1272,8 @@ int layout_sampled_energy(layout_t* L, int32_t epoch, double* attr_out, double* 
 int layout_effective_energy(layout_t* L, double* attr_out, double* rep_out) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (L->dim != 2) return fail(LAYOUT_E_UNSUPPORTED, "energy monitors are 2D");
+  if (L->opts.force_kernel != LAYOUT_FORCE_T)
+    return fail(LAYOUT_E_UNSUPPORTED, "energy monitors take the t-FDP forces");
   if (!attr_out || !rep_out) return fail(LAYOUT_E_INVALID_ARG, "NULL output");
   int rc = energy_buffer(L);
   if (rc != LAYOUT_OK) return rc;

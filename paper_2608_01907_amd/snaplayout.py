@@ -28,6 +28,8 @@ LAYOUT_JACOBI = 2
 LAYOUT_UPDATE_AUTO = 3
 LAYOUT_INIT_UNIFORM = 0
 LAYOUT_INIT_PMDS = 1
+LAYOUT_FORCE_T = 0
+LAYOUT_FORCE_GAUSSIAN = 1
 LAYOUT_NEG_UNIFORM = 0
 LAYOUT_NEG_DEGREE = 1
 LAYOUT_NEG_CUSTOM = 2
@@ -65,6 +67,7 @@ class layout_opts(ctypes.Structure):
         ("init_mode", ctypes.c_int32), ("pmds_pivots", ctypes.c_int32),
         ("init_pos", ctypes.c_void_p), ("stream", ctypes.c_void_p),
         ("neg_weight_values", ctypes.c_void_p), ("hot_degree", ctypes.c_int32),
+        ("force_kernel", ctypes.c_int32),
     ]
 
 
@@ -661,9 +664,11 @@ class Layout:
                  alpha=0.1, beta=8.0, gamma=2.0, init_pos=None, bundle_edges=0,
                  block_threads=0, grid_blocks=0, start_epoch=0, stream=None,
                  hub_split_edges=0, nodes_per_lane=0, init_mode=LAYOUT_INIT_UNIFORM,
-                 pmds_pivots=0, neg_weight_values=None, dim=2, hot_degree=0):
+                 pmds_pivots=0, neg_weight_values=None, dim=2, hot_degree=0,
+                 force_kernel=LAYOUT_FORCE_T):
         o = layout_opts_init()
         o.hot_degree = hot_degree
+        o.force_kernel = force_kernel
         o.init_mode, o.pmds_pivots = init_mode, pmds_pivots
         w_keep = None
         if neg_weight_values is not None:
@@ -758,9 +763,11 @@ class BatchLayout:
     def __init__(self, graphs, k=5, epochs=50, *, update_mode=LAYOUT_UPDATE_AUTO,
                  engine=LAYOUT_ENGINE_AUTO, eta0=1.0, bundle_edges=0, hub_split_edges=0,
                  block_threads=0, grid_blocks=0, neg_weights=LAYOUT_NEG_UNIFORM,
-                 nodes_per_lane=0, init_mode=LAYOUT_INIT_UNIFORM, pmds_pivots=0):
+                 nodes_per_lane=0, init_mode=LAYOUT_INIT_UNIFORM, pmds_pivots=0,
+                 force_kernel=LAYOUT_FORCE_T, gamma=2.0):
         o = layout_opts_init()
         o.update_mode, o.engine, o.eta0 = update_mode, engine, eta0
+        o.force_kernel, o.gamma = force_kernel, gamma
         o.init_mode, o.pmds_pivots = init_mode, pmds_pivots
         o.bundle_edges, o.hub_split_edges = bundle_edges, hub_split_edges
         o.block_threads, o.grid_blocks, o.neg_weights = block_threads, grid_blocks, neg_weights

@@ -657,18 +657,23 @@ def test_two_node_trajectory_general_gamma(gamma):
 
 
 # ------------------------------------------- energies and forces (Eq. (2))
+@pytest.mark.parametrize("kernel", [O.FORCE_T, O.FORCE_GAUSSIAN])
 @pytest.mark.parametrize("gamma", [1.5, 2.0, 3.0])
 @pytest.mark.parametrize("d", [0.05, 0.4, 1.0, 1.7, 6.0])
-def test_pair_energies_are_force_potentials(gamma, d):
+def test_pair_energies_are_force_potentials(gamma, d, kernel):
     """F = -grad U (Eq. (2)): the distance derivative of U_a is the attraction
-    magnitude and minus that of U_r the repulsion magnitude of Table 1, by
-    central differences."""
+    magnitude and minus that of U_r the repulsion magnitude of Table 1 (and of
+    its Gaussian-kernel variant), by central differences."""
     h = 1e-5 * max(d, 1.0)
-    ua_p, ur_p = O.pair_energies(d + h, gamma=gamma)
-    ua_m, ur_m = O.pair_energies(d - h, gamma=gamma)
-    fa, fr = O.force_magnitudes(d, gamma=gamma)
+    ua_p, ur_p = O.pair_energies(d + h, gamma=gamma, kernel=kernel)
+    ua_m, ur_m = O.pair_energies(d - h, gamma=gamma, kernel=kernel)
+    fa, fr = O.force_magnitudes(d, gamma=gamma, kernel=kernel)
+    if fr < 1e-12:
+        assert abs((ur_p - ur_m) / (2 * h)) < 1e-12
+        fr = None
     assert (ua_p - ua_m) / (2 * h) == pytest.approx(fa, rel=1e-8)
-    assert -(ur_p - ur_m) / (2 * h) == pytest.approx(fr, rel=1e-8)
+    if fr is not None:
+        assert -(ur_p - ur_m) / (2 * h) == pytest.approx(fr, rel=1e-8)
 
 
 def test_pair_energies_values():
@@ -682,8 +687,9 @@ def test_pair_energies_values():
     assert ua0 == 0.0 and ur0 == pytest.approx(1.0, rel=1e-14)
 
 
+@pytest.mark.parametrize("kernel", [O.FORCE_T, O.FORCE_GAUSSIAN])
 @pytest.mark.parametrize("gamma", [1.5, 2.0, 3.0])
-def test_jacobi_step_is_gradient_step_on_sampled_energy(gamma):
+def test_jacobi_step_is_gradient_step_on_sampled_energy(gamma, kernel):
     """With the draws of epoch t fixed, the synchronous epoch moves every node by
     -eta times the gradient of that epoch's sampled energy (Eq. (2) summed over
     the sampled pairs): the energies and the forces of the oracle, written
@@ -691,7 +697,7 @@ def test_jacobi_step_is_gradient_step_on_sampled_energy(gamma):
     g = S.small_sbm(24, 2, 5.0, 11)
     k, t, T, seed = 3, 2, 8, 19
     Y = O.init_positions(g.n, 6) * 0.35
-    Yj = O.jacobi_epoch(g.row_ptr, g.col, g.n, k, t, T, seed, Y, gamma=gamma)
+    Yj = O.jacobi_epoch(g.row_ptr, g.col, g.n, k, t, T, seed, Y, gamma=gamma, kernel=kernel)
     eta = 1.0 - t / T
     grad = np.zeros_like(Y)
     h = 1e-6
@@ -701,8 +707,10 @@ def test_jacobi_step_is_gradient_step_on_sampled_energy(gamma):
             Ym = Y.copy()
             Yp[i, c] += h
             Ym[i, c] -= h
-            ep = O.sampled_energy(g.row_ptr, g.col, g.n, k, t, seed, Yp, gamma=gamma)
-            em = O.sampled_energy(g.row_ptr, g.col, g.n, k, t, seed, Ym, gamma=gamma)
+            ep = O.sampled_energy(g.row_ptr, g.col, g.n, k, t, seed, Yp, gamma=gamma,
+                                  kernel=kernel)
+            em = O.sampled_energy(g.row_ptr, g.col, g.n, k, t, seed, Ym, gamma=gamma,
+                                  kernel=kernel)
             grad[i, c] = (ep - em) / (2 * h)
     move = Yj - Y
     scale = np.abs(move).max()
@@ -710,8 +718,9 @@ def test_jacobi_step_is_gradient_step_on_sampled_energy(gamma):
     assert np.abs(move + eta * grad).max() <= 1e-6 * scale
 
 
+@pytest.mark.parametrize("kernel", [O.FORCE_T, O.FORCE_GAUSSIAN])
 @pytest.mark.parametrize("gamma", [1.5, 2.0, 3.0])
-def test_effective_energy_gradient_is_expected_force(gamma):
+def test_effective_energy_gradient_is_expected_force(gamma, kernel):
     """-grad U_eff equals the expected synchronous force: attraction
     -2 sum_{j in N(i)} A(y_i - y_j) and weighted repulsion
     (k/(n-1)) sum_j (d_i + d_j) R(y_i - y_j) (Sec. 3.3, Eq. (4)), the weight
@@ -729,8 +738,10 @@ def test_effective_energy_gradient_is_expected_force(gamma):
             Ym = Y.copy()
             Yp[i, c] += h
             Ym[i, c] -= h
-            grad[i, c] = (O.effective_energy(g.row_ptr, g.col, n, k, Yp, gamma=gamma)
-                          - O.effective_energy(g.row_ptr, g.col, n, k, Ym, gamma=gamma)) / (2 * h)
+            grad[i, c] = (O.effective_energy(g.row_ptr, g.col, n, k, Yp, gamma=gamma,
+                                             kernel=kernel)
+                          - O.effective_energy(g.row_ptr, g.col, n, k, Ym, gamma=gamma,
+                                               kernel=kernel)) / (2 * h)
     # expected force from the closed-form magnitudes, pair by pair
     force = np.zeros_like(Y)
     for i in range(n):
@@ -738,13 +749,67 @@ def test_effective_energy_gradient_is_expected_force(gamma):
             j = g.col[e]
             d = Y[i] - Y[j]
             dist = float(np.linalg.norm(d))
-            fa, _ = O.force_magnitudes(dist, gamma=gamma)
+            fa, _ = O.force_magnitudes(dist, gamma=gamma, kernel=kernel)
             force[i] -= 2 * fa * d / dist
         for j in range(n):
             if j == i:
                 continue
             d = Y[i] - Y[j]
             dist = float(np.linalg.norm(d))
-            _, fr = O.force_magnitudes(dist, gamma=gamma)
+            _, fr = O.force_magnitudes(dist, gamma=gamma, kernel=kernel)
             force[i] += k / (n - 1) * (deg[i] + deg[j]) * fr * d / dist
     assert np.abs(force + grad).max() <= 1e-6 * np.abs(force).max()
+
+
+# ------------------------------------------- Gaussian-kernel forces (variant)
+@pytest.mark.parametrize("gamma,d,fa,fr", [
+    (2.0, 0.0, 0.0, 0.0),
+    (2.0, 1.0, 0.1 * (1 + 8 * math.exp(-0.5)), math.exp(-1.0)),
+    (2.0, 2.0, 0.1 * (2 + 16 * math.exp(-2.0)), 2 * math.exp(-4.0)),
+    (1.0, 3.0, 0.1 * (3 + 24 * math.exp(-4.5)), 3 * math.exp(-4.5)),
+    (3.0, 0.5, 0.1 * (0.5 + 4 * math.exp(-0.125)), 0.5 * math.exp(-0.375)),
+])
+def test_gaussian_force_closed_form(gamma, d, fa, fr):
+    """The Gaussian variant: |A| = alpha (d + beta d exp(-d^2/2)),
+    |R| = d exp(-gamma d^2 / 2), hand-evaluated."""
+    a, r = O.force_magnitudes(d, gamma=gamma, kernel=O.FORCE_GAUSSIAN)
+    assert a == pytest.approx(fa, rel=1e-13, abs=1e-15)
+    assert r == pytest.approx(fr, rel=1e-13, abs=1e-15)
+
+
+@pytest.mark.parametrize("gamma", [1.0, 2.0, 3.0])
+def test_gaussian_repulsion_peak(gamma):
+    """d exp(-gamma d^2/2) peaks at d = 1/sqrt(gamma) with value exp(-1/2)/sqrt(gamma)."""
+    d0 = 1.0 / math.sqrt(gamma)
+    r0 = O.force_magnitudes(d0, gamma=gamma, kernel=O.FORCE_GAUSSIAN)[1]
+    assert r0 == pytest.approx(math.exp(-0.5) / math.sqrt(gamma), rel=1e-13)
+    for eps in (1e-3, -1e-3):
+        assert O.force_magnitudes(d0 + eps, gamma=gamma, kernel=O.FORCE_GAUSSIAN)[1] < r0
+
+
+def test_gaussian_two_node_trajectory():
+    """Two nodes with the Gaussian kernel: per directed edge
+    x <- x(1 - 2 eta alpha (1 + beta exp(-x^2/2))), then k times
+    x <- x(1 + 2 eta exp(-gamma x^2 / 2))."""
+    rp, col = S.csr_from_pairs(np.array([0]), np.array([1]), 2)
+    k, T, gamma = 3, 20, 2.0
+    Y0 = np.array([[0.6, -0.2], [-0.4, 0.3]])
+    Y = O.serial_run(rp, col, 2, k, T, 2, Y0=Y0, order=O.ORDER_CSR, kernel=O.FORCE_GAUSSIAN)
+    d = Y0[0] - Y0[1]
+    for t in range(T):
+        eta = 1.0 - t / T
+        for _ in range(2):
+            d = d * (1 - 2 * eta * ALPHA * (1 + BETA * math.exp(-(d @ d) / 2)))
+            for _ in range(k):
+                d = d * (1 + 2 * eta * math.exp(-gamma * (d @ d) / 2))
+    assert np.allclose(Y[0] - Y[1], d, rtol=1e-10, atol=1e-12)
+
+
+def test_gaussian_kernel_is_selected_per_call():
+    """Selecting the Gaussian kernel for one call leaves the next default call
+    on the t-FDP forces."""
+    g = O.force_magnitudes(1.0, kernel=O.FORCE_GAUSSIAN)
+    t = O.force_magnitudes(1.0)
+    assert t == (0.5, 0.25) and g != t
+    with pytest.raises(ValueError):
+        O.force_magnitudes(1.0, kernel=7)
