@@ -20,7 +20,8 @@ The JSON line also carries
                    host's cores on a bounded sample (a few epochs);
   batched_and_served -- short runs of the other two workloads (default run
                    only; --no-extra skips them): the 512-graph batch against
-                   one graph per launch (plain time from every 8th graph), and
+                   one graph per launch (plain time from every 8th graph in
+                   size order), and
                    200 served jobs at 0.8 of the plain capacity, p50/p99
                    against FIFO one job at a time.
 Other workloads (--workload): batched-512 (512 graphs in one HIP-graph
@@ -153,11 +154,15 @@ def bench_plain(args):
     out_d = torch.empty((g.n, dim), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
 
+    engine = {"auto": SL.LAYOUT_ENGINE_AUTO, "global": SL.LAYOUT_ENGINE_GLOBAL,
+              "xcd": SL.LAYOUT_ENGINE_XCD, "lds": SL.LAYOUT_ENGINE_LDS}[args.engine]
+
     def opts():
         o = SL.layout_opts_init()
         o.update_mode = mode
         o.bundle_edges = args.bundle
         o.grid_blocks = args.grid
+        o.engine = engine
         return o
 
     if args.profile_epochs:
@@ -290,6 +295,10 @@ def bench_plain(args):
         roof["gather_pattern_ms"] = {k_: round(v, 4) for k_, v in gather.items()}
     if cache_probe:
         roof["cache_probe"] = cache_probe
+    quality = None
+    if args.quality:
+        quality = layout_quality(SL, rp_d, col_d, g, dim, k, T, opts, args.quality)
+        log(f"[bench] quality {quality}")
     cpu = None
     if not args.no_cpu and maker.startswith("gpu:"):
         log("[bench] no CPU baseline for a device-generated workload (headline workload only)")
@@ -317,7 +326,29 @@ def bench_plain(args):
         "positions_finite": finite,
         "roofline": roof,
         "cpu_baseline": cpu,
+        **({"quality": quality} if quality is not None else {}),
     }
+
+
+def layout_quality(SL, rp_d, col_d, g, dim, k, T, opts, seeds):
+    """NP and SI of whole layouts (seeds 0..seeds-1) from the library's own
+    monitors: exact SI over all nodes (O(n^2) on the device) for the planted
+    labels, and exact NP (r = 2) at 2,000 seeded sample nodes."""
+    if g.labels is None or g.n > 5_000_000 or dim != 2:
+        return {"skipped": "needs planted labels, a 2D layout and n <= 5M"}
+    rng = np.random.default_rng(12345)
+    nodes = np.sort(rng.choice(g.n, size=min(2000, g.n), replace=False)).astype(np.int32)
+    runs = []
+    for seed in range(seeds):
+        h = SL.layout_create_ex(rp_d, col_d, g.n, dim, k, T, seed, opts(), 1)
+        SL.layout_epoch(h, T)
+        si = SL.layout_silhouette(h, g.labels)
+        np_mean, _, _ = SL.layout_neighbourhood(h, nodes, 2)
+        SL.layout_destroy(h)
+        runs.append({"seed": seed, "np": round(float(np_mean), 5), "si": round(float(si), 5)})
+    return {"runs": runs, "np_mean": float(np.mean([r["np"] for r in runs])),
+            "si_mean": float(np.mean([r["si"] for r in runs])), "np_sample": int(nodes.size),
+            "si": "exact, all nodes"}
 
 
 # ---------------------------------------------------------------- batched
@@ -375,12 +406,15 @@ def bench_batched(args):
     SL.layout_batch_destroy(hb)
     log(f"[bench] batched {dt * 1e3:.1f} ms/step, replay {replay_ms:.1f} ms; timing the plain path")
     # plain path: one graph per launch sequence, same graphs; with a sample
-    # stride s > 1 only every s-th graph runs and the total is s times the
-    # sample's (graph sizes are drawn independently of the index)
+    # stride s > 1 the graphs are ordered by edge count and every s-th of that
+    # order runs (a systematic sample over sizes, both graph kinds), the
+    # total being s times the sample's
     stride = max(1, args.plain_stride)
+    by_size = sorted(range(len(gs)), key=lambda q: (gs[q].nnz, q))
+    sample = set(by_size[stride // 2::stride]) if stride > 1 else set(range(len(gs)))
     t0 = time.perf_counter()
     for q, g in enumerate([] if args.no_plain else gs):
-        if q % stride:
+        if q not in sample:
             continue
         hp = SL.layout_create_ex(rps[q], cols[q], g.n, 2, k, T, q, SL.layout_opts_init(), 1)
         SL.layout_epoch(hp, T)
@@ -390,7 +424,7 @@ def bench_batched(args):
             log(f"[bench] plain path: {q + 1}/{len(gs)} graphs, "
                 f"{time.perf_counter() - t0:.1f}s")
     torch.cuda.synchronize()
-    plain_s = (time.perf_counter() - t0) * stride
+    plain_s = (time.perf_counter() - t0) * len(gs) / max(1, len(sample))
     plain_value = edges * (1 + k) * T / plain_s if not args.no_plain else None
     log(f"[bench] batched {dt * 1e3:.1f} ms/step (replay {replay_ms:.1f} ms), plain "
         f"{plain_s * 1e3:.1f} ms")
@@ -538,6 +572,11 @@ def main():
     ap.add_argument("--bundle", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--engine", default="auto", choices=["auto", "global", "xcd", "lds"],
+                    help="plain workloads: the engine (default: the library's choice)")
+    ap.add_argument("--quality", type=int, default=0, metavar="SEEDS",
+                    help="plain workloads: also report NP and SI of this many whole layouts "
+                         "(seeds 0..SEEDS-1), computed by the library's device monitors")
     ap.add_argument("--relabel", default="none", choices=["none", "degree", "community"],
                     help="plain workloads: renumber the nodes before the run (descending "
                          "degree, or by community then degree) to measure locality")
