@@ -68,8 +68,6 @@ def test_sampled_energy_degree_weighted_draws(d1):
 @pytest.mark.parametrize("which", ["d1", "pl20k"])
 def test_effective_energy_matches_oracle(which, gamma, d1, pl20k):
     g = {"d1": d1, "pl20k": pl20k}[which]
-    if which == "pl20k" and gamma == 3.0:
-        pytest.skip("one large case is enough for the pair sweep")
     with SL.Layout(g.row_ptr, g.col, g.n, k=5, epochs=30, seed=1, gamma=gamma) as L:
         L.run(5)
         Y = L.positions().astype(np.float64)

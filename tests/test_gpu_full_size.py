@@ -9,6 +9,8 @@ automatic launch shape).
   259k-node graph against the FP64 oracle, within 1e-5 x the output's
   diameter (eta0 = 1/d_max, the step at which a hub stays inside the layout;
   the same bar as the smaller cases);
+* the same Jacobi epochs from a start squeezed into [-1, 1]^2, where the
+  repulsion is as strong as the attraction (and shown to matter);
 * the same Jacobi epoch of the 4M-node graph with 3D positions;
 * one ATOMIC epoch of the 4M-node graph conserves the centroid (every pair
   update adds +v and -v) within 1e-4 of the layout's extent.
@@ -74,6 +76,38 @@ def test_full_size_jacobi_epoch(which, d3, d3_dev):
     err = float(np.abs(Y - ref).max())
     print(f"{which}: Jacobi epoch max error {err:.3e}, diameter {_diam(ref):.1f}", flush=True)
     assert err <= 1e-5 * _diam(ref), (err, _diam(ref))
+
+
+@pytest.mark.parametrize("which", ["lj-like-4m", "orkut-like-259k"])
+def test_full_size_jacobi_epoch_dense_start(which, d3, d3_dev):
+    """The same synchronous epoch from a start squeezed into [-1, 1]^2, where
+    every pair is close and the repulsion matters as much as the attraction:
+    within 1e-5 x diameter of the oracle, while dropping the repulsion from
+    the oracle moves the result by more than 100 x that bar (so the check
+    covers the negatives' forces at full size, not only the attraction)."""
+    if which == "lj-like-4m":
+        g = d3
+        rp, col = d3_dev
+    else:
+        g = S.cached(which, S.orkut_like)
+        rp, col = g.row_ptr, g.col
+    eta0 = 1.0 / float(g.degrees().max())
+    Y0 = (O.init_positions(g.n, 1) / np.sqrt(np.float32(g.n))).astype(np.float32)
+    ref = O.jacobi_epoch(g.row_ptr, g.col, g.n, 5, 0, 30, 1, Y0.astype(np.float64), eta0=eta0)
+    attr_only = O.jacobi_epoch(g.row_ptr, g.col, g.n, 5, 0, 30, 1, Y0.astype(np.float64),
+                               eta0=eta0, use_rep=False)
+    init = torch.from_numpy(Y0).to("cuda:0") if hasattr(rp, "is_cuda") else Y0
+    with SL.Layout(rp, col, g.n, k=5, epochs=30, seed=1, update_mode=SL.LAYOUT_JACOBI,
+                   eta0=eta0, init_pos=init) as L:
+        L.run(1)
+        Y = L.positions().astype(np.float64)
+    tol = 1e-5 * _diam(ref)
+    err = float(np.abs(Y - ref).max())
+    rep = float(np.abs(ref - attr_only).max())
+    print(f"{which} dense start: Jacobi epoch max error {err:.3e}, tol {tol:.3e}, "
+          f"repulsion's share of the move up to {rep:.3e}", flush=True)
+    assert rep > 100 * tol
+    assert err <= tol, (err, tol)
 
 
 def test_d3_jacobi_epoch_in_3d(d3, d3_dev):
