@@ -476,6 +476,10 @@ def bench_served(args):
     # own graph, svc_of[picks[i]]
     used = np.unique(picks)
     svc_of = np.full(len(pool), np.nan)
+    # first, untimed: one graph of each engine's size range (the first call of
+    # each engine loads its code objects)
+    by_n = sorted(used, key=lambda q: pool[q].n)
+    run_plain([by_n[0], by_n[len(by_n) // 2], by_n[-1]])
     svc_of[used] = run_plain(used)
     job_svc = svc_of[picks]
     mean_svc = float(job_svc.mean())
@@ -497,11 +501,13 @@ def bench_served(args):
                 log(f"[bench] rho {rho}: {len(ids)}/{args.jobs} jobs submitted, "
                     f"{time.perf_counter() - t_start:.1f}s")
         log(f"[bench] rho {rho}: {len(ids)} jobs submitted")
+        served_lat = []
         for q, (jid, n) in enumerate(ids):
             SL.layout_server_wait(srv, jid, 600.0)
-            SL.layout_server_take(srv, jid, n)
+            served_lat.append(SL.layout_server_take(srv, jid, n)[1])
             if (q + 1) % 50 == 0:
                 log(f"[bench] rho {rho}: {q + 1}/{len(ids)} jobs done")
+        served_lat = np.array(served_lat)
         wall = time.perf_counter() - t_start
         st = SL.layout_server_get_stats(srv)
         SL.layout_server_destroy(srv)
@@ -513,12 +519,19 @@ def bench_served(args):
             t_free = start + s
             lat.append(t_free - ta)
         lat = np.array(lat)
+        # the jobs behind the served tail: nodes, plain service time, served
+        # and FIFO latency of the five slowest served jobs
+        slow = np.argsort(served_lat)[::-1][:5]
+        tail = [[int(pool[picks[i]].n), round(float(job_svc[i]), 3), round(float(served_lat[i]), 3),
+                 round(float(lat[i]), 3)] for i in slow]
         results[str(rho)] = {
             "served": {"p50_s": st["p50_latency_s"], "p99_s": st["p99_latency_s"],
                        "edge_updates_per_s": st["edge_updates"] / wall, "wall_s": wall,
                        "rounds": st["rounds"]},
             "plain_fifo": {"p50_s": float(np.percentile(lat, 50)),
                            "p99_s": float(np.percentile(lat, 99))},
+            "slowest_served": {"columns": ["nodes", "plain_s", "served_s", "fifo_s"],
+                               "jobs": tail},
         }
         log(f"[bench] rho {rho}: {results[str(rho)]}")
     # capacity: the first jobs of the stream submitted at once; makespan

@@ -110,12 +110,12 @@ typedef struct layout_opts {
                                  256-lane workgroup per CU and n / nodes_per_lane lanes */
     int32_t hub_split_edges;  /* rows with more edges are split into segments of this many
                                  edges, one lane each; 0 = default (4 * bundle_edges on the
-                                 global engine, never on the LDS engine) */
+                                 global and XCD-local engines, 64 on the LDS engine) */
     int32_t nodes_per_lane;   /* concurrency cap of the automatic launch shape: lanes in
                                  flight <= n / nodes_per_lane on the global and XCD-local
                                  engines (workgroups of that many lanes rounded up to 64, at
-                                 most 256), working lanes = n / nodes_per_lane in [64, 256] on
-                                 the LDS engine, so that few concurrent updates hit one node
+                                 most 256), working lanes = n / nodes_per_lane rounded up to 64
+                                 on the LDS engine, so that few concurrent updates hit one node
                                  (Sec. 3.4); 0 = default 32 */
     int32_t init_mode;        /* LAYOUT_INIT_UNIFORM (default) / LAYOUT_INIT_PMDS; ignored
                                  when init_pos is given */
@@ -497,20 +497,27 @@ void layout_batch_destroy(layout_batch_t *B);
 
 /* ---- served layout: continuous batching of submitted jobs -----------------
  *
- * A server owns one device stream and a scheduler thread.  Jobs (a graph, k,
- * epochs, seed) are submitted from any host thread and copied at submission.
- * The scheduler admits queued jobs in arrival order while a slot is free and
- * the job's device footprint fits the HBM budget, keeps every admitted job's
- * CSR, positions and chunk table resident on the device, and runs rounds:
- *   - a job whose positions fit one workgroup's LDS runs all its epochs in
- *     one workgroup (LDS engine) in its first round;
- *   - every other job advances by a slice of its current epoch (at most
- *     round_edges directed edges shared among the running jobs) in one
- *     multi-graph launch of the global engine; an epoch may span rounds.
- * When a job's last epoch ends its positions are copied to host memory, its
- * device memory is freed and the next queued job can be admitted.  Latency is
- * measured from submission to positions-on-host.  The method per job is the
- * same as layout_create + layout_epoch (same draws for the same seed). */
+ * A server owns a scheduler thread and one device stream per class of job.
+ * Jobs (a graph, k, epochs, seed) are submitted from any host thread and
+ * copied at submission.  The scheduler admits queued jobs in arrival order
+ * while a slot is free and the job's device footprint fits the HBM budget,
+ * and keeps every admitted job's CSR, positions and chunk table resident on
+ * the device.  Each class runs launches of its own, the next one as soon as
+ * its last one has ended, independently of the other classes:
+ *   - jobs whose positions fit one workgroup's LDS: all their remaining
+ *     epochs, one workgroup each (LDS engine);
+ *   - jobs whose positions fit one XCD's L2 (engine AUTO or XCD,
+ *     HOGWILD_STORE, automatic launch shape): a slice of each one's current
+ *     epoch on XCD-local bins;
+ *   - every other job: a slice of the current epoch of the oldest jobs whose
+ *     lane caps (n / 32 each) fit the device's lanes together, plus later ones
+ *     that still fit, in one multi-graph launch on all CUs; the others wait.
+ * A launch's slices share at most round_edges directed edges, in proportion
+ * to the jobs' sizes; an epoch may span launches.  When a job's last epoch
+ * ends its positions are copied to host memory, its device memory is freed
+ * and the next queued job can be admitted.  Latency is measured from
+ * submission to positions-on-host.  The method per job is the same as
+ * layout_create + layout_epoch (same draws for the same seed). */
 
 typedef struct layout_server layout_server_t;
 
@@ -526,7 +533,7 @@ typedef struct layout_server_stats {
     int64_t submitted, completed, failed, rejected;
     int64_t queued, running;
     int64_t hbm_in_use, hbm_budget; /* bytes */
-    int64_t rounds;
+    int64_t rounds;        /* launches that have ended, over all classes */
     double edge_updates;   /* sum over completed jobs of |E| (1 + k) epochs */
     double busy_seconds;   /* wall time with at least one job admitted */
     double p50_latency_s, p99_latency_s, mean_latency_s; /* over completed jobs */
@@ -536,12 +543,8 @@ typedef struct layout_server_stats {
 /* Starts a server.  hbm_budget_bytes: cap on the summed device footprint of
  * admitted jobs (0 = 90% of the free device memory at start).  max_slots:
  * cap on concurrently admitted jobs (>= 1).  round_edges: directed edges of
- * global-engine work per round (0 = default, 32M).  opts: as for
- * layout_create_ex (init_pos, start_epoch, stream are ignored).  Each round
- * runs the remaining epochs of every job that fits LDS, an epoch slice of
- * every job whose positions fit one XCD's L2 on XCD-local bins (engine AUTO
- * or XCD, HOGWILD_STORE, automatic launch shape), and an
- * epoch slice of every other job in one all-CU launch.
+ * a launch's epoch slices (0 = default, 32M).  opts: as for
+ * layout_create_ex (init_pos, start_epoch, stream are ignored).
  * opts->update_mode = LAYOUT_JACOBI (engine AUTO or GLOBAL) serves the
  * synchronous test mode of layout_create_ex: every job runs on the global
  * engine, its pair forces of one epoch summed (over the epoch's slices) into
@@ -569,7 +572,7 @@ int layout_server_submit_ex(layout_server_t *S, const int32_t *row_ptr, const in
                             int64_t *job_id);
 
 /* Cancels a job.  A queued job ends at once; a running one is retired after
- * the round in flight, its device memory freed.  Its state becomes
+ * its launch in flight, its device memory freed.  Its state becomes
  * LAYOUT_JOB_CANCELLED; layout_server_wait then returns LAYOUT_E_INVALID_ARG
  * and layout_server_take forgets it.  A job that has already ended (or an
  * unknown id): LAYOUT_E_INVALID_ARG.  Thread-safe. */
@@ -591,14 +594,15 @@ int layout_server_get_stats(layout_server_t *S, layout_server_stats *stats);
 
 /* hold != 0: the scheduler keeps admitting queued jobs and setting up their
  * device state (copy, validation, chunk and alias tables, initial positions)
- * but runs no round until hold = 0; running jobs pause between rounds.
+ * but starts no launch until hold = 0; running jobs pause once their
+ * current launches end.
  * Thread-safe. */
 int layout_server_hold(layout_server_t *S, int32_t hold);
 
 /* Test support: the k negatives that a queued or running job draws in epoch
  * `epoch` for each of its nnz directed edges, host_out[e*k + m] (caller-owned,
  * nnz*k int32), computed on the device from the job's own device state (its
- * seed, size and alias table) by the scheduler between rounds.  Blocks until
+ * seed, size and alias table) by the scheduler between launches.  Blocks until
  * the job has been admitted and the request answered; with the server held
  * (layout_server_hold) the answer precedes the job's first epoch.  A job
  * that has already ended: LAYOUT_E_DONE.  Thread-safe (Algorithm 1; the draw
@@ -606,7 +610,7 @@ int layout_server_hold(layout_server_t *S, int32_t hold);
 int layout_server_debug_draws(layout_server_t *S, int64_t job_id, int32_t epoch,
                               int32_t *host_out);
 
-/* Stops the scheduler after the running jobs' current round, frees every
+/* Stops the scheduler once the launches in flight have ended, frees every
  * job.  NULL is ignored. */
 int layout_server_destroy(layout_server_t *S);
 

@@ -279,13 +279,15 @@ namespace {
 // move to the device-wide group while one of them alone would outlast it:
 // nnz_g > X / kLdsBalance, with X the device-wide group's directed edges.
 // kLdsBalance is the measured ratio of the device's edge rate on the XCD
-// bins to one CU's on the LDS engine (about 700 on MI355X at k = 5: 1.07e10
-// against 1.5e7 directed edges per second).  Graphs below kLdsKeepEdges stay
+// bins to one CU's on the LDS engine for the graphs the rule weighs (about
+// 250 on MI355X at k = 5: 1.07e10 against 3.8e7 to 5.2e7 directed edges per
+// second for 10k- to 18k-node power-law graphs, n / 32 lanes, hub rows
+// split).  Graphs below kLdsKeepEdges stay
 // in LDS, so a batch of small graphs keeps its one-launch replay.  Then, at
 // most one LDS graph per CU: a second LDS workgroup on a CU waits for the
 // first when their positions do not fit its LDS together, so the largest
 // graphs beyond the CU count move as well.
-constexpr double kLdsBalance = 700.0;
+constexpr double kLdsBalance = 250.0;
 constexpr int64_t kLdsKeepEdges = 100000;
 
 void balance_lds(const std::vector<int64_t>& nnz, std::vector<uint8_t>& in_lds, int cus) {
@@ -430,10 +432,10 @@ int layout_batch_create(const layout_graph* graphs, int32_t count, int32_t k, in
     if (lds) {
       const int block = o.block_threads ? o.block_threads : lds_lanes_for(gr.n, o.nodes_per_lane);
       B->lds_block[g] = block;
-      // one workgroup per graph: chunks of whole rows, rows never split
+      // one workgroup per graph: enough chunks for every lane, hub rows split
       B->lds_bundle[g] = o.bundle_edges ? o.bundle_edges
                                         : std::max(1, std::min(16, nnz / (4 * block)));
-      B->lds_hub[g] = o.hub_split_edges ? o.hub_split_edges : std::max(1, nnz);
+      B->lds_hub[g] = o.hub_split_edges ? o.hub_split_edges : kLdsHub;
       cap = nnz > 0 ? chunk_bound(nnz, B->lds_bundle[g], B->lds_hub[g]) : 0;
       max_lds = std::max(max_lds, lds_bytes_for(gr.n));
       B->lds_ids.push_back(g);

@@ -20,13 +20,18 @@ constexpr int kNodesPerLane = 32;            // lanes in flight <= n / 32 (both 
 constexpr int kLanesPerCU = 256;             // global engine: at most 256 lanes per CU in flight
                                              // (the random-access throughput saturates there)
 
-// Active lanes of the LDS engine for an n-node graph: n / nodes_per_lane,
-// a multiple of 64 in [64, 256].
+// Active lanes of the LDS engine for an n-node graph: n / nodes_per_lane
+// rounded up to whole wavefronts, as on the other engines (at most 1024, one
+// workgroup; a 2D graph that fits LDS has at most 640).
 inline int lds_lanes_for(int32_t n, int nodes_per_lane) {
   const int npl = nodes_per_lane > 0 ? nodes_per_lane : kNodesPerLane;
-  int lanes = (n / npl) / 64 * 64;
-  return lanes < 64 ? 64 : (lanes > 256 ? 256 : lanes);
+  const int want = (((n / npl) > 1 ? (n / npl) : 1) + 63) / 64 * 64;
+  return want > 1024 ? 1024 : want;
 }
+// LDS engine: rows above this many edges are split into segments, as on the
+// other engines.  A wavefront runs its lanes' chunks in step, so one lane on
+// a whole hub row would hold its 63 neighbours idle for the row's length.
+constexpr int kLdsHub = kHubFactor * kDefaultBundle;
 constexpr long long kLdsAutoMaxEdges = 400000;  // AUTO picks LDS below this many directed edges
 constexpr long long kXcdMaxPositionBytes = 3 << 20;  // XCD-local engine: positions within 3 MiB
                                                      // of the 4 MiB L2 of one XCD

@@ -2,25 +2,28 @@
 // include/snaplayout.h).
 //
 // Threads: callers submit, poll, wait and take under one mutex; a single
-// scheduler thread owns every HIP call after creation.  Per round the
-// scheduler
-//   1. admits queued jobs in arrival order while a slot is free and the job's
+// scheduler thread owns every HIP call after creation.  Jobs fall into three
+// classes by size (LDS, one XCD's L2, all CUs), and each class has a stream
+// and launches of its own.  In a loop the scheduler
+//   1. notes the launches that have ended (an event per class), advances
+//      their jobs' epoch counters and retires finished jobs (positions to
+//      host, device memory freed, latency recorded) and cancelled ones;
+//   2. admits queued jobs in arrival order while a slot is free and the job's
 //      device footprint fits the budget (device copy, validation, chunk
 //      table, alias table of weighted negatives, initial positions: the
 //      caller's, seeded uniform or Pivot MDS);
-//   2. launches, on two streams, the LDS engine for newly admitted small jobs
-//      (all their epochs) and one multi-graph launch of the global engine
-//      that advances every other job by a slice of its current epoch (the
-//      slices share the round's edge budget);
-//   3. waits, advances epoch counters, and retires finished jobs (positions to
-//      host, device memory freed, latency recorded) and cancelled ones.
-// In JACOBI mode (the synchronous test mode) every job runs on the global
-// engine with its own accumulator D; the epoch's slices add into D and the
-// job's positions move (Y += D) once its last slice of the epoch has run.
-// While the server is held (layout_server_hold) jobs are still admitted and
-// set up, but no round runs; per-job debug requests (the negatives a job
-// draws) are answered by the scheduler between rounds, on the job's own
-// device state.
+//   3. starts the next launch of every class whose last one has ended: all
+//      remaining epochs of the LDS jobs, one workgroup each; a slice of the
+//      current epoch of every XCD-class job on XCD-local bins; a slice of the
+//      current epoch of the oldest all-CU jobs that fit the device's lanes.
+// No class waits for another, so a long launch of one class holds up no job
+// of the others.  In JACOBI mode (the synchronous test mode) every job runs
+// on the global engine with its own accumulator D; the epoch's slices add
+// into D and the job's positions move (Y += D) once its last slice of the
+// epoch has run.  While the server is held (layout_server_hold) jobs are
+// still admitted and set up, but no launch starts; per-job debug requests
+// (the negatives a job draws) are answered by the scheduler between
+// launches, on the job's own device state.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -71,6 +74,8 @@ struct Job {
   DeviceBuffers buf;
   int64_t footprint = 0;
   bool lds = false;
+  int cls = 0;             // kClassLds, kClassXcd or kClassWide
+  bool in_flight = false;  // part of a launch that has not ended
   int32_t bundle = kDefaultBundle, hub = kDefaultBundle * kHubFactor;
   int32_t lanes = 0;  // LDS engine: working lanes of the workgroup
   int64_t chunk_cap = 0, n_chunks = 0;
@@ -78,6 +83,25 @@ struct Job {
   float2* D = nullptr;    // JACOBI: the epoch's accumulated displacement
   int32_t t = 0;          // epochs completed
   int64_t chunk_pos = 0;  // chunks of the current epoch already processed
+};
+
+// The three classes of job.  Each has launches of its own, on a stream of its
+// own: jobs whose positions fit one workgroup's LDS, jobs whose positions fit
+// one XCD's L2, and the rest, which run on all CUs.
+enum { kClassLds = 0, kClassXcd = 1, kClassWide = 2, kClasses = 3 };
+
+// A class's launch: the jobs it advances, the chunks of its current epoch
+// each runs, and the host tables its uploads read (kept until it has ended).
+struct ClassLaunch {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  std::vector<Job*> jobs;
+  std::vector<int64_t> slice;
+  std::vector<GraphDesc> table;
+  std::vector<int32_t> ids;
+  std::vector<XcdSeg> segs;
+  XcdBin bins[kXcds];
 };
 
 // A caller's request for the negatives a running job draws in one epoch,
@@ -100,7 +124,7 @@ struct layout_server {
   std::unordered_map<int64_t, Job*> jobs;
   std::vector<Job*> active;  // scheduler thread only
   bool stop = false;
-  bool hold = false;  // admit and set up jobs, but run no round
+  bool hold = false;  // admit and set up jobs, but start no launch
   std::deque<DrawRequest*> draw_requests;
   bool dead = false;  // a device error stopped the scheduler
   std::string dead_msg;
@@ -111,7 +135,8 @@ struct layout_server {
   int32_t max_slots = 1;
   int64_t next_id = 1;
   int dev = 0;
-  hipStream_t stream = nullptr, side = nullptr;
+  hipStream_t stream = nullptr;  // job setup, readout and debug requests
+  ClassLaunch cls[kClasses];
   GraphDesc* d_table = nullptr;
   GraphDesc* d_table_lds = nullptr;
   int32_t* d_ids = nullptr;
@@ -149,11 +174,14 @@ void plan_job(const layout_server_t* S, Job& j) {
         S->opts.block_threads ? S->opts.block_threads : lds_lanes_for(j.n, S->opts.nodes_per_lane);
     j.lanes = block;
     j.bundle = S->opts.bundle_edges ? S->opts.bundle_edges : std::max(1, std::min(16, nz / (4 * block)));
-    j.hub = S->opts.hub_split_edges ? S->opts.hub_split_edges : std::max(1, nz);
+    j.hub = S->opts.hub_split_edges ? S->opts.hub_split_edges : kLdsHub;
   } else {
     j.bundle = S->opts.bundle_edges ? S->opts.bundle_edges : kDefaultBundle;
     j.hub = S->opts.hub_split_edges ? S->opts.hub_split_edges : kHubFactor * j.bundle;
   }
+  j.cls = j.lds ? kClassLds
+          : (S->xcd_ok && int64_t(j.n) * 8 <= kXcdMaxPositionBytes) ? kClassXcd
+                                                                    : kClassWide;
   j.footprint = footprint_of(S, j, j.bundle, j.hub);
 }
 
@@ -269,171 +297,237 @@ void finish_job(layout_server_t* S, Job* j, int code, const std::string& msg) {
   S->cv_done.notify_all();
 }
 
-// One round over the active jobs; returns a HIP/ABI status.
-int run_round(layout_server_t* S) {
-  const int k = S->active.empty() ? 0 : S->active.front()->k;
-  std::vector<Job*> lds_jobs, glob_jobs;
-  for (Job* j : S->active) {
-    if (j->nnz == 0 || j->t >= j->epochs) continue;
-    if (j->lds)
-      lds_jobs.push_back(j);
-    else
-      glob_jobs.push_back(j);
-  }
-  // LDS jobs: all epochs in this round, one workgroup each (grouped by k)
-  std::vector<GraphDesc> lt;
-  std::vector<int32_t> ids;
-  int max_lds = 8;
-  for (Job* j : lds_jobs) {
+// Jobs of class c that can join its next launch: admitted, in no launch,
+// not cancelled and not done.  Arrival order (the order of `active`).
+std::vector<Job*> ready_jobs(layout_server_t* S, int c) {
+  std::vector<Job*> v;
+  for (Job* j : S->active)
+    if (j->cls == c && !j->in_flight && !j->cancel.load() && j->nnz > 0 && j->t < j->epochs)
+      v.push_back(j);
+  return v;
+}
+
+// LDS class: every job runs all its remaining epochs in one workgroup.
+int start_lds(layout_server_t* S, ClassLaunch& L, const std::vector<Job*>& jobs) {
+  const int k = jobs.front()->k;
+  L.table.clear();
+  L.ids.clear();
+  int max_lds = 8, block = 64;
+  for (Job* j : jobs) {
     GraphDesc d = j->desc;
     d.n_chunks = j->n_chunks;
     d.t0 = j->t;
-    ids.push_back(static_cast<int32_t>(lt.size()));
-    lt.push_back(d);
+    L.ids.push_back(static_cast<int32_t>(L.table.size()));
+    L.table.push_back(d);
     max_lds = std::max(max_lds, lds_bytes_for(j->n));
+    block = std::max(block, j->lanes);
   }
-  // global jobs: a slice of the current epoch each, the round's edges shared
-  // in proportion to the jobs' sizes so that every job advances the same
-  // fraction of an epoch per round (large jobs are not starved by many small
-  // ones)
-  std::vector<GraphDesc> gt;
-  std::vector<int64_t> slice(glob_jobs.size());
+  hipError_t e = hipMemcpyAsync(S->d_table_lds, L.table.data(), sizeof(GraphDesc) * L.table.size(),
+                                hipMemcpyHostToDevice, L.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(S->d_ids, L.ids.data(), sizeof(int32_t) * L.ids.size(),
+                       hipMemcpyHostToDevice, L.stream);
+  if (e != hipSuccess) return hip_fail(e, "uploading the LDS table");
+  int rc = allow_lds(k, max_lds);
+  if (rc != LAYOUT_OK) return rc;
+  LdsGroup lg;
+  lg.d_table = S->d_table_lds;
+  lg.d_ids = S->d_ids;
+  lg.blocks = static_cast<int>(L.table.size());
+  lg.lds_bytes = max_lds;
+  lg.k = k;
+  lg.mode = S->mode_lds;
+  lg.degree = S->opts.neg_weights != LAYOUT_NEG_UNIFORM;
+  lg.block = block;
+  // one launch when the jobs share the epoch count, else one launch per job
+  std::vector<int32_t> counts;
+  for (Job* j : jobs) counts.push_back(j->epochs - j->t);
+  const bool uniform =
+      std::all_of(counts.begin(), counts.end(), [&](int32_t c) { return c == counts.front(); });
+  if (uniform) {
+    rc = launch_lds_epochs(L.stream, lg, 0, counts.front());
+  } else {
+    for (size_t q = 0; q < jobs.size() && rc == LAYOUT_OK; ++q) {
+      LdsGroup one = lg;
+      one.d_ids = S->d_ids + q;
+      one.blocks = 1;
+      rc = launch_lds_epochs(L.stream, one, 0, counts[q]);
+    }
+  }
+  L.jobs = jobs;
+  L.slice.assign(jobs.size(), 0);
+  return rc;
+}
+
+// A slice of the current epoch for each job: the launch's edge budget shared
+// in proportion to the jobs' sizes, so that every job advances the same
+// fraction of an epoch per launch (large jobs are not starved by many small
+// ones).
+void take_slices(layout_server_t* S, ClassLaunch& L, const std::vector<Job*>& jobs,
+                 std::vector<GraphDesc>& out) {
   double total_nnz = 0.0;
-  for (Job* j : glob_jobs) total_nnz += double(j->nnz);
-  for (size_t q = 0; q < glob_jobs.size(); ++q) {
-    Job* j = glob_jobs[q];
+  for (Job* j : jobs) total_nnz += double(j->nnz);
+  L.jobs = jobs;
+  L.slice.clear();
+  out.clear();
+  for (Job* j : jobs) {
     const int64_t share = std::max<int64_t>(
-        kMinSliceEdges, int64_t(double(S->round_edges) * double(j->nnz) / std::max(1.0, total_nnz)));
+        kMinSliceEdges,
+        int64_t(double(S->round_edges) * double(j->nnz) / std::max(1.0, total_nnz)));
     const double edges_per_chunk = double(j->nnz) / double(std::max<int64_t>(1, j->n_chunks));
     const int64_t want = std::max<int64_t>(1, int64_t(double(share) / edges_per_chunk));
-    slice[q] = std::min(want, j->n_chunks - j->chunk_pos);
+    const int64_t slice = std::min(want, j->n_chunks - j->chunk_pos);
+    L.slice.push_back(slice);
     GraphDesc d = j->desc;
     d.t0 = j->t;
     d.chunk_offset = j->chunk_pos;
-    d.n_chunks = slice[q];
-    gt.push_back(d);
+    d.n_chunks = slice;
+    out.push_back(d);
   }
-  hipError_t e = hipSuccess;
-  int rc = LAYOUT_OK;
-  if (!lt.empty()) {
-    e = hipMemcpyAsync(S->d_table_lds, lt.data(), sizeof(GraphDesc) * lt.size(),
-                       hipMemcpyHostToDevice, S->side);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(S->d_ids, ids.data(), sizeof(int32_t) * ids.size(), hipMemcpyHostToDevice,
-                         S->side);
-    if (e != hipSuccess) return hip_fail(e, "uploading the LDS table");
-    if ((rc = allow_lds(k, max_lds)) != LAYOUT_OK) return rc;
-    LdsGroup lg;
-    lg.d_table = S->d_table_lds;
-    lg.d_ids = S->d_ids;
-    lg.blocks = static_cast<int>(lt.size());
-    lg.lds_bytes = max_lds;
-    lg.k = k;
-    lg.mode = S->mode_lds;
-    lg.degree = S->opts.neg_weights != LAYOUT_NEG_UNIFORM;
-    int lds_block = 64;
-    for (Job* j : lds_jobs) lds_block = std::max(lds_block, j->lanes);
-    lg.block = lds_block;
-    // every LDS job runs all its remaining epochs in this round; one launch
-    // when they share the count, else one launch per job
-    int32_t count = 0;
-    for (Job* j : lds_jobs) count = std::max(count, j->epochs - j->t);
-    std::vector<int32_t> counts;
-    for (Job* j : lds_jobs) counts.push_back(j->epochs - j->t);
-    const bool uniform = std::all_of(counts.begin(), counts.end(),
-                                     [&](int32_t c) { return c == counts.front(); });
-    if (uniform) {
-      rc = launch_lds_epochs(S->side, lg, 0, count);
-    } else {
-      for (size_t q = 0; q < lds_jobs.size() && rc == LAYOUT_OK; ++q) {
-        LdsGroup one = lg;
-        one.d_ids = S->d_ids + q;
-        one.blocks = 1;
-        rc = launch_lds_epochs(S->side, one, 0, counts[q]);
-      }
-    }
-    if (rc != LAYOUT_OK) return rc;
+}
+
+// XCD class: the jobs' slices on XCD-local bins, one launch.
+int start_xcd(layout_server_t* S, ClassLaunch& L, const std::vector<Job*>& jobs) {
+  std::vector<GraphDesc> gx;
+  take_slices(S, L, jobs, gx);
+  L.table.clear();
+  L.segs.clear();
+  XcdGroup xg;
+  xg.grid = plan_xcd_bins(gx, S->opts.nodes_per_lane, L.table, L.segs, L.bins);
+  xg.d_table = S->d_table_xcd;
+  xg.d_segs = S->d_segs;
+  xg.d_bins = S->d_bins;
+  xg.d_counters = S->d_xcd_ctr;
+  xg.n_segs = static_cast<int32_t>(L.segs.size());
+  xg.k = jobs.front()->k;
+  xg.degree = S->opts.neg_weights != LAYOUT_NEG_UNIFORM;
+  for (const GraphDesc& d : gx) xg.total_chunks += d.n_chunks;
+  hipError_t e = hipMemcpyAsync(S->d_table_xcd, L.table.data(), sizeof(GraphDesc) * L.table.size(),
+                                hipMemcpyHostToDevice, L.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(S->d_segs, L.segs.data(), sizeof(XcdSeg) * L.segs.size(),
+                       hipMemcpyHostToDevice, L.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(S->d_bins, L.bins, sizeof(XcdBin) * kXcds, hipMemcpyHostToDevice, L.stream);
+  if (e != hipSuccess) return hip_fail(e, "uploading the XCD bins");
+  launch_fill_i32(L.stream, S->d_xcd_ctr, xg.n_segs, 0);
+  return launch_xcd_group_epochs(L.stream, xg, 0, 1);
+}
+
+// All-CU class.  The jobs take turns in arrival order: a launch runs the
+// oldest ones whose lane caps (n / nodes_per_lane each, the concurrency a job
+// has alone) fit the device's lanes together, plus any later one that still
+// fits, so that each runs at the speed it has alone instead of all of them
+// sharing the device and all finishing late.  The others keep their device
+// state and wait.
+int start_wide(layout_server_t* S, ClassLaunch& L, const std::vector<Job*>& ready) {
+  const int npl = S->opts.nodes_per_lane > 0 ? S->opts.nodes_per_lane : kNodesPerLane;
+  const int64_t device_lanes = int64_t(device_props().cus) * kLanesPerCU;
+  std::vector<Job*> jobs;
+  int64_t used = 0;
+  for (Job* j : ready) {
+    const int64_t cap = std::max<int64_t>(64, j->n / npl);
+    if (!jobs.empty() && used + cap > device_lanes) continue;
+    used += cap;
+    jobs.push_back(j);
   }
-  // global jobs that fit one XCD's L2: XCD-local bins, one launch
-  {
-    std::vector<GraphDesc> gx, rest;
-    for (const GraphDesc& d : gt) {
-      if (S->xcd_ok && int64_t(d.n) * 8 <= kXcdMaxPositionBytes && d.n_chunks > 0)
-        gx.push_back(d);
-      else
-        rest.push_back(d);
-    }
-    if (!gx.empty()) {
-      std::vector<GraphDesc> table;
-      std::vector<XcdSeg> segs;
-      XcdBin bins[kXcds];
-      XcdGroup xg;
-      xg.grid = plan_xcd_bins(gx, S->opts.nodes_per_lane, table, segs, bins);
-      xg.d_table = S->d_table_xcd;
-      xg.d_segs = S->d_segs;
-      xg.d_bins = S->d_bins;
-      xg.d_counters = S->d_xcd_ctr;
-      xg.n_segs = static_cast<int32_t>(segs.size());
-      xg.k = k;
-      xg.degree = S->opts.neg_weights != LAYOUT_NEG_UNIFORM;
-      for (const GraphDesc& d : gx) xg.total_chunks += d.n_chunks;
-      e = hipMemcpyAsync(S->d_table_xcd, table.data(), sizeof(GraphDesc) * table.size(),
-                         hipMemcpyHostToDevice, S->stream);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(S->d_segs, segs.data(), sizeof(XcdSeg) * segs.size(),
-                           hipMemcpyHostToDevice, S->stream);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(S->d_bins, bins, sizeof(XcdBin) * kXcds, hipMemcpyHostToDevice,
-                           S->stream);
-      if (e != hipSuccess) return hip_fail(e, "uploading the XCD bins");
-      launch_fill_i32(S->stream, S->d_xcd_ctr, xg.n_segs, 0);
-      rc = launch_xcd_group_epochs(S->stream, xg, 0, 1);
-      if (rc != LAYOUT_OK) return rc;
-      // the host arrays above are read by the copies: finish them first
-      e = hipStreamSynchronize(S->stream);
-      if (e != hipSuccess) return hip_fail(e, "running the XCD bins");
-    }
-    gt.swap(rest);
-  }
-  if (!gt.empty()) {
-    GlobalGroup gg;
-    gg.d_table = S->d_table;
-    gg.G = static_cast<int>(gt.size());
-    for (const GraphDesc& d : gt) gg.total_chunks += d.n_chunks;
-    gg.k = k;
-    gg.mode = S->mode_global;
-    gg.degree = S->opts.neg_weights != LAYOUT_NEG_UNIFORM;
-    gg.block = S->opts.block_threads && S->opts.block_threads <= 256 ? S->opts.block_threads : 256;
-    gg.grid = S->opts.grid_blocks;
-    gg.max_lanes = fair_lanes(gt, S->opts.nodes_per_lane);
-    if (!S->opts.block_threads)  // small lane caps get small workgroups
-      gg.block = static_cast<int>(
-          std::min<int64_t>(256, std::max<int64_t>(64, div_up(std::max<int64_t>(1, gg.max_lanes), 64) * 64)));
-    plan_rounds(gt, gg, int64_t(global_grid(gg)) * gg.block);
-    e = hipMemcpyAsync(S->d_table, gt.data(), sizeof(GraphDesc) * gt.size(), hipMemcpyHostToDevice,
-                       S->stream);
-    if (e != hipSuccess) return hip_fail(e, "uploading the round table");
-    rc = launch_global_epochs(S->stream, gg, 0, 1);
-    if (rc != LAYOUT_OK) return rc;
-  }
-  // JACOBI: a job whose epoch ended in this round moves by its summed D
+  std::vector<GraphDesc>& gt = L.table;
+  take_slices(S, L, jobs, gt);
+  GlobalGroup gg;
+  gg.d_table = S->d_table;
+  gg.G = static_cast<int>(gt.size());
+  for (const GraphDesc& d : gt) gg.total_chunks += d.n_chunks;
+  gg.k = jobs.front()->k;
+  gg.mode = S->mode_global;
+  gg.degree = S->opts.neg_weights != LAYOUT_NEG_UNIFORM;
+  gg.block = S->opts.block_threads && S->opts.block_threads <= 256 ? S->opts.block_threads : 256;
+  gg.grid = S->opts.grid_blocks;
+  gg.max_lanes = fair_lanes(gt, S->opts.nodes_per_lane);
+  if (!S->opts.block_threads)  // small lane caps get small workgroups
+    gg.block = static_cast<int>(std::min<int64_t>(
+        256, std::max<int64_t>(64, div_up(std::max<int64_t>(1, gg.max_lanes), 64) * 64)));
+  plan_rounds(gt, gg, int64_t(global_grid(gg)) * gg.block);
+  hipError_t e = hipMemcpyAsync(S->d_table, gt.data(), sizeof(GraphDesc) * gt.size(),
+                                hipMemcpyHostToDevice, L.stream);
+  if (e != hipSuccess) return hip_fail(e, "uploading the launch table");
+  const int rc = launch_global_epochs(L.stream, gg, 0, 1);
+  if (rc != LAYOUT_OK) return rc;
+  // JACOBI: a job whose epoch ends in this launch moves by its summed D
   if (S->mode_global == LAYOUT_JACOBI)
-    for (size_t q = 0; q < glob_jobs.size(); ++q)
-      if (glob_jobs[q]->chunk_pos + slice[q] >= glob_jobs[q]->n_chunks)
-        launch_jacobi_apply(S->stream, glob_jobs[q]->desc.Y, glob_jobs[q]->D, glob_jobs[q]->n);
-  e = hipStreamSynchronize(S->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(S->side);
-  if (e != hipSuccess) return hip_fail(e, "running a round");
-  for (size_t q = 0; q < glob_jobs.size(); ++q) {
-    Job* j = glob_jobs[q];
-    j->chunk_pos += slice[q];
+    for (size_t q = 0; q < jobs.size(); ++q)
+      if (jobs[q]->chunk_pos + L.slice[q] >= jobs[q]->n_chunks)
+        launch_jacobi_apply(L.stream, jobs[q]->desc.Y, jobs[q]->D, jobs[q]->n);
+  return LAYOUT_OK;
+}
+
+int start_class(layout_server_t* S, int c, const std::vector<Job*>& jobs) {
+  ClassLaunch& L = S->cls[c];
+  const int rc = c == kClassLds   ? start_lds(S, L, jobs)
+                 : c == kClassXcd ? start_xcd(S, L, jobs)
+                                  : start_wide(S, L, jobs);
+  if (rc != LAYOUT_OK) return rc;
+  const hipError_t e = hipEventRecord(L.done, L.stream);
+  if (e != hipSuccess) return hip_fail(e, "recording a launch");
+  for (Job* j : L.jobs) j->in_flight = true;
+  L.busy = true;
+  return LAYOUT_OK;
+}
+
+// Book-keeping once a class's launch has ended: epoch counters advance.
+void end_class(layout_server_t* S, ClassLaunch& L) {
+  for (size_t q = 0; q < L.jobs.size(); ++q) {
+    Job* j = L.jobs[q];
+    j->in_flight = false;
+    if (j->cls == kClassLds) {
+      j->t = j->epochs;
+      continue;
+    }
+    j->chunk_pos += L.slice[q];
     if (j->chunk_pos >= j->n_chunks) {
       j->chunk_pos = 0;
       j->t += 1;
     }
   }
-  for (Job* j : lds_jobs) j->t = j->epochs;
-  return LAYOUT_OK;
+  L.jobs.clear();
+  L.busy = false;
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->rounds += 1;
+}
+
+// Retires the jobs in no launch that are done (positions to host, device
+// memory freed) or cancelled.
+int retire_jobs(layout_server_t* S) {
+  std::vector<Job*> still;
+  int rc = LAYOUT_OK;
+  for (Job* j : S->active) {
+    if (j->in_flight || rc != LAYOUT_OK) {
+      still.push_back(j);
+      continue;
+    }
+    if (j->cancel.load()) {
+      finish_job(S, j, kCancelled, "cancelled");
+      continue;
+    }
+    if (j->t < j->epochs && j->nnz > 0) {
+      still.push_back(j);
+      continue;
+    }
+    j->result.resize(size_t(j->n) * 2);
+    hipError_t e = hipSuccess;
+    if (j->n > 0) {
+      e = hipMemcpyAsync(j->result.data(), j->desc.Y, sizeof(float2) * size_t(j->n),
+                         hipMemcpyDeviceToHost, S->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+    }
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "reading positions");
+      still.push_back(j);
+      continue;
+    }
+    finish_job(S, j, LAYOUT_OK, "");
+  }
+  S->active.swap(still);
+  return rc;
 }
 
 // Answers the pending draw requests of jobs whose device state is set up
@@ -491,17 +585,42 @@ void serve_draw_requests(layout_server_t* S) {
   if (!answered.empty()) S->cv_done.notify_all();
 }
 
+bool admissible(const layout_server_t* S) {  // under mu
+  return !S->queue.empty() && int64_t(S->active.size()) < int64_t(S->max_slots) &&
+         S->in_use + S->queue.front()->footprint <= S->budget;
+}
+
 void scheduler(layout_server_t* S) {
   (void)hipSetDevice(S->dev);
+  double t_last = now_s();
   for (;;) {
+    // launches that have ended, then the jobs that are done
+    int rc = LAYOUT_OK;
+    for (ClassLaunch& L : S->cls) {
+      if (!L.busy || rc != LAYOUT_OK) continue;
+      const hipError_t e = hipEventQuery(L.done);
+      if (e == hipErrorNotReady) continue;
+      if (e != hipSuccess) {
+        rc = hip_fail(e, "running a launch");
+        continue;
+      }
+      end_class(S, L);
+    }
+    if (rc == LAYOUT_OK) rc = retire_jobs(S);
+    // admission in arrival order while a slot is free and the job's footprint
+    // fits the budget
     std::vector<Job*> admit;
+    bool held = false, busy = false;
+    for (const ClassLaunch& L : S->cls) busy = busy || L.busy;
     {
-      std::unique_lock<std::mutex> lk(S->mu);
-      S->cv_work.wait(lk, [&] {
-        return S->stop || !S->queue.empty() || !S->draw_requests.empty() ||
-               (!S->active.empty() && !S->hold);
-      });
-      if (S->stop) break;
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (S->stop || rc != LAYOUT_OK) {
+        if (rc != LAYOUT_OK) {
+          S->dead = true;
+          S->dead_msg = g_last_error;
+        }
+        break;
+      }
       while (!S->queue.empty() &&
              int64_t(S->active.size() + admit.size()) < int64_t(S->max_slots)) {
         Job* j = S->queue.front();
@@ -511,15 +630,18 @@ void scheduler(layout_server_t* S) {
         j->state = LAYOUT_JOB_RUNNING;
         admit.push_back(j);
       }
+      held = S->hold;
+      const double now = now_s();
+      if (!S->active.empty() || busy) S->busy_seconds += now - t_last;
+      t_last = now;
     }
-    const double t0 = now_s();
     for (Job* j : admit) {
       if (j->cancel.load()) {
         finish_job(S, j, kCancelled, "cancelled");
         continue;
       }
       g_last_error.clear();
-      const int rc = setup_job(S, *j);
+      rc = setup_job(S, *j);
       if (rc != LAYOUT_OK) {
         finish_job(S, j, rc, g_last_error);
         if (rc == LAYOUT_E_DEVICE) {
@@ -533,54 +655,40 @@ void scheduler(layout_server_t* S) {
     }
     if (S->dead) break;
     serve_draw_requests(S);
-    bool held;
-    {
-      std::lock_guard<std::mutex> lk(S->mu);
-      held = S->hold;
-    }
-    if (S->active.empty() || held) {
-      // held: sleep until a submission, a request or the release (polling
-      // slowly, since a request may wait for a job queued behind full slots)
-      std::unique_lock<std::mutex> lk(S->mu);
-      if (!S->stop && S->hold) S->cv_work.wait_for(lk, std::chrono::milliseconds(50));
-      continue;
-    }
+    // every class whose last launch has ended starts its next one, whatever
+    // the other classes are doing
     g_last_error.clear();
-    int rc = run_round(S);
+    rc = LAYOUT_OK;
+    for (int c = 0; c < kClasses && !held && rc == LAYOUT_OK; ++c) {
+      if (S->cls[c].busy) continue;
+      const std::vector<Job*> jobs = ready_jobs(S, c);
+      if (!jobs.empty()) rc = start_class(S, c, jobs);
+    }
     if (rc != LAYOUT_OK) {
-      std::string msg = g_last_error;
-      for (Job* j : S->active) finish_job(S, j, rc, msg);
-      S->active.clear();
       std::lock_guard<std::mutex> lk(S->mu);
       S->dead = true;
-      S->dead_msg = msg;
+      S->dead_msg = g_last_error;
       break;
     }
-    // retire finished and cancelled jobs
-    std::vector<Job*> still;
-    for (Job* j : S->active) {
-      if (j->cancel.load()) {
-        finish_job(S, j, kCancelled, "cancelled");
-        continue;
-      }
-      if (j->t < j->epochs && j->nnz > 0) {
-        still.push_back(j);
-        continue;
-      }
-      j->result.resize(size_t(j->n) * 2);
-      hipError_t e = hipSuccess;
-      if (j->n > 0)
-        e = hipMemcpy(j->result.data(), j->desc.Y, sizeof(float2) * size_t(j->n),
-                      hipMemcpyDeviceToHost);
-      finish_job(S, j, e == hipSuccess ? LAYOUT_OK : hip_fail(e, "reading positions"),
-                 g_last_error);
+    busy = false;
+    for (const ClassLaunch& L : S->cls) busy = busy || L.busy;
+    if (busy) {
+      // a launch is running: look again shortly (its end, new arrivals)
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      continue;
     }
-    S->active.swap(still);
-    std::lock_guard<std::mutex> lk(S->mu);
-    S->rounds += 1;
-    S->busy_seconds += now_s() - t0;
+    // nothing running: sleep until a submission, a request, the release or
+    // the stop (polling slowly while held, since a request may wait for a
+    // job queued behind full slots)
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_work.wait_for(lk, std::chrono::milliseconds(50), [&] {
+      return S->stop || !S->draw_requests.empty() || admissible(S) ||
+             (!S->hold && !S->active.empty());
+    });
   }
-  // drain: fail whatever is left
+  // drain: let running launches end, then fail whatever is left
+  for (ClassLaunch& L : S->cls)
+    if (L.busy) (void)hipStreamSynchronize(L.stream);
   for (Job* j : S->active) finish_job(S, j, LAYOUT_E_DEVICE, S->dead ? S->dead_msg : "server stopped");
   S->active.clear();
   std::lock_guard<std::mutex> lk(S->mu);
@@ -659,7 +767,10 @@ int layout_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int64_t ro
     S->budget = hbm_budget_bytes;
   }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking);
+  for (ClassLaunch& L : S->cls) {
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
+  }
   if (e == hipSuccess) e = hipMalloc(&S->d_table, sizeof(GraphDesc) * size_t(max_slots));
   if (e == hipSuccess) e = hipMalloc(&S->d_table_lds, sizeof(GraphDesc) * size_t(max_slots));
   if (e == hipSuccess) e = hipMalloc(&S->d_ids, sizeof(int32_t) * size_t(max_slots));
@@ -725,7 +836,7 @@ int layout_server_submit_ex(layout_server_t* S, const int32_t* row_ptr, const in
     return fail(LAYOUT_E_OOM, "job needs %lld bytes, budget is %lld", (long long)fp,
                 (long long)S->budget);
   }
-  // the rounds of one server share k (one kernel instantiation per launch)
+  // the jobs of one server share k (one kernel instantiation per launch)
   for (auto& kv : S->jobs)
     if (kv.second->k != k && kv.second->state <= LAYOUT_JOB_RUNNING) {
       delete j;
@@ -763,7 +874,7 @@ int layout_server_cancel(layout_server_t* S, int64_t job_id) {
     return LAYOUT_OK;
   }
   if (j->state == LAYOUT_JOB_RUNNING) {
-    j->cancel.store(true);  // retired after the current round
+    j->cancel.store(true);  // retired once its launch in flight has ended
     return LAYOUT_OK;
   }
   return fail(LAYOUT_E_INVALID_ARG, "job %lld has already ended", (long long)job_id);
@@ -914,7 +1025,10 @@ int layout_server_destroy(layout_server_t* S) {
   if (S->d_xcd_ctr) (void)hipFree(S->d_xcd_ctr);
   if (S->d_err) (void)hipFree(S->d_err);
   if (S->stream) (void)hipStreamDestroy(S->stream);
-  if (S->side) (void)hipStreamDestroy(S->side);
+  for (ClassLaunch& L : S->cls) {
+    if (L.done) (void)hipEventDestroy(L.done);
+    if (L.stream) (void)hipStreamDestroy(L.stream);
+  }
   delete S;
   return LAYOUT_OK;
 }

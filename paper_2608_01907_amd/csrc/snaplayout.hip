@@ -949,9 +949,7 @@ int create_impl(const int32_t* row32, const int64_t* row64, const int32_t* col_i
     // enough chunks to keep every lane busy, each as long as possible
     const int64_t per_lane = std::max<int64_t>(1, L->nnz / (4 * L->block));
     L->bundle = o.bundle_edges ? o.bundle_edges : static_cast<int32_t>(std::min<int64_t>(16, per_lane));
-    // one workgroup: a lane may own a whole long row without stalling others
-    L->hub = o.hub_split_edges ? o.hub_split_edges
-                               : static_cast<int32_t>(std::max<int64_t>(1, L->nnz));
+    L->hub = o.hub_split_edges ? o.hub_split_edges : kLdsHub;
   } else {
     // a whole workgroup works on the graph, so small graphs get small
     // workgroups: n / nodes_per_lane lanes rounded up to whole wavefronts
