@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -789,6 +790,38 @@ int read_energy(layout_t* L, double* out) {
   return LAYOUT_OK;
 }
 
+// 3D positions are 16-byte (x, y, z, w) on the device and rows of 3 floats
+// in the caller's host arrays.  A strided copy between device and pageable
+// host memory with 12-byte rows moves one row at a time (minutes for
+// millions of nodes), so host transfers move whole 16-byte positions
+// through a host buffer of n float4 and repack there.
+int read_positions3(hipStream_t s, const float2* d_Y, int32_t n, float* host_out) {
+  std::unique_ptr<float4[]> tmp(new (std::nothrow) float4[size_t(n)]);
+  if (!tmp) return fail(LAYOUT_E_OOM, "host buffer for %d positions", n);
+  hipError_t e = hipMemcpyAsync(tmp.get(), d_Y, sizeof(float4) * size_t(n),
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "reading positions");
+  for (size_t i = 0; i < size_t(n); ++i) {
+    host_out[3 * i] = tmp[i].x;
+    host_out[3 * i + 1] = tmp[i].y;
+    host_out[3 * i + 2] = tmp[i].z;
+  }
+  return LAYOUT_OK;
+}
+
+int write_positions3(hipStream_t s, const float* host_in, int32_t n, float2* d_Y) {
+  std::unique_ptr<float4[]> tmp(new (std::nothrow) float4[size_t(n)]);
+  if (!tmp) return fail(LAYOUT_E_OOM, "host buffer for %d positions", n);
+  for (size_t i = 0; i < size_t(n); ++i)
+    tmp[i] = make_float4(host_in[3 * i], host_in[3 * i + 1], host_in[3 * i + 2], 0.0f);
+  hipError_t e = hipMemcpyAsync(d_Y, tmp.get(), sizeof(float4) * size_t(n),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "writing positions");
+  return LAYOUT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1032,8 +1065,10 @@ int create_impl(const int32_t* row32, const int64_t* row64, const int32_t* col_i
 
   // initial positions
   if (n > 0) {
-    if (o.init_pos && dim == 3) {
-      // n x 3 rows into 16-byte positions (w = 0)
+    if (o.init_pos && dim == 3 && !inputs_on_device) {
+      // n x 3 host rows into 16-byte positions (w = 0)
+      if ((rc = write_positions3(L->stream, o.init_pos, n, d_Y)) != LAYOUT_OK) return bail(rc);
+    } else if (o.init_pos && dim == 3) {
       e = hipMemsetAsync(d_Y, 0, size_t(pos_bytes) * size_t(n), L->stream);
       if (e == hipSuccess)
         e = hipMemcpy2DAsync(d_Y, 16, o.init_pos, 12, 12, size_t(n), kind, L->stream);
@@ -1176,11 +1211,9 @@ int layout_get_positions(const layout_t* L, float* host_out) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (!host_out) return fail(LAYOUT_E_INVALID_ARG, "host_out is NULL");
   if (L->n == 0) return LAYOUT_OK;
-  hipError_t e = L->dim == 3
-                     ? hipMemcpy2DAsync(host_out, 12, L->host_desc.Y, 16, 12, size_t(L->n),
-                                        hipMemcpyDeviceToHost, L->stream)
-                     : hipMemcpyAsync(host_out, L->host_desc.Y, sizeof(float2) * size_t(L->n),
-                                      hipMemcpyDeviceToHost, L->stream);
+  if (L->dim == 3) return read_positions3(L->stream, L->host_desc.Y, L->n, host_out);
+  hipError_t e = hipMemcpyAsync(host_out, L->host_desc.Y, sizeof(float2) * size_t(L->n),
+                                hipMemcpyDeviceToHost, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   if (e != hipSuccess) return hip_fail(e, "reading positions");
   return LAYOUT_OK;
@@ -1213,11 +1246,9 @@ int layout_set_positions(layout_t* L, const float* host_in) {
   if (!check_handle(L)) return LAYOUT_E_INVALID_ARG;
   if (!host_in) return fail(LAYOUT_E_INVALID_ARG, "host_in is NULL");
   if (L->n == 0) return LAYOUT_OK;
-  hipError_t e = L->dim == 3
-                     ? hipMemcpy2DAsync(L->host_desc.Y, 16, host_in, 12, 12, size_t(L->n),
-                                        hipMemcpyHostToDevice, L->stream)
-                     : hipMemcpyAsync(L->host_desc.Y, host_in, sizeof(float2) * size_t(L->n),
-                                      hipMemcpyHostToDevice, L->stream);
+  if (L->dim == 3) return write_positions3(L->stream, host_in, L->n, L->host_desc.Y);
+  hipError_t e = hipMemcpyAsync(L->host_desc.Y, host_in, sizeof(float2) * size_t(L->n),
+                                hipMemcpyHostToDevice, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   if (e != hipSuccess) return hip_fail(e, "writing positions");
   return LAYOUT_OK;

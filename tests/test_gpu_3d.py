@@ -160,3 +160,39 @@ def test_readout_set_positions_and_refusals(d1):
     with pytest.raises(SL.LayoutError) as ei:
         _layout(big, engine=SL.LAYOUT_ENGINE_LDS)
     assert ei.value.code == SL.LAYOUT_E_UNSUPPORTED
+
+
+def test_host_transfers_3d_at_scale():
+    """3D positions are 16 bytes on the device and rows of 3 floats on the
+    host: caller init from host and from device, readout and set_positions
+    are exact at 1M nodes, and each host transfer takes well under a second
+    (a strided copy with 12-byte rows between device and pageable memory
+    would move one row at a time and take minutes)."""
+    import time
+    import torch
+
+    n = 1_000_000
+    rp, col = S.csr_from_pairs(np.arange(n), (np.arange(n) + 1) % n, n)
+    rng = np.random.default_rng(4)
+    Y0 = rng.standard_normal((n, 3)).astype(np.float32)
+    t0 = time.perf_counter()
+    with SL.Layout(rp, col, n, k=5, epochs=3, seed=2, dim=3, init_pos=Y0) as L:
+        t_create = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        got = L.positions()
+        t_read = time.perf_counter() - t0
+        assert np.array_equal(got, Y0)
+        Z = rng.standard_normal((n, 3)).astype(np.float32)
+        t0 = time.perf_counter()
+        L.set_positions(Z)
+        t_write = time.perf_counter() - t0
+        assert np.array_equal(L.positions(), Z)
+        L.run(1)
+        assert np.all(np.isfinite(L.positions()))
+    print(f"3D host transfers at n = {n}: create {t_create:.3f} s, readout {t_read:.3f} s, "
+          f"set {t_write:.3f} s", flush=True)
+    assert t_read < 2.0 and t_write < 2.0 and t_create < 5.0
+    dev = torch.device("cuda:0")
+    with SL.Layout(torch.from_numpy(rp).to(dev), torch.from_numpy(col).to(dev), n, k=5, epochs=3,
+                   seed=2, dim=3, init_pos=torch.from_numpy(Y0).to(dev)) as L:
+        assert np.array_equal(L.positions(), Y0)
