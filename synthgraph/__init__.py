@@ -287,6 +287,17 @@ def lj_like(seed: int = 0) -> Graph:
     return g
 
 
+def cl_350k(seed: int = 21) -> Graph:
+    """350,000 nodes, 2,800,000 edges, tau = 2.2, 270 communities, 90%
+    intra: a graph whose positions (2.8 MB) fit one XCD's L2 with more than
+    one XCD's worth of lanes at n / 32 (the served pool's recipe at that
+    size)."""
+    g = chung_lu_communities(350_000, 2_800_000, tau=2.2, dmax=2400.0, n_comm=270, intra=0.9,
+                             seed=seed)
+    g.name = "cl-350k"
+    return g
+
+
 def cached(name: str, maker, cache_dir: str | None = None) -> Graph:
     """Generate once and keep an .npz copy (generation is never timed)."""
     cache_dir = cache_dir or os.environ.get("SNAP_GRAPH_CACHE", "/tmp/snap_graphs")
