@@ -609,7 +609,7 @@ def main():
     ap.add_argument("--pool", type=int, default=48)
     ap.add_argument("--jobs", type=int, default=200)
     ap.add_argument("--rho", type=float, nargs="+", default=[0.5, 0.8])
-    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--slots", type=int, default=128)
     ap.add_argument("--budget", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
