@@ -30,8 +30,10 @@ inline int lds_lanes_for(int32_t n, int nodes_per_lane) {
 }
 // LDS engine: rows above this many edges are split into segments, as on the
 // other engines.  A wavefront runs its lanes' chunks in step, so one lane on
-// a whole hub row would hold its 63 neighbours idle for the row's length.
-constexpr int kLdsHub = kHubFactor * kDefaultBundle;
+// a whole hub row would hold its 63 neighbours idle for the row's length;
+// on one CU the engine is bound by issue, so segments of at most twice the
+// bundle keep the chunks of a wavefront close in length.
+constexpr int kLdsHub = 2 * kDefaultBundle;
 constexpr long long kLdsAutoMaxEdges = 400000;  // AUTO picks LDS below this many directed edges
 constexpr long long kXcdMaxPositionBytes = 3 << 20;  // XCD-local engine: positions within 3 MiB
                                                      // of the 4 MiB L2 of one XCD
