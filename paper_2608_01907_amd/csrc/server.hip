@@ -686,9 +686,9 @@ void scheduler(layout_server_t* S) {
              (!S->hold && !S->active.empty());
     });
   }
-  // drain: let running launches end, then fail whatever is left
-  for (ClassLaunch& L : S->cls)
-    if (L.busy) (void)hipStreamSynchronize(L.stream);
+  // drain: let every launch end (also those of a class whose start failed
+  // part way), then fail whatever is left
+  for (ClassLaunch& L : S->cls) (void)hipStreamSynchronize(L.stream);
   for (Job* j : S->active) finish_job(S, j, LAYOUT_E_DEVICE, S->dead ? S->dead_msg : "server stopped");
   S->active.clear();
   std::lock_guard<std::mutex> lk(S->mu);
