@@ -4,7 +4,9 @@ and in the mix (NP and SI of the single-graph path, mean over eight paired
 seeds within 0.01); every served job draws the oracle's negatives, whatever
 engine serves it; in the synchronous mode a served job's positions after T
 epochs are the oracle's T chained synchronous epochs within 1e-5 x diameter;
-admission respects the HBM budget; a malformed job fails alone."""
+admission respects the HBM budget; a malformed job fails alone; all-CU jobs
+that do not fit the device's lanes together take turns in arrival order while
+smaller jobs pass in their own class."""
 import threading
 import time
 
@@ -144,7 +146,7 @@ def test_server_concurrent_submitters(pool):
 
 
 def test_server_small_job_moves_and_stays_finite(pool):
-    """A job small enough for the LDS engine runs whole in one round."""
+    """A job small enough for the LDS engine runs whole in one launch."""
     g = pool[0]
     srv = SL.layout_server_create(0, 2, 0)
     try:
@@ -380,3 +382,29 @@ def test_server_draws_match_oracle_on_every_engine(pool, wide_graph, weighted):
             assert ei.value.code == SL.LAYOUT_E_INVALID_ARG
     finally:
         SL.layout_server_destroy(srv)
+
+
+def test_server_all_cu_jobs_take_turns_and_small_jobs_pass():
+    """Two jobs whose lane caps (n / 32 each) do not fit the device's lanes
+    together run one after the other in arrival order, so the first ends
+    well before the second; a small job submitted after both runs in its own
+    class and ends before the second.  Every result is finite."""
+    n = 1_100_000  # n / 32 = 34,375 lanes; two exceed 256 CUs x 256 lanes
+    rp, col = S.csr_from_pairs(np.arange(n), (np.arange(n) + 1) % n, n)
+    small = S.small_sbm(2500, 4, 12.0, seed=41)
+    srv = SL.layout_server_create(0, 16, 0)
+    try:
+        a = SL.layout_server_submit(srv, rp, col, n, 5, 400, 1)
+        b = SL.layout_server_submit(srv, rp, col, n, 5, 400, 2)
+        time.sleep(0.02)
+        c = SL.layout_server_submit(srv, small.row_ptr, small.col, small.n, 5, 30, 3)
+        lat = {}
+        for name, jid, nn in (("a", a, n), ("b", b, n), ("c", c, small.n)):
+            SL.layout_server_wait(srv, jid, 120.0)
+            Y, lat[name] = SL.layout_server_take(srv, jid, nn)
+            assert np.all(np.isfinite(Y)), name
+    finally:
+        SL.layout_server_destroy(srv)
+    print("latencies", {k: round(v, 3) for k, v in lat.items()}, flush=True)
+    assert lat["a"] < 0.75 * lat["b"], lat
+    assert lat["c"] < lat["b"], lat
