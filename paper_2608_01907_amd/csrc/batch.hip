@@ -118,7 +118,7 @@ int build_global_chunks(layout_batch_t* B) {
   std::vector<GraphDesc> table;
   for (int32_t g : B->global_ids)
     if (B->nnz[g] > 0) table.push_back(B->desc[g]);
-  B->gg.max_lanes = table.empty() ? 0 : fair_lanes(table, B->opts.nodes_per_lane);
+  B->gg.max_lanes = table.empty() ? 0 : lane_caps(table, B->opts.nodes_per_lane);
   // small lane caps get small workgroups (whole wavefronts), as on one graph
   if (!B->opts.block_threads)
     B->gg.block = static_cast<int>(
@@ -133,7 +133,10 @@ int upload_global_table(layout_batch_t* B, int grid) {
   for (int32_t g : B->global_ids)
     if (B->nnz[g] > 0) table.push_back(B->desc[g]);
   if (table.empty()) return LAYOUT_OK;
-  plan_rounds(table, B->gg, int64_t(grid) * B->gg.block);
+  plan_lanes(table, B->gg, int64_t(grid) * B->gg.block, B->opts.nodes_per_lane);
+  // every graph keeps at least one lane: a launch too small for that grows
+  if (B->gg.total_index > int64_t(grid) * B->gg.block)
+    B->gg.grid = static_cast<int>(div_up(B->gg.total_index, B->gg.block));
   hipError_t e = hipMemcpyAsync(B->d_table_global, table.data(), sizeof(GraphDesc) * table.size(),
                                 hipMemcpyHostToDevice, B->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(B->stream);

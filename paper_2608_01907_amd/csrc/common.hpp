@@ -152,8 +152,8 @@ struct GlobalGroup {
   const GraphDesc* d_table = nullptr;
   int G = 0;
   int64_t total_chunks = 0;  // chunks of all graphs
-  int64_t round_size = 0;    // G > 1: positions per round (sum of the slices)
-  int64_t total_index = 0;   // G > 1: rounds * round_size
+  int64_t round_size = 0;    // unused by the global engine (lanes, not rounds)
+  int64_t total_index = 0;   // G > 1: lanes handed out by plan_lanes
   int k = 5, mode = kStore;
   bool degree = false;
   int block = 256;
@@ -195,12 +195,18 @@ int plan_xcd_bins(const std::vector<GraphDesc>& graphs, int nodes_per_lane,
 int launch_xcd_group_epochs(hipStream_t stream, const XcdGroup& g, int32_t dt, int32_t count);
 void launch_fill_i32(hipStream_t stream, int32_t* p, int64_t n, int32_t v);
 int lds_bytes_for(int32_t n, int dim = 2);  // LDS of one graph's positions
-// Cuts the chunks of the graphs in table (host copy, n_chunks set) into
-// rounds for a launch of `lanes` lanes: sets each entry's slice/chunk_base and
-// the group's round_size/total_index/total_chunks.
-void plan_rounds(std::vector<GraphDesc>& table, GlobalGroup& g, int64_t lanes);
-// Lanes of a multi-graph launch such that every graph g, which receives lanes
-// in proportion to its chunk count, has at most n_g / nodes_per_lane of them.
+// Lanes of a multi-graph launch of the global engine (table: host copy,
+// n_chunks set): graph g gets the lanes [chunk_base, chunk_base + slice), its
+// cap n_g / nodes_per_lane (at least 1, at most its chunks) when the caps fit
+// `lanes`, else lanes in proportion to its chunks up to that cap.  Sets the
+// group's total_index (the lanes handed out, which a launch must cover) and
+// total_chunks.
+void plan_lanes(std::vector<GraphDesc>& table, GlobalGroup& g, int64_t lanes, int nodes_per_lane);
+// The sum of those caps (the lanes such a launch wants).
+int64_t lane_caps(const std::vector<GraphDesc>& table, int nodes_per_lane);
+// Lanes of a multi-graph XCD-local segment such that every graph g, which
+// receives lanes in proportion to its chunk count, has at most
+// n_g / nodes_per_lane of them.
 int64_t fair_lanes(const std::vector<GraphDesc>& table, int nodes_per_lane);
 int global_grid(const GlobalGroup& g);  // resolved grid size
 int launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t dt, int32_t count);
@@ -221,6 +227,12 @@ struct DeviceBuffers {
   size_t bytes() const { return total; }
   void free_all() {
     for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    total = 0;
+  }
+  // stream-ordered: for buffers from hipMallocAsync; waits for no other stream
+  void free_all_async(hipStream_t stream) {
+    for (void* p : ptrs) (void)hipFreeAsync(p, stream);
     ptrs.clear();
     total = 0;
   }

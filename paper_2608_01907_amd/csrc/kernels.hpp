@@ -496,7 +496,8 @@ __device__ __forceinline__ Pos<DIM>* pos_of(float2* p) {
   return reinterpret_cast<Pos<DIM>*>(p);
 }
 
-// Graph of a position inside a round (tables are short; binary search).
+// Entry of the table whose [chunk_base, ...) range holds c: a position inside
+// a round (XCD bins) or a lane (global engine); tables are short.
 __device__ __forceinline__ int find_graph(const GraphDesc* __restrict__ table, int G, int64_t c) {
   int lo = 0, hi = G - 1;
   while (lo < hi) {
@@ -510,46 +511,47 @@ __device__ __forceinline__ int find_graph(const GraphDesc* __restrict__ table, i
 }
 
 // ------------------------------------------------------------- epoch kernels
-// One epoch of every graph in the table; lanes stride over all chunks.
-// With several graphs the index space is cut into rounds of round_size
-// positions; a round holds a slice of every graph (in proportion to its
-// chunk count), so that the lanes in flight at any moment spread over all
-// graphs as they would over each graph alone (bounded per-node concurrency).
-// A single graph (G = 1) has a uniform position base, which its accesses use
-// through BufferMem when n * sizeof(position) < 2^32; 3D layouts always run
-// one graph per launch.
+// One epoch of every graph in the table.  Graph g owns the lanes
+// [chunk_base, chunk_base + slice) of the launch (slice: its lane cap, about
+// n / nodes_per_lane), and its lanes stride over its own chunks, so every
+// graph runs at the concurrency it has alone, whatever else shares the
+// launch (bounded per-node concurrency, Sec. 3.4).  lanes_used: the lanes
+// the table hands out, at most the launch's.  A single graph (G = 1) has a
+// uniform position base, which its accesses use through BufferMem when
+// n * sizeof(position) < 2^32; 3D layouts always run one graph per launch.
 template <int K, int MODE, bool DEGREE, class Mem = GlobalMem, int DIM = 2>
 static __global__ void __launch_bounds__(256)
-    epoch_global_kernel(const GraphDesc* __restrict__ table, int G, int64_t total_index,
-                        int64_t round_size, int32_t dt) {
+    epoch_global_kernel(const GraphDesc* __restrict__ table, int G, int64_t lanes_used,
+                        int32_t dt) {
   using P = Pos<DIM>;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t launch = static_cast<int64_t>(gridDim.x) * blockDim.x;
   const int64_t first = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (DIM == 3 || (G == 1 && int64_t(table[0].n) * int64_t(sizeof(P)) < (int64_t(1) << 32))) {
     const GraphDesc& g = table[0];
+    const int64_t lanes = g.slice > 0 && g.slice < launch ? g.slice : launch;
+    if (first >= lanes) return;
     const BufferMem<P> mem(pos_of<DIM>(g.Y), g.n);
     const int32_t t = g.t0 + dt;
     const float eta = eta_of(g, t);
-    for (int64_t c = first; c < g.n_chunks; c += stride)
+    for (int64_t c = first; c < g.n_chunks; c += lanes)
       process_chunk<K, MODE, DEGREE>(mem, g, pos_of<DIM>(g.Y), pos_of<DIM>(g.D),
                                      g.chunk_offset + c, t, eta);
     return;
   }
   if constexpr (DIM == 2) {
-    for (int64_t c = first; c < total_index; c += stride) {
-      int64_t r = 0, w = c;
-      if (G > 1) {
-        r = c / round_size;
-        w = c - r * round_size;
-      }
-      const int gi = G == 1 ? 0 : find_graph(table, G, w);
-      const GraphDesc& g = table[gi];
-      const int64_t local = r * g.slice + (w - g.chunk_base);
-      if (local >= g.n_chunks) continue;  // past this graph's last chunk
-      const int32_t t = g.t0 + dt;
-      process_chunk<K, MODE, DEGREE>(Mem{}, g, g.Y, g.D, g.chunk_offset + local, t,
-                                     eta_of(g, t));
-    }
+    if (first >= lanes_used) return;
+    const int gi = G == 1 ? 0 : find_graph(table, G, first);
+    const GraphDesc& g = table[gi];
+    // one graph: at most the launch's lanes (the host sizes several graphs'
+    // lanes to fit the launch)
+    const int64_t step =
+        G == 1 ? (g.slice > 0 && g.slice < launch ? g.slice : launch) : (g.slice > 0 ? g.slice : 1);
+    const int64_t lane = first - g.chunk_base;
+    if (lane >= step) return;  // beyond the last graph's lanes
+    const int32_t t = g.t0 + dt;
+    const float eta = eta_of(g, t);
+    for (int64_t c = lane; c < g.n_chunks; c += step)
+      process_chunk<K, MODE, DEGREE>(Mem{}, g, g.Y, g.D, g.chunk_offset + c, t, eta);
   }
 }
 

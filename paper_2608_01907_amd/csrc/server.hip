@@ -185,9 +185,11 @@ void plan_job(const layout_server_t* S, Job& j) {
   j.footprint = footprint_of(S, j, j.bundle, j.hub);
 }
 
-int jalloc(Job& j, void** p, size_t bytes, const char* what) {
+int jalloc(layout_server_t* S, Job& j, void** p, size_t bytes, const char* what) {
   if (bytes == 0) bytes = 8;
-  hipError_t e = hipMalloc(p, bytes);
+  // stream-ordered: a plain hipMalloc/hipFree pair would make every
+  // admission and retirement wait for all classes' launches to end
+  hipError_t e = hipMallocAsync(p, bytes, S->stream);
   if (e != hipSuccess) return hip_fail(e, what);
   j.buf.add(*p, bytes);
   return LAYOUT_OK;
@@ -201,11 +203,11 @@ int setup_job(layout_server_t* S, Job& j) {
   uint32_t *thr = nullptr, *alias = nullptr;
   j.chunk_cap = j.nnz > 0 ? chunk_bound(j.nnz, j.bundle, j.hub) : 0;
   int rc;
-  if ((rc = jalloc(j, reinterpret_cast<void**>(&row), 8 * (size_t(j.n) + 1), "row_ptr")) ||
-      (rc = jalloc(j, reinterpret_cast<void**>(&col), 4 * size_t(j.nnz), "col")) ||
-      (rc = jalloc(j, reinterpret_cast<void**>(&Y), 8 * size_t(j.n), "positions")) ||
-      (rc = jalloc(j, reinterpret_cast<void**>(&cb), 8 * size_t(j.chunk_cap + 1), "chunk begin")) ||
-      (rc = jalloc(j, reinterpret_cast<void**>(&cs), 4 * size_t(j.chunk_cap), "chunk src")))
+  if ((rc = jalloc(S, j, reinterpret_cast<void**>(&row), 8 * (size_t(j.n) + 1), "row_ptr")) ||
+      (rc = jalloc(S, j, reinterpret_cast<void**>(&col), 4 * size_t(j.nnz), "col")) ||
+      (rc = jalloc(S, j, reinterpret_cast<void**>(&Y), 8 * size_t(j.n), "positions")) ||
+      (rc = jalloc(S, j, reinterpret_cast<void**>(&cb), 8 * size_t(j.chunk_cap + 1), "chunk begin")) ||
+      (rc = jalloc(S, j, reinterpret_cast<void**>(&cs), 4 * size_t(j.chunk_cap), "chunk src")))
     return rc;
   if ((rc = upload_row_ptr(S->stream, j.row.data(), j.n, false, row)) != LAYOUT_OK) return rc;
   hipError_t e = hipSuccess;
@@ -217,8 +219,8 @@ int setup_job(layout_server_t* S, Job& j) {
                                            &j.n_chunks)) != LAYOUT_OK)
     return rc;
   if (S->opts.neg_weights != LAYOUT_NEG_UNIFORM && j.nnz > 0) {
-    if ((rc = jalloc(j, reinterpret_cast<void**>(&thr), 4 * size_t(j.n), "alias thr")) ||
-        (rc = jalloc(j, reinterpret_cast<void**>(&alias), 4 * size_t(j.n), "alias")))
+    if ((rc = jalloc(S, j, reinterpret_cast<void**>(&thr), 4 * size_t(j.n), "alias thr")) ||
+        (rc = jalloc(S, j, reinterpret_cast<void**>(&alias), 4 * size_t(j.n), "alias")))
       return rc;
     rc = S->opts.neg_weights == LAYOUT_NEG_CUSTOM
              ? upload_weights_and_build_alias(S->stream, row, j.weights.data(), j.n, false, thr,
@@ -227,7 +229,7 @@ int setup_job(layout_server_t* S, Job& j) {
     if (rc != LAYOUT_OK) return rc;
   }
   if (S->mode_global == LAYOUT_JACOBI) {
-    if ((rc = jalloc(j, reinterpret_cast<void**>(&j.D), 8 * size_t(j.n), "jacobi delta")))
+    if ((rc = jalloc(S, j, reinterpret_cast<void**>(&j.D), 8 * size_t(j.n), "jacobi delta")))
       return rc;
     launch_fill_zero(S->stream, j.D, j.n);
   }
@@ -276,7 +278,7 @@ int setup_job(layout_server_t* S, Job& j) {
 }
 
 void finish_job(layout_server_t* S, Job* j, int code, const std::string& msg) {
-  j->buf.free_all();
+  j->buf.free_all_async(S->stream);
   std::lock_guard<std::mutex> lk(S->mu);
   S->in_use -= j->footprint;
   j->t_done = now_s();
@@ -442,11 +444,13 @@ int start_wide(layout_server_t* S, ClassLaunch& L, const std::vector<Job*>& read
   gg.degree = S->opts.neg_weights != LAYOUT_NEG_UNIFORM;
   gg.block = S->opts.block_threads && S->opts.block_threads <= 256 ? S->opts.block_threads : 256;
   gg.grid = S->opts.grid_blocks;
-  gg.max_lanes = fair_lanes(gt, S->opts.nodes_per_lane);
+  gg.max_lanes = lane_caps(gt, S->opts.nodes_per_lane);
   if (!S->opts.block_threads)  // small lane caps get small workgroups
     gg.block = static_cast<int>(std::min<int64_t>(
         256, std::max<int64_t>(64, div_up(std::max<int64_t>(1, gg.max_lanes), 64) * 64)));
-  plan_rounds(gt, gg, int64_t(global_grid(gg)) * gg.block);
+  const int grid = global_grid(gg);
+  plan_lanes(gt, gg, int64_t(grid) * gg.block, S->opts.nodes_per_lane);
+  gg.grid = static_cast<int>(std::max<int64_t>(grid, div_up(gg.total_index, gg.block)));
   hipError_t e = hipMemcpyAsync(S->d_table, gt.data(), sizeof(GraphDesc) * gt.size(),
                                 hipMemcpyHostToDevice, L.stream);
   if (e != hipSuccess) return hip_fail(e, "uploading the launch table");
@@ -560,7 +564,8 @@ void serve_draw_requests(layout_server_t* S) {
     int32_t* d_out = nullptr;
     int rc = LAYOUT_OK;
     if (count > 0) {
-      hipError_t e = hipMalloc(&d_out, sizeof(int32_t) * count);
+      hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&d_out), sizeof(int32_t) * count,
+                                    S->stream);
       if (e != hipSuccess) rc = hip_fail(e, "debug draws buffer");
       if (rc == LAYOUT_OK)
         rc = launch_dump_draws(S->stream, j->k, S->opts.neg_weights != LAYOUT_NEG_UNIFORM,
@@ -571,7 +576,7 @@ void serve_draw_requests(layout_server_t* S) {
         if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
         if (e != hipSuccess) rc = hip_fail(e, "reading debug draws");
       }
-      if (d_out) (void)hipFree(d_out);
+      if (d_out) (void)hipFreeAsync(d_out, S->stream);
     }
     r->rc = rc;
     r->msg = g_last_error;
@@ -1012,10 +1017,11 @@ int layout_server_destroy(layout_server_t* S) {
   S->cv_work.notify_all();
   if (S->thr.joinable()) S->thr.join();
   for (auto& kv : S->jobs) {
-    kv.second->buf.free_all();
+    kv.second->buf.free_all_async(S->stream);
     delete kv.second;
   }
   S->jobs.clear();
+  if (S->stream) (void)hipStreamSynchronize(S->stream);
   if (S->d_table) (void)hipFree(S->d_table);
   if (S->d_table_lds) (void)hipFree(S->d_table_lds);
   if (S->d_ids) (void)hipFree(S->d_ids);

@@ -242,7 +242,9 @@ int snap::build_chunk_table(hipStream_t stream, const int64_t* d_row, int32_t n,
   void* tmp = nullptr;
   const size_t b_scan = sizeof(int32_t) * size_t(tiles + 1);
   const size_t bytes = b_scan + size_t(n) + 64;
-  hipError_t e = hipMalloc(&tmp, bytes);
+  // stream-ordered scratch: allocating and freeing it waits for no other
+  // stream (a plain free waits for the whole device to go idle)
+  hipError_t e = hipMallocAsync(&tmp, bytes, stream);
   if (e != hipSuccess) return hip_fail(e, "chunk scratch");
   auto* scan = static_cast<int32_t*>(tmp);
   auto* flags = reinterpret_cast<uint8_t*>(scan + tiles + 1);
@@ -264,7 +266,7 @@ int snap::build_chunk_table(hipStream_t stream, const int64_t* d_row, int32_t n,
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     *n_chunks = count;
   }
-  (void)hipFree(tmp);
+  (void)hipFreeAsync(tmp, stream);
   if (e != hipSuccess) return hip_fail(e, "building the chunk table");
   return LAYOUT_OK;
 }
@@ -283,7 +285,7 @@ int snap::build_alias_table(hipStream_t stream, const int64_t* d_row, const uint
   const size_t b_items = sizeof(int32_t) * size_t(n);
   const size_t b_inc = sizeof(int64_t) * size_t(n);
   const size_t bytes = b_sums + 2 * b_items + 2 * b_inc + 64;
-  hipError_t e = hipMalloc(&tmp, bytes);
+  hipError_t e = hipMallocAsync(&tmp, bytes, stream);
   if (e != hipSuccess) return hip_fail(e, "alias scratch");
   char* p = static_cast<char*>(tmp);
   auto* sums = reinterpret_cast<AliasScanItem*>(p);
@@ -300,7 +302,7 @@ int snap::build_alias_table(hipStream_t stream, const int64_t* d_row, const uint
                      d_alias);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  (void)hipFree(tmp);
+  (void)hipFreeAsync(tmp, stream);
   if (e != hipSuccess) return hip_fail(e, "building the alias table");
   return LAYOUT_OK;
 }
@@ -323,7 +325,7 @@ int snap::upload_row_ptr(hipStream_t stream, const int32_t* row_ptr, int32_t n, 
     if (e == hipSuccess) e = hipStreamSynchronize(stream);  // h is read by the copy
   } else {
     int32_t* tmp = nullptr;
-    e = hipMalloc(&tmp, sizeof(int32_t) * count);
+    e = hipMallocAsync(reinterpret_cast<void**>(&tmp), sizeof(int32_t) * count, stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(tmp, row_ptr, sizeof(int32_t) * count, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess) {
@@ -331,7 +333,7 @@ int snap::upload_row_ptr(hipStream_t stream, const int32_t* row_ptr, int32_t n, 
                          tmp, d_row, int64_t(count));
       e = hipStreamSynchronize(stream);
     }
-    if (tmp) (void)hipFree(tmp);
+    if (tmp) (void)hipFreeAsync(tmp, stream);
   }
   if (e != hipSuccess) return hip_fail(e, "copying row_ptr");
   return LAYOUT_OK;
@@ -353,13 +355,13 @@ int snap::upload_weights_and_build_alias(hipStream_t stream, const int64_t* d_ro
     return fail(LAYOUT_E_INVALID_ARG, "negative weights sum to %lld (need 0 < W < 2^32)",
                 (long long)W);
   uint32_t* d_w = nullptr;
-  e = hipMalloc(&d_w, sizeof(uint32_t) * size_t(n));
+  e = hipMallocAsync(reinterpret_cast<void**>(&d_w), sizeof(uint32_t) * size_t(n), stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(d_w, w.data(), sizeof(uint32_t) * size_t(n), hipMemcpyHostToDevice, stream);
   int rc = LAYOUT_OK;
   if (e == hipSuccess) rc = build_alias_table(stream, d_row, d_w, n, W, d_thr, d_alias);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (d_w) (void)hipFree(d_w);
+  if (d_w) (void)hipFreeAsync(d_w, stream);
   if (e != hipSuccess) return hip_fail(e, "building the weighted alias table");
   return rc;
 }
@@ -389,20 +391,58 @@ int snap::global_grid(const GlobalGroup& g) {
   return static_cast<int>(std::min<int64_t>(want, int64_t(per_cu) * device_props().cus));
 }
 
-void snap::plan_rounds(std::vector<GraphDesc>& table, GlobalGroup& g, int64_t lanes) {
+int64_t snap::lane_caps(const std::vector<GraphDesc>& table, int nodes_per_lane) {
+  const int npl = nodes_per_lane > 0 ? nodes_per_lane : kNodesPerLane;
   int64_t total = 0;
-  for (const GraphDesc& d : table) total += d.n_chunks;
-  g.total_chunks = total;
-  // a pass of the grid covers about two rounds
-  const int64_t rounds = std::max<int64_t>(1, div_up(2 * total, std::max<int64_t>(1, lanes)));
-  int64_t base = 0;
-  for (GraphDesc& d : table) {
-    d.slice = div_up(d.n_chunks, rounds);
-    d.chunk_base = base;
-    base += d.slice;
+  for (const GraphDesc& d : table)
+    total += std::max<int64_t>(1, std::min<int64_t>(d.n / npl, d.n_chunks));
+  return total;
+}
+
+void snap::plan_lanes(std::vector<GraphDesc>& table, GlobalGroup& g, int64_t lanes,
+                      int nodes_per_lane) {
+  const int npl = nodes_per_lane > 0 ? nodes_per_lane : kNodesPerLane;
+  const int64_t G = static_cast<int64_t>(table.size());
+  std::vector<int64_t> cap(table.size());
+  int64_t chunks = 0, caps = 0;
+  for (size_t q = 0; q < table.size(); ++q) {
+    cap[q] = std::max<int64_t>(1, std::min<int64_t>(table[q].n / npl, table[q].n_chunks));
+    chunks += table[q].n_chunks;
+    caps += cap[q];
   }
-  g.round_size = std::max<int64_t>(1, base);
-  g.total_index = rounds * g.round_size;
+  // Every graph gets its cap when the caps fit the launch.  Otherwise the
+  // lanes go in proportion to the graphs' chunks, none beyond its cap
+  // (slice = min(cap, lambda * chunks), lambda found by bisection), so that
+  // the uncapped graphs end their epochs together and no lane idles while
+  // work is left; one lane per graph is kept aside for the rounding up.
+  std::vector<int64_t> slice(cap);
+  if (caps > lanes) {
+    const double target = double(std::max<int64_t>(0, lanes - G));
+    auto used = [&](double lam) {
+      double u = 0.0;
+      for (size_t q = 0; q < table.size(); ++q)
+        u += std::min(double(cap[q]), lam * double(table[q].n_chunks));
+      return u;
+    };
+    double lo = 0.0, hi = 1.0;
+    while (used(hi) < target && hi < 1e18) hi *= 2.0;
+    for (int it = 0; it < 80; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      (used(mid) <= target ? lo : hi) = mid;
+    }
+    for (size_t q = 0; q < table.size(); ++q)
+      slice[q] = std::max<int64_t>(
+          1, static_cast<int64_t>(std::min(double(cap[q]), lo * double(table[q].n_chunks))));
+  }
+  int64_t base = 0;
+  for (size_t q = 0; q < table.size(); ++q) {
+    table[q].chunk_base = base;
+    table[q].slice = slice[q];
+    base += slice[q];
+  }
+  g.total_chunks = chunks;
+  g.total_index = base;  // lanes handed out; a launch must cover them
+  g.round_size = 0;
 }
 
 int64_t snap::fair_lanes(const std::vector<GraphDesc>& table, int nodes_per_lane) {
@@ -529,11 +569,12 @@ int snap::launch_global_epochs(hipStream_t stream, const GlobalGroup& g, int32_t
         return with_dim(g.dim, [&](auto dmc) -> int {
           constexpr int DIM = decltype(dmc)::value;
           using P = Pos<DIM>;
+          // several graphs: the lanes their table hands out (plan_lanes);
+          // one graph: its table entry bounds its own lanes
+          const int64_t lanes_used = g.G > 1 ? g.total_index : int64_t(grid) * g.block;
           for (int32_t ep = 0; ep < count; ++ep) {
-            const int64_t index = g.G > 1 ? g.total_index : g.total_chunks;
             hipLaunchKernelGGL((epoch_global_kernel<K, MODE, DEG, GlobalMem, DIM>), dim3(grid),
-                               dim3(g.block), 0, stream, g.d_table, g.G, index, g.round_size,
-                               dt + ep);
+                               dim3(g.block), 0, stream, g.d_table, g.G, lanes_used, dt + ep);
             // JACOBI: apply after every epoch when the group owns one contiguous
             // Y/D (a caller that applies per graph itself passes no nodes)
             if constexpr (MODE == kJacobi) {
@@ -1121,8 +1162,12 @@ int create_impl(const int32_t* row32, const int64_t* row64, const int32_t* col_i
   g.thr = d_thr;
   g.alias = d_alias;
   g.hot = d_hot;
+  // the global engine's lanes for this graph: n / nodes_per_lane, or all of
+  // an explicit launch (grid_blocks)
   g.chunk_base = 0;
-  g.slice = L->n_chunks;
+  g.slice = o.grid_blocks > 0
+                ? std::max<int64_t>(1, L->n_chunks)
+                : std::max<int64_t>(1, n / (o.nodes_per_lane > 0 ? o.nodes_per_lane : kNodesPerLane));
   g.n_chunks = L->n_chunks;
   g.nnz = L->nnz;
   g.n = n;
