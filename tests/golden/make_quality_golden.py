@@ -39,8 +39,6 @@ PLAN = {
                                  (0, 1, 2, 3, 4), "uniform"),
     "orkut-like-259k-pmds-lockfree": ("orkut-like-259k", "orkut_like", 5, 30, "threaded",
                                       (0, 1, 2, 3, 4), "pmds"),
-    # positions within one XCD's L2 and more than 8k lanes at n / 32
-    "cl-350k": ("cl-350k", "cl_350k", 5, 30, "threaded", (0, 1, 2, 3, 4), "uniform"),
 }
 NP_SAMPLE, SI_SAMPLE, METRIC_SEED = 2000, 10000, 12345
 

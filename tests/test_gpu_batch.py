@@ -98,13 +98,14 @@ def test_batch_jacobi_matches_oracle(mix):
 
 @pytest.mark.parametrize("engine", [SL.LAYOUT_ENGINE_AUTO, SL.LAYOUT_ENGINE_GLOBAL])
 def test_batch_hogwild_quality_alone_and_in_mix(mix, engine):
-    """Lock-free runs are not bit-reproducible, so the same eight seeds run
+    """Lock-free runs are not bit-reproducible, so the same sixteen seeds run
     alone and in the mix and are compared pairwise (mean difference within
-    0.01).  AUTO puts the larger graphs on XCD bins; GLOBAL keeps every graph
-    in the all-CU multi-graph launch, and the graphs alone then run on the
-    all-CU engine as well."""
+    0.01; the SI of these graphs varies by about 0.01 from seed to seed).
+    AUTO puts the larger graphs on XCD bins; GLOBAL keeps every graph in the
+    all-CU multi-graph launch, where each owns its n/32 lanes, and the graphs
+    alone then run on the all-CU engine at n/32 working lanes as well."""
     T = 40
-    seeds = tuple(100 + 600 * q for q in range(8))
+    seeds = tuple(100 + 600 * q for q in range(16))
     inmix = {}
     for s0 in seeds:
         with SL.BatchLayout(_desc(mix, s0), k=5, epochs=T, engine=engine) as B:
@@ -120,10 +121,6 @@ def test_batch_hogwild_quality_alone_and_in_mix(mix, engine):
             continue
         assert all(np.all(np.isfinite(inmix[(q, s0)])) for s0 in seeds)
         if g.n < 500:
-            continue
-        if engine == SL.LAYOUT_ENGINE_GLOBAL and g.n < 64 * 32:
-            # alone, the all-CU engine runs at least one 64-lane wave, more than
-            # the n/32 lanes such a graph gets in the mix
             continue
         qa, qm = [], []
         for s0 in seeds:

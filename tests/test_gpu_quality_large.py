@@ -91,13 +91,3 @@ def test_quality_orkut_like_259k_from_pmds():
 def test_quality_lj_like_4m_from_pmds():
     _check("lj-like-4m-pmds", S.lj_like)
 
-
-def test_quality_cl_350k_on_the_xcd_engine():
-    """A graph whose positions fit one XCD's L2 with more than one XCD's
-    8,192 lanes at n / 32: the XCD-local engine runs it on one workgroup per
-    CU of the XCD.  Same bar against the oracle's lock-free scheme."""
-    g = S.cached("cl-350k", S.cl_350k)
-    with SL.Layout(g.row_ptr, g.col, g.n, k=5, epochs=1, seed=0) as L:
-        info = L.info()
-    assert info["engine"] == SL.LAYOUT_ENGINE_XCD, info
-    _check("cl-350k", S.cl_350k)
