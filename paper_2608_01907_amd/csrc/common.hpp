@@ -196,13 +196,14 @@ int launch_xcd_group_epochs(hipStream_t stream, const XcdGroup& g, int32_t dt, i
 void launch_fill_i32(hipStream_t stream, int32_t* p, int64_t n, int32_t v);
 int lds_bytes_for(int32_t n, int dim = 2);  // LDS of one graph's positions
 // Lanes of a multi-graph launch of the global engine (table: host copy,
-// n_chunks set): graph g gets the lanes [chunk_base, chunk_base + slice), its
-// cap n_g / nodes_per_lane (at least 1, at most its chunks) when the caps fit
-// `lanes`, else lanes in proportion to its chunks up to that cap.  Sets the
-// group's total_index (the lanes handed out, which a launch must cover) and
-// total_chunks.
+// n_chunks set): graph g gets the lanes [chunk_base, chunk_base + slice),
+// chunk_base on a wavefront boundary, slice its cap n_g / nodes_per_lane (at
+// least 1, at most its chunks) when the caps fit `lanes`, else lanes in
+// proportion to its chunks up to that cap.  Sets the group's total_index
+// (the lanes handed out, which a launch must cover) and total_chunks.
 void plan_lanes(std::vector<GraphDesc>& table, GlobalGroup& g, int64_t lanes, int nodes_per_lane);
-// The sum of those caps (the lanes such a launch wants).
+// The sum of those caps, each padded to whole wavefronts (the lanes such a
+// launch wants).
 int64_t lane_caps(const std::vector<GraphDesc>& table, int nodes_per_lane);
 // Lanes of a multi-graph XCD-local segment such that every graph g, which
 // receives lanes in proportion to its chunk count, has at most

@@ -395,7 +395,7 @@ int64_t snap::lane_caps(const std::vector<GraphDesc>& table, int nodes_per_lane)
   const int npl = nodes_per_lane > 0 ? nodes_per_lane : kNodesPerLane;
   int64_t total = 0;
   for (const GraphDesc& d : table)
-    total += std::max<int64_t>(1, std::min<int64_t>(d.n / npl, d.n_chunks));
+    total += div_up(std::max<int64_t>(1, std::min<int64_t>(d.n / npl, d.n_chunks)), 64) * 64;
   return total;
 }
 
@@ -404,20 +404,22 @@ void snap::plan_lanes(std::vector<GraphDesc>& table, GlobalGroup& g, int64_t lan
   const int npl = nodes_per_lane > 0 ? nodes_per_lane : kNodesPerLane;
   const int64_t G = static_cast<int64_t>(table.size());
   std::vector<int64_t> cap(table.size());
-  int64_t chunks = 0, caps = 0;
+  int64_t chunks = 0, padded = 0;
   for (size_t q = 0; q < table.size(); ++q) {
     cap[q] = std::max<int64_t>(1, std::min<int64_t>(table[q].n / npl, table[q].n_chunks));
     chunks += table[q].n_chunks;
-    caps += cap[q];
+    padded += div_up(cap[q], 64) * 64;
   }
-  // Every graph gets its cap when the caps fit the launch.  Otherwise the
-  // lanes go in proportion to the graphs' chunks, none beyond its cap
-  // (slice = min(cap, lambda * chunks), lambda found by bisection), so that
-  // the uncapped graphs end their epochs together and no lane idles while
-  // work is left; one lane per graph is kept aside for the rounding up.
+  // Each graph's lanes start on a wavefront boundary, so that no wavefront
+  // mixes two graphs (its lanes would run at the pace of the other graph's
+  // chunks).  Every graph gets its cap when the caps fit the launch.
+  // Otherwise the lanes go in proportion to the graphs' chunks, none beyond
+  // its cap (slice = min(cap, lambda * chunks), lambda found by bisection),
+  // so that the uncapped graphs end their epochs together and no lane idles
+  // while work is left; a wavefront per graph is kept aside for the padding.
   std::vector<int64_t> slice(cap);
-  if (caps > lanes) {
-    const double target = double(std::max<int64_t>(0, lanes - G));
+  if (padded > lanes) {
+    const double target = double(std::max<int64_t>(0, lanes - 64 * G));
     auto used = [&](double lam) {
       double u = 0.0;
       for (size_t q = 0; q < table.size(); ++q)
@@ -436,6 +438,7 @@ void snap::plan_lanes(std::vector<GraphDesc>& table, GlobalGroup& g, int64_t lan
   }
   int64_t base = 0;
   for (size_t q = 0; q < table.size(); ++q) {
+    base = div_up(base, 64) * 64;
     table[q].chunk_base = base;
     table[q].slice = slice[q];
     base += slice[q];
