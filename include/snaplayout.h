@@ -504,8 +504,8 @@ void layout_batch_destroy(layout_batch_t *B);
  * and keeps every admitted job's CSR, positions and chunk table resident on
  * the device.  Each class runs launches of its own, the next one as soon as
  * its last one has ended, independently of the other classes:
- *   - jobs whose positions fit one workgroup's LDS: all their remaining
- *     epochs, one workgroup each (LDS engine);
+ *   - jobs whose positions fit one workgroup's LDS: up to ten of their
+ *     remaining epochs per launch, one workgroup each (LDS engine);
  *   - jobs whose positions fit one XCD's L2 (engine AUTO or XCD,
  *     HOGWILD_STORE, automatic launch shape): a slice of each one's current
  *     epoch on XCD-local bins;

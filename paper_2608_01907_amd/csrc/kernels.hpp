@@ -650,7 +650,8 @@ static __global__ void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32
 }
 
 // Whole epochs [dt, dt + count) of one small graph per workgroup, positions in
-// LDS for the duration of the launch.
+// LDS for the duration of the launch; a graph whose last epoch comes sooner
+// stops there (graphs at different epochs share one launch).
 template <int K, int MODE, bool DEGREE, int DIM = 2>
 static __global__ void __launch_bounds__(1024) epoch_lds_kernel(const GraphDesc* __restrict__ table,
                                                          const int32_t* __restrict__ graph_ids,
@@ -667,7 +668,9 @@ static __global__ void __launch_bounds__(1024) epoch_lds_kernel(const GraphDesc*
   const int32_t lanes = g.lanes > 0 && g.lanes < static_cast<int32_t>(blockDim.x)
                             ? g.lanes
                             : static_cast<int32_t>(blockDim.x);
-  for (int32_t ep = 0; ep < count; ++ep) {
+  const int32_t left = g.T - (g.t0 + dt);
+  const int32_t epochs = count < left ? count : left;
+  for (int32_t ep = 0; ep < epochs; ++ep) {
     const int32_t t = g.t0 + dt + ep;
     const float eta = eta_of(g, t);
     if (static_cast<int32_t>(threadIdx.x) < lanes)

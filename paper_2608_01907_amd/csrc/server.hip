@@ -12,8 +12,8 @@
 //      device footprint fits the budget (device copy, validation, chunk
 //      table, alias table of weighted negatives, initial positions: the
 //      caller's, seeded uniform or Pivot MDS);
-//   3. starts the next launch of every class whose last one has ended: all
-//      remaining epochs of the LDS jobs, one workgroup each; a slice of the
+//   3. starts the next launch of every class whose last one has ended: up to
+//      ten epochs of every LDS job, one workgroup each; a slice of the
 //      current epoch of every XCD-class job on XCD-local bins; a slice of the
 //      current epoch of the oldest all-CU jobs that fit the device's lanes.
 // No class waits for another, so a long launch of one class holds up no job
@@ -55,6 +55,7 @@ double now_s() {
 constexpr int64_t kDefaultRoundEdges = 32ll << 20;
 constexpr int kCancelled = 1;  // finish_job code of a cancelled job (not an error)
 constexpr int64_t kMinSliceEdges = 1ll << 18;
+constexpr int32_t kLdsLaunchEpochs = 10;  // LDS class: epochs of a job per launch
 
 struct Job {
   int64_t id = 0;
@@ -309,7 +310,9 @@ std::vector<Job*> ready_jobs(layout_server_t* S, int c) {
   return v;
 }
 
-// LDS class: every job runs all its remaining epochs in one workgroup.
+// LDS class: every job runs up to kLdsLaunchEpochs of its remaining epochs in
+// one workgroup, so that a job arriving meanwhile waits for at most that many
+// epochs of the largest LDS job, not for all of them.
 int start_lds(layout_server_t* S, ClassLaunch& L, const std::vector<Job*>& jobs) {
   const int k = jobs.front()->k;
   L.table.clear();
@@ -341,23 +344,16 @@ int start_lds(layout_server_t* S, ClassLaunch& L, const std::vector<Job*>& jobs)
   lg.mode = S->mode_lds;
   lg.degree = S->opts.neg_weights != LAYOUT_NEG_UNIFORM;
   lg.block = block;
-  // one launch when the jobs share the epoch count, else one launch per job
-  std::vector<int32_t> counts;
-  for (Job* j : jobs) counts.push_back(j->epochs - j->t);
-  const bool uniform =
-      std::all_of(counts.begin(), counts.end(), [&](int32_t c) { return c == counts.front(); });
-  if (uniform) {
-    rc = launch_lds_epochs(L.stream, lg, 0, counts.front());
-  } else {
-    for (size_t q = 0; q < jobs.size() && rc == LAYOUT_OK; ++q) {
-      LdsGroup one = lg;
-      one.d_ids = S->d_ids + q;
-      one.blocks = 1;
-      rc = launch_lds_epochs(L.stream, one, 0, counts[q]);
-    }
+  // one launch for all: each workgroup stops at its own job's last epoch
+  int32_t count = 0;
+  L.slice.clear();
+  for (Job* j : jobs) {
+    const int32_t c = std::min<int32_t>(kLdsLaunchEpochs, j->epochs - j->t);
+    L.slice.push_back(c);
+    count = std::max(count, c);
   }
+  rc = launch_lds_epochs(L.stream, lg, 0, count);
   L.jobs = jobs;
-  L.slice.assign(jobs.size(), 0);
   return rc;
 }
 
@@ -483,7 +479,7 @@ void end_class(layout_server_t* S, ClassLaunch& L) {
     Job* j = L.jobs[q];
     j->in_flight = false;
     if (j->cls == kClassLds) {
-      j->t = j->epochs;
+      j->t += static_cast<int32_t>(L.slice[q]);  // epochs run in this launch
       continue;
     }
     j->chunk_pos += L.slice[q];
