@@ -96,6 +96,28 @@ def test_batch_jacobi_matches_oracle(mix):
         assert np.abs(got[q] - alone).max() <= tol, q
 
 
+@pytest.mark.parametrize("grid", [1, 2])
+def test_batch_jacobi_with_fewer_lanes_than_caps(mix, grid):
+    """A launch of `grid` workgroups has fewer lanes than the graphs' caps
+    (n/32 each, about 2,900 lanes here): the lanes are shared in proportion
+    to the graphs' chunks, and with one workgroup even a lane per graph on
+    wavefront boundaries exceeds it, so the launch grows.  Every chunk must
+    still run exactly once: each member's synchronous epochs against the
+    oracle's."""
+    T, eta0 = 2, 0.05
+    with SL.BatchLayout(_desc(mix), k=3, epochs=T, update_mode=SL.LAYOUT_JACOBI, eta0=eta0,
+                        grid_blocks=grid) as B:
+        B.run()
+        got = [B.positions(q) for q in range(len(mix))]
+    for q, g in enumerate(mix):
+        if g.n == 0:
+            continue
+        ref = _oracle_jacobi_chain(g, 3, T, 100 + q, eta0)
+        tol = 1e-5 * max(_diam(ref), 1e-6)
+        err = float(np.abs(got[q] - ref).max())
+        assert err <= tol, (grid, q, err, tol)
+
+
 @pytest.mark.parametrize("engine", [SL.LAYOUT_ENGINE_AUTO, SL.LAYOUT_ENGINE_GLOBAL])
 def test_batch_hogwild_quality_alone_and_in_mix(mix, engine):
     """Lock-free runs are not bit-reproducible, so the same sixteen seeds run
